@@ -1,0 +1,12 @@
+"""FP64 CPU oracle for the density-matrix solver -- TEST INFRASTRUCTURE ONLY.
+
+Plain, slow, obviously correct NumPy implementations of what the GPU path
+computes, each function citing the passage of the paper it follows.  Only the
+test-suite, the smoke check and the benchmark's CPU-baseline leg may import
+this package; the product path never does, and the oracle shares no code with
+the HIP implementation.
+
+Parity status per function is stated in ``oracle/sp2_oracle.py``.
+"""
+
+from .sp2_oracle import *  # noqa: F401,F403

@@ -1,0 +1,19 @@
+"""Seeded synthetic inputs for the density-matrix solver.
+
+This package only draws input matrices (Hamiltonians, perturbations and
+weights).  It holds none of the solver's arithmetic, so both the FP64 oracle
+and the GPU path can take their inputs from here without sharing any code
+with each other.
+"""
+
+from .hamiltonians import (  # noqa: F401
+    random_orthogonal_hamiltonian,
+    water_box_positions,
+    water_box_hamiltonian,
+    water_box_length,
+    symmetric_normal,
+    trajectory_perturbation,
+    trajectory_hamiltonian,
+    pad_matrix,
+    WATER_ONSITE,
+)
