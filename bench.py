@@ -1,0 +1,207 @@
+"""Benchmark: DNN-SP2 density-matrix solves/s at N = 6144 on one MI355X.
+
+One step = one full ``sp2_density_ex`` call on a device-resident FP32
+Hamiltonian: Gershgorin bounds, input layer, every SP2 layer (split 16-bit
+MFMA products with FP64 trace-driven branch/stop decisions on the device)
+and the FP32 McWeeny refinement, ending with P in a caller buffer.
+
+Workload: seeded tight-binding water box, 1024 molecules, N = 6144,
+n_occ = 4096, H in FP32 (synthetic stand-in for the paper's SCC-DFTB water).
+
+Prints ONE JSON line.  Also reported: effective TFLOPS (3 products of
+2 N^3 per split layer + 2 N^3 per refinement product), the error against the
+FP64 oracle from stored samples of the exact density matrix, plain FP32 SP2
+on the same GPU, the roofline of the layer kernel (HIP-event durations
+recorded around every layer launch during the timed steps) and the FP64
+oracle timed on the host cores.
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SP2 density-matrix solves/s + effective TFLOPS at N=6144; error vs FP64 oracle"
+PEAK_TFLOPS = {"bf16x3": 2500.0, "fp16x3": 2500.0, "bf16x1": 2500.0, "fp32": 157.3}
+PRODUCTS = {"bf16x3": 3, "fp16x3": 3, "bf16x1": 1, "fp32": 1}
+GOLDEN = os.path.join(ROOT, "tests", "golden", "water_m1024_seed0.npz")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="bf16x3", choices=list(PRODUCTS))
+    ap.add_argument("--refine", default="fp32", choices=["none", "fp32", "split"])
+    ap.add_argument("--no-fp32-compare", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-layers", type=int, default=4,
+                    help="FP64 oracle layers timed for the CPU baseline sample")
+    return ap.parse_args()
+
+
+def timed_solves(pk, H, n_occ, precision, refine, steps, warmup, time_layers):
+    import torch
+    opt = pk.make_options(precision, refine, time_layers=time_layers)
+    ws = pk.allocate_workspace(H.shape[0], opt, H.device)
+    P = torch.empty_like(H)
+    for _ in range(warmup):
+        pk.sp2_density_ex(H, n_occ, opt, P, ws)
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st, info, br = pk.sp2_density_ex(H, n_occ, opt, P, ws)
+        infos.append(info.as_dict())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return P, infos, (t1 - t0) / steps
+
+
+def sampled_error(P, gold):
+    """||P - P_ref||_F / sqrt(N) estimated from uniformly sampled entries of the
+    exact P_ref, plus the exact diagonal error."""
+    n = int(gold["n"])
+    p = P.detach()
+    pi = np.asarray(gold["pair_i"], dtype=np.int64)
+    pj = np.asarray(gold["pair_j"], dtype=np.int64)
+    import torch
+    got = p[torch.from_numpy(pi).to(p.device), torch.from_numpy(pj).to(p.device)]
+    d = got.double().cpu().numpy() - gold["pair_val"]
+    diag = torch.diagonal(p).double().cpu().numpy() - gold["diag"]
+    return {
+        "fro_over_sqrt_n_est": math.sqrt(n * float(np.mean(d * d))),
+        "max_abs_sampled": float(np.max(np.abs(d))),
+        "diag_rms": float(np.sqrt(np.mean(diag * diag))),
+        "samples": int(d.size),
+    }
+
+
+def device_checks(P, n_occ):
+    import torch
+    p = P.detach()
+    n = p.shape[0]
+    pp = p @ p
+    return {
+        "idempotency": float(torch.linalg.norm((pp - p).double()).item() / math.sqrt(n)),
+        "trace_err": float(abs(torch.trace(p.double()).item() - n_occ)),
+        "symmetric": bool(torch.equal(p, p.T)),
+    }
+
+
+def cpu_baseline(h32, n_occ, layers, n_iter_ref):
+    """The FP64 oracle as it stands on the host cores, on a bounded sample:
+    bounds + input layer + ``layers`` SP2 layers at full N, extrapolated to a
+    full solve of ``n_iter_ref`` layers."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()
+                       if d.get("user_api") == "blas"] or [os.cpu_count() or 1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    h = h32.astype(np.float64)
+    t0 = time.perf_counter()
+    oracle.sp2(h, n_occ, tol=0.0, max_iter=0)
+    t1 = time.perf_counter()
+    oracle.sp2(h, n_occ, tol=0.0, max_iter=layers)
+    t2 = time.perf_counter()
+    setup = t1 - t0
+    per_layer = max(0.0, (t2 - t1) - setup) / layers
+    t_solve = setup + n_iter_ref * per_layer
+    return {
+        "value": 1.0 / t_solve,
+        "unit": "solves/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": f"FP64 oracle sp2(): bounds + input layer + {layers} layers at N={h.shape[0]} "
+                  f"({t2 - t1:.1f} s), extrapolated to {n_iter_ref} layers",
+        "seconds_per_solve": t_solve,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver has no "
+              "multi-GPU path in this build.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2107_02737_amd as pk
+    from workloads import water_box_hamiltonian
+
+    gold = np.load(GOLDEN)
+    m, n_occ = int(gold["molecules"]), int(gold["n_occ"])
+    h32 = water_box_hamiltonian(m, seed=int(gold["seed"])).astype(np.float32)
+    n = h32.shape[0]
+    if abs(float(h32.astype(np.float64).sum()) - float(gold["h_sum"])) > 1e-6 * abs(float(gold["h_sum"])):
+        raise RuntimeError("water-box generator drifted from the stored golden values")
+    H = torch.from_numpy(h32).to("cuda")
+    pk.load_library()
+
+    P, infos, sec = timed_solves(pk, H, n_occ, args.precision, args.refine, args.steps,
+                                 args.warmup, True)
+    n_iter = infos[-1]["n_iter"]
+    prods = PRODUCTS[args.precision]
+    nref = 2 if args.refine != "none" else 0
+    eff_flop = (n_iter * prods + nref) * 2.0 * n ** 3
+    layer_ms = float(np.mean([d["layer_ms"] / max(1, d["n_iter"]) for d in infos]))
+    # algorithmic work of one layer launch: upper-triangle tiles only, i.e.
+    # prods * N^3 FMA = 2 * prods * N^3 / 2 flop
+    layer_flop = prods * float(n) ** 3
+    achieved = layer_flop / (layer_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+
+    err = sampled_error(P, gold)
+    err.update(device_checks(P, n_occ))
+
+    out = {
+        "metric": METRIC,
+        "value": 1.0 / sec,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"bf16x3": "bf16", "bf16x1": "bf16", "fp16x3": "fp16", "fp32": "f32"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"tight-binding water box, {m} molecules, N={n}, n_occ={n_occ}, "
+                               f"seed {int(gold['seed'])}, H fp32 on device",
+                   "n": n, "n_occ": n_occ, "precision": args.precision, "refine": args.refine,
+                   "parallelism": "single GPU"},
+        "n_iter": n_iter,
+        "effective_tflops": eff_flop / sec / 1e12,
+        "error_vs_oracle": err,
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": f"k_sym_split ({args.precision} layer product)"
+                               if args.precision != "fp32" else "k_sym_f32 (fp32 layer product)",
+                     "layer_ms": layer_ms,
+                     "refine_ms": float(np.mean([d["refine_ms"] for d in infos]))},
+    }
+    if not args.no_fp32_compare and args.precision != "fp32":
+        _, finfo, fsec = timed_solves(pk, H, n_occ, "fp32", args.refine, 3, 1, True)
+        f_layer_ms = float(np.mean([d["layer_ms"] / max(1, d["n_iter"]) for d in finfo]))
+        out["fp32_sp2"] = {"solves_per_s": 1.0 / fsec, "n_iter": finfo[-1]["n_iter"],
+                           "layer_ms": f_layer_ms,
+                           "layer_tflops": float(n) ** 3 / (f_layer_ms * 1e-3) / 1e12,
+                           "speedup_of_split": fsec / sec}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(h32, n_occ, args.cpu_layers, n_iter)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,178 @@
+/*
+ * sp2.h -- C ABI of the MI355X (gfx950) density-matrix solver.
+ *
+ * Computes the zero-temperature density matrix D = theta(mu I - H) of a
+ * symmetric Hamiltonian H in an orthogonal basis (Section II.C, Eq. 18 of
+ * Finkelstein et al., arXiv 2107.02737) with the recursive second-order
+ * spectral projection written as a deep network, DNN-SP2 (Section II.D,
+ * Eq. 19 and Fig. 1): S_0 maps the spectrum of H linearly onto [0, 1] in
+ * reverse order, and each layer is S_n = S_{n-1}^2 or 2 S_{n-1} - S_{n-1}^2.
+ * The matrix squares run on MFMA matrix cores, optionally in the dual 16-bit
+ * representation X = X0 + X1 of Eq. (20)-(22).
+ *
+ * Conventions shared by every entry point:
+ *   - Matrix pointers are DEVICE pointers (HIP device memory) owned by the
+ *     caller.  Matrices are square, FP32, row-major with leading dimension
+ *     `ld` (elements, ld >= n).  Because every matrix here is symmetric,
+ *     row- and column-major agree.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *     All device work is ordered on it.
+ *   - `workspace` is caller-owned device memory of at least
+ *     sp2_workspace_bytes(n, opt) bytes, 256-byte aligned.  The library
+ *     never allocates device matrix memory; it only allocates a few KB of
+ *     pinned host memory once per thread for status read-back.
+ *   - Functions never throw; they return an sp2_status.  On failure
+ *     sp2_last_error() gives a thread-local description.
+ *   - Calls that share a workspace must not overlap in time.
+ */
+#ifndef SP2_H
+#define SP2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SP2_OK = 0,
+  SP2_ERR_INVALID_ARG = 1,   /* bad size, pointer, option or n_occ outside [0, n] */
+  SP2_ERR_NONFINITE = 2,     /* H holds NaN or Inf (found by the bound pass) */
+  SP2_ERR_NOT_CONVERGED = 3, /* stop test not met within max_iter layers, or H = cI
+                                with 0 < n_occ < n (no gap); P holds the last iterate */
+  SP2_ERR_WORKSPACE = 4,     /* workspace missing, too small or misaligned */
+  SP2_ERR_DEVICE = 5,        /* a HIP runtime call failed */
+  SP2_ERR_TAPE = 6           /* derivative requested but the workspace holds no tape */
+} sp2_status;
+
+/* Arithmetic of the layer products S^2 (Section II.D, Eq. 20-22).  All modes
+ * accumulate in FP32; traces, bounds and branch decisions are FP64.
+ *   SP2_FP32   one FP32 MFMA product per layer.
+ *   SP2_BF16X1 one bfloat16 product (X0 X0 only; single pass).
+ *   SP2_BF16X3 X0 X0 + X0 X1 + X1 X0 with X0 = BF16[X], X1 = BF16[X - X0].
+ *   SP2_FP16X3 the same with IEEE half on 2^14 X (exact power-of-two scale
+ *              that keeps the residual X1 out of the half subnormal range). */
+typedef enum { SP2_FP32 = 0, SP2_BF16X1 = 1, SP2_BF16X3 = 2, SP2_FP16X3 = 3 } sp2_precision;
+
+/* Refinement after the last layer: the McWeeny purification 3 S^2 - 2 S^3
+ * (the refinement step that closes Section II.D).
+ *   SP2_REFINE_NONE  no refinement.
+ *   SP2_REFINE_FP32  both products in FP32 MFMA.
+ *   SP2_REFINE_SPLIT both products in the FP16X3 split representation. */
+typedef enum { SP2_REFINE_NONE = 0, SP2_REFINE_FP32 = 1, SP2_REFINE_SPLIT = 2 } sp2_refine;
+
+#define SP2_MAX_ITER 256
+#define SP2_FLAG_TIME_LAYERS 1
+
+typedef struct {
+  int32_t precision;        /* sp2_precision (default SP2_BF16X3) */
+  int32_t refine;           /* sp2_refine (default SP2_REFINE_FP32) */
+  int32_t max_iter;         /* layer cap, 1..SP2_MAX_ITER (default 100) */
+  int32_t stop_rule;        /* 0: stop when e_n < tol; 1 (default): also stop when
+                               e_n < stall_gate and e_n >= e_{n-2} (rounding floor) */
+  int32_t checkpoint_every; /* 0 (default): no tape.  k > 0: keep S_0 and every k-th
+                               iterate in the workspace for sp2_jvp / sp2_vjp */
+  int32_t flags;            /* bit SP2_FLAG_TIME_LAYERS: time every layer launch with HIP
+                               events on `stream` (fills sp2_info.layer_ms/refine_ms) */
+  double tol;               /* stop when e_n = |Tr S_n - ||S_n||_F^2| < tol (default 1e-5) */
+  double stall_gate;        /* default 1.0 */
+} sp2_options;
+
+typedef struct {
+  int32_t n_iter;      /* layers applied (refinement not counted) */
+  int32_t converged;   /* 1 if the stop test passed */
+  int32_t status;      /* sp2_status of the call */
+  int32_t reserved;
+  double eps_min;      /* Gershgorin lower bound of spectrum(H), FP64 */
+  double eps_max;      /* Gershgorin upper bound */
+  double trace;        /* Tr P of the returned P, FP64 sum of FP32 entries */
+  double idem_err;     /* |Tr P - ||P||_F^2| of the returned P */
+  double layer_ms;     /* with SP2_FLAG_TIME_LAYERS: summed event time of the n_iter applied
+                          layer launches (each from the previous launch's end to its own end) */
+  double refine_ms;    /* with SP2_FLAG_TIME_LAYERS: event time of the refinement */
+} sp2_info;
+
+/* Fills *opt with the defaults listed above. */
+void sp2_default_options(sp2_options* opt);
+
+/* Bytes of device workspace needed by sp2_density / sp2_density_ex /
+ * sp2_layer / sp2_jvp / sp2_vjp for matrices of order n with options opt
+ * (NULL = defaults).  Includes the derivative tape when
+ * opt->checkpoint_every > 0.  Returns 0 for invalid arguments. */
+size_t sp2_workspace_bytes(int64_t n, const sp2_options* opt);
+
+/* Density matrix P = theta(mu I - H) with the n_occ lowest states occupied
+ * (Eq. 17-19), default options and tolerance tol.  H and P: n x n, ld = n.
+ * On return (the call blocks until the solve is done):
+ *   *n_iter   layers applied;
+ *   branches  min(n_iter, branches_cap) bytes: 1 for S^2 (W_n = +I),
+ *             0 for 2S - S^2 (W_n = -I); may be NULL when branches_cap = 0.
+ * Special cases: n_occ = 0 gives P = 0 and n_occ = n gives P = I, with no
+ * layers.  Returns SP2_OK, or an error as listed in sp2_status. */
+sp2_status sp2_density(const float* H, int64_t n, int64_t n_occ, double tol, float* P,
+                       int32_t* n_iter, uint8_t* branches, int32_t branches_cap,
+                       void* workspace, size_t ws_bytes, void* stream);
+
+/* Full form of sp2_density: leading dimension ld for H and P, explicit
+ * options (NULL = defaults; opt->tol is used), and an info record (may be
+ * NULL).  With opt->checkpoint_every > 0 the workspace keeps the tape used
+ * by sp2_jvp / sp2_vjp until the next call on the same workspace. */
+sp2_status sp2_density_ex(const float* H, int64_t n, int64_t ld, int64_t n_occ,
+                          const sp2_options* opt, float* P, sp2_info* info,
+                          uint8_t* branches, int32_t branches_cap,
+                          void* workspace, size_t ws_bytes, void* stream);
+
+/* Forward derivative (density-matrix response, as needed for the XL-BOMD
+ * kernel of Section III): P1 = dP/dH [H1] of the network recorded by the
+ * last sp2_density_ex call on this workspace, with the spectral bounds and
+ * the branch signs held fixed.  dS_0 = -H1 / (eps_max - eps_min); each layer
+ * maps dS -> S dS + dS S (sign +) or 2 dS - (S dS + dS S) (sign -), using the
+ * recomputed forward iterates; the refinement contributes its own
+ * derivative.  The derivative products run in FP32 MFMA.  H1 (symmetric) and
+ * P1: n x n with leading dimension ld.  Returns SP2_ERR_TAPE when the
+ * forward call kept no tape. */
+sp2_status sp2_jvp(void* workspace, size_t ws_bytes, const float* H1, int64_t ld, float* P1,
+                   void* stream);
+
+/* Reverse derivative: the symmetric G with Tr(G H1) = Tr(W P1) for every
+ * symmetric H1, i.e. dTr(W P)/dH of the recorded network (bounds and
+ * branches fixed; W is symmetrised).  Replays the branch sequence backwards;
+ * each layer maps G -> S G + G S (sign +) or 2 G - (S G + G S) (sign -); the
+ * iterates S_n are recomputed segment by segment from the checkpoints.
+ * Products in FP32 MFMA.  W and G: n x n with leading dimension ld. */
+sp2_status sp2_vjp(void* workspace, size_t ws_bytes, const float* W, int64_t ld, float* G,
+                   void* stream);
+
+/* Gershgorin enclosure of the spectrum of H (the linear map of the input
+ * layer needs spectral bounds; Section II.D): eps_min = min_i(H_ii -
+ * sum_{j!=i}|H_ij|), eps_max = max_i(H_ii + sum_{j!=i}|H_ij|), FP64 sums of
+ * the FP32 entries.  Outputs are host doubles; blocks until done.  Returns
+ * SP2_ERR_NONFINITE when H holds NaN/Inf. */
+sp2_status sp2_bounds(const float* H, int64_t n, int64_t ld, double* eps_min, double* eps_max,
+                      void* workspace, size_t ws_bytes, void* stream);
+
+/* Dual representation of Eq. (20)-(21): hi = R[X], lo = R[X - hi] with
+ * round-to-nearest-even R into bfloat16 (precision SP2_BF16X3/SP2_BF16X1)
+ * or IEEE half of 2^14 X (SP2_FP16X3).  X: n x n FP32 with leading
+ * dimension ld; hi, lo: n x n raw 16-bit patterns, leading dimension n.
+ * Asynchronous on stream. */
+sp2_status sp2_split(const float* X, int64_t n, int64_t ld, int32_t precision,
+                     uint16_t* hi, uint16_t* lo, void* stream);
+
+/* One expansion layer (Eq. 19, Fig. 1): Y = X^2 (sign = +1) or
+ * Y = 2X - X^2 (sign = -1) for a symmetric X, computed by the same
+ * symmetric-output MFMA kernels (and arithmetic `precision`) as the solver's
+ * layers.  X, Y: n x n, leading dimension ld, distinct buffers.  Blocks
+ * until done. */
+sp2_status sp2_layer(const float* X, int64_t n, int64_t ld, int32_t precision, int32_t sign,
+                     float* Y, void* workspace, size_t ws_bytes, void* stream);
+
+/* Thread-local text describing the last error of this thread ("" if none). */
+const char* sp2_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SP2_H */

@@ -10,3 +10,4 @@ Parity status per function is stated in ``oracle/sp2_oracle.py``.
 """
 
 from .sp2_oracle import *  # noqa: F401,F403
+from . import precision_emulation  # noqa: F401,E402

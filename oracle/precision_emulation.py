@@ -1,0 +1,66 @@
+"""Rounding-level emulation of the GPU precision modes -- TEST INFRASTRUCTURE.
+
+Runs the same DNN-SP2 network as ``sp2_oracle.sp2`` but stores every iterate
+in FP32 and forms each square from the dual 16-bit representation of
+Eq. (20)-(22) (or plain FP32), with FP32 accumulation (NumPy ``float32``
+matmul).  Used only to predict the error floor each precision mode reaches
+against the exact density matrix, from which the end-to-end test
+tolerances are derived.  The accumulation order differs from the GPU's
+MFMA, so agreement with the GPU is statistical, not bitwise
+(parity unpinned for bitwise equality).
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+from .sp2_oracle import (FP16_SPLIT_SCALE_LOG2, choose_branch, gershgorin_bounds, should_stop,
+                         split_bf16, split_fp16_scaled)
+
+MODES = ("fp32", "bf16x1", "bf16x3", "fp16x3")
+
+
+def square_emulated(x, mode):
+    """``X^2`` of an FP32 symmetric matrix in the given arithmetic, FP32 result.
+    Split modes use Eq. (22): ``X0 X0 + X0 X1 + X1 X0`` (``X1 X1`` dropped)."""
+    x = np.asarray(x, dtype=np.float32)
+    if mode == "fp32":
+        return x @ x
+    if mode == "bf16x1":
+        hi, _ = split_bf16(x)
+        return hi @ hi
+    if mode == "bf16x3":
+        hi, lo = split_bf16(x)
+        return hi @ hi + (hi @ lo + lo @ hi)
+    if mode == "fp16x3":
+        hi, lo = split_fp16_scaled(x)
+        return (hi @ hi + (hi @ lo + lo @ hi)) * np.float32(2.0 ** (-2 * FP16_SPLIT_SCALE_LOG2))
+    raise ValueError(mode)
+
+
+def sp2_emulated(h, n_occ, mode, tol=1e-5, max_iter=100, stop_rule=1, stall_gate=1.0,
+                 refine=True):
+    """FP32-stored DNN-SP2 with the layer squares of ``mode``; the traces,
+    bounds and decisions are FP64 as on the GPU.  Returns ``(P, n_iter)``."""
+    h = np.asarray(h, dtype=np.float32)
+    n = h.shape[0]
+    lo_b, hi_b = gershgorin_bounds(h.astype(np.float64))
+    s = ((hi_b * np.eye(n) - h.astype(np.float64)) / (hi_b - lo_b)).astype(np.float32)
+    errs = []
+    layers = 0
+    for k in range(max_iter + 1):
+        sd = s.astype(np.float64)
+        t1 = float(np.trace(sd))
+        t2 = float(np.sum(sd * sd))
+        errs.append(abs(t1 - t2))
+        if should_stop(k, errs, tol, stop_rule, stall_gate) or k == max_iter:
+            break
+        sign = choose_branch(t1, t2, n_occ)
+        sq = square_emulated(s, mode).astype(np.float32)
+        s = sq if sign > 0 else np.float32(2.0) * s - sq
+        s = np.triu(s) + np.triu(s, 1).T          # upper triangle mirrored, as computed
+        layers += 1
+    if refine:
+        s2 = s @ s
+        s = np.float32(3.0) * s2 - np.float32(2.0) * (s @ s2)
+    return s, layers

@@ -143,6 +143,7 @@ class SP2Record:
     err: list = field(default_factory=list)
     converged: bool = False
     refine: bool = False
+    trivial: bool = False     # n_occ in {0, N}: P = 0 or I, independent of H
 
     @property
     def n_iter(self):
@@ -177,6 +178,7 @@ def sp2(h, n_occ, tol=1e-10, max_iter=100, stop_rule=0, stall_gate=1.0,
     rec = SP2Record(eps_min=eps_min, eps_max=eps_max, refine=refine)
     if n_occ == 0 or n_occ == n:
         rec.converged = True
+        rec.trivial = True
         d = np.zeros((n, n)) if n_occ == 0 else np.eye(n)
         return (d, rec, [d]) if return_iterates else (d, rec)
     if not eps_max > eps_min:
@@ -266,7 +268,7 @@ def sp2_jvp(h, h1, rec):
     ``3 (S dS + dS S) - 2 (S^2 dS + S dS S + dS S^2)``."""
     h1 = np.asarray(h1, dtype=np.float64)
     n = h.shape[0]
-    if len(rec.t1) == 0:          # n_occ in {0, N}: P does not depend on H
+    if rec.trivial:               # P does not depend on H
         return np.zeros((n, n))
     iters = _replay(h, rec)
     y = -h1 / (rec.eps_max - rec.eps_min)
@@ -288,7 +290,7 @@ def sp2_vjp(h, wmat, rec):
     ``dS -> S dS + dS S`` is the same map, so ``G <- S G + G S`` (sign +) or
     ``2 G - (S G + G S)`` (sign -), ending with ``-G / (eps_max - eps_min)``."""
     n = h.shape[0]
-    if len(rec.t1) == 0:          # n_occ in {0, N}: P does not depend on H
+    if rec.trivial:               # P does not depend on H
         return np.zeros((n, n))
     g = 0.5 * (np.asarray(wmat, dtype=np.float64) + np.asarray(wmat, dtype=np.float64).T)
     iters = _replay(h, rec)

@@ -1,0 +1,244 @@
+"""ctypes binding of the C ABI in ``include/sp2.h`` (argument marshalling only).
+
+Every function here has the name of the C entry point it calls and takes
+torch tensors where the C side takes device pointers.  torch supplies device
+memory and the current HIP stream; all computation runs in the library's
+HIP kernels.  torch is imported before the library is loaded so that both
+share one HIP runtime.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+from .build import LIB_PATH
+
+c_int32 = ctypes.c_int32
+c_int64 = ctypes.c_int64
+c_double = ctypes.c_double
+c_size_t = ctypes.c_size_t
+c_void_p = ctypes.c_void_p
+
+SP2_OK = 0
+SP2_ERR_INVALID_ARG = 1
+SP2_ERR_NONFINITE = 2
+SP2_ERR_NOT_CONVERGED = 3
+SP2_ERR_WORKSPACE = 4
+SP2_ERR_DEVICE = 5
+SP2_ERR_TAPE = 6
+STATUS_NAMES = {0: "SP2_OK", 1: "SP2_ERR_INVALID_ARG", 2: "SP2_ERR_NONFINITE",
+                3: "SP2_ERR_NOT_CONVERGED", 4: "SP2_ERR_WORKSPACE", 5: "SP2_ERR_DEVICE",
+                6: "SP2_ERR_TAPE"}
+
+PRECISIONS = {"fp32": 0, "bf16x1": 1, "bf16x3": 2, "fp16x3": 3}
+REFINES = {"none": 0, None: 0, False: 0, "fp32": 1, True: 1, "split": 2}
+SP2_MAX_ITER = 256
+
+# Every symbol include/sp2.h declares.
+EXPORTED = ["sp2_default_options", "sp2_workspace_bytes", "sp2_density", "sp2_density_ex",
+            "sp2_jvp", "sp2_vjp", "sp2_bounds", "sp2_split", "sp2_layer", "sp2_last_error"]
+
+
+class sp2_options(ctypes.Structure):
+    _fields_ = [("precision", c_int32), ("refine", c_int32), ("max_iter", c_int32),
+                ("stop_rule", c_int32), ("checkpoint_every", c_int32), ("flags", c_int32),
+                ("tol", c_double), ("stall_gate", c_double)]
+
+
+class sp2_info(ctypes.Structure):
+    _fields_ = [("n_iter", c_int32), ("converged", c_int32), ("status", c_int32),
+                ("reserved", c_int32), ("eps_min", c_double), ("eps_max", c_double),
+                ("trace", c_double), ("idem_err", c_double), ("layer_ms", c_double),
+                ("refine_ms", c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class SP2Error(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_LIB = None
+
+
+def load_library(path=None):
+    """Load ``libsp2.so`` (built in-tree by ``__graft_entry__.build()``).
+    Fails loudly when it is missing: there is no fallback path."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run __graft_entry__.build() first")
+    lib = ctypes.CDLL(path)
+    vp = c_void_p
+    lib.sp2_default_options.argtypes = [ctypes.POINTER(sp2_options)]
+    lib.sp2_default_options.restype = None
+    lib.sp2_workspace_bytes.argtypes = [c_int64, ctypes.POINTER(sp2_options)]
+    lib.sp2_workspace_bytes.restype = c_size_t
+    lib.sp2_density.argtypes = [vp, c_int64, c_int64, c_double, vp, ctypes.POINTER(c_int32), vp,
+                                c_int32, vp, c_size_t, vp]
+    lib.sp2_density.restype = c_int32
+    lib.sp2_density_ex.argtypes = [vp, c_int64, c_int64, c_int64, ctypes.POINTER(sp2_options), vp,
+                                   ctypes.POINTER(sp2_info), vp, c_int32, vp, c_size_t, vp]
+    lib.sp2_density_ex.restype = c_int32
+    lib.sp2_jvp.argtypes = [vp, c_size_t, vp, c_int64, vp, vp]
+    lib.sp2_jvp.restype = c_int32
+    lib.sp2_vjp.argtypes = [vp, c_size_t, vp, c_int64, vp, vp]
+    lib.sp2_vjp.restype = c_int32
+    lib.sp2_bounds.argtypes = [vp, c_int64, c_int64, ctypes.POINTER(c_double),
+                               ctypes.POINTER(c_double), vp, c_size_t, vp]
+    lib.sp2_bounds.restype = c_int32
+    lib.sp2_split.argtypes = [vp, c_int64, c_int64, c_int32, vp, vp, vp]
+    lib.sp2_split.restype = c_int32
+    lib.sp2_layer.argtypes = [vp, c_int64, c_int64, c_int32, c_int32, vp, vp, c_size_t, vp]
+    lib.sp2_layer.restype = c_int32
+    lib.sp2_last_error.argtypes = []
+    lib.sp2_last_error.restype = ctypes.c_char_p
+    _LIB = lib
+    return lib
+
+
+def _check(status, allow=()):
+    if status != SP2_OK and status not in allow:
+        msg = load_library().sp2_last_error().decode(errors="replace")
+        raise SP2Error(status, msg)
+    return status
+
+
+def _dev_ptr(t, dtype=torch.float32, name="tensor"):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}")
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError(f"{name} must be a 2-D row-major tensor")
+    return c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    return c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+SP2_FLAG_TIME_LAYERS = 1
+
+
+def make_options(precision="bf16x3", refine="fp32", max_iter=100, stop_rule=1,
+                 checkpoint_every=0, tol=1e-5, stall_gate=1.0, time_layers=False):
+    lib = load_library()
+    o = sp2_options()
+    lib.sp2_default_options(ctypes.byref(o))
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.refine = REFINES[refine] if not isinstance(refine, int) or isinstance(refine, bool) else int(refine)
+    o.max_iter = int(max_iter)
+    o.stop_rule = int(stop_rule)
+    o.checkpoint_every = int(checkpoint_every)
+    o.tol = float(tol)
+    o.stall_gate = float(stall_gate)
+    o.flags = SP2_FLAG_TIME_LAYERS if time_layers else 0
+    return o
+
+
+def sp2_default_options():
+    o = sp2_options()
+    load_library().sp2_default_options(ctypes.byref(o))
+    return o
+
+
+def sp2_workspace_bytes(n, opt=None):
+    lib = load_library()
+    return int(lib.sp2_workspace_bytes(int(n), ctypes.byref(opt) if opt is not None else None))
+
+
+def allocate_workspace(n, opt=None, device=None):
+    """Caller-owned device workspace (a torch uint8 tensor, 256-byte aligned)."""
+    nbytes = sp2_workspace_bytes(n, opt)
+    if nbytes == 0:
+        raise SP2Error(SP2_ERR_INVALID_ARG, "invalid size or options")
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device or "cuda")
+    off = (-ws.data_ptr()) % 256
+    return ws[off:off + nbytes]
+
+
+def sp2_density(H, n_occ, tol, P, workspace, branches_cap=SP2_MAX_ITER):
+    """Minimal form.  Returns ``(status, n_iter, branches)`` with ``branches`` a
+    host ``bytes`` object (1 = S^2, 0 = 2S - S^2)."""
+    lib = load_library()
+    n = H.shape[0]
+    n_iter = c_int32(0)
+    br = (ctypes.c_uint8 * max(1, branches_cap))()
+    st = lib.sp2_density(_dev_ptr(H, name="H"), n, int(n_occ), float(tol), _dev_ptr(P, name="P"),
+                         ctypes.byref(n_iter), br, branches_cap,
+                         c_void_p(workspace.data_ptr()), workspace.numel(), _stream(H.device))
+    _check(st, allow=(SP2_ERR_NOT_CONVERGED,))
+    return st, n_iter.value, bytes(br[:min(n_iter.value, branches_cap)])
+
+
+def sp2_density_ex(H, n_occ, opt, P, workspace, branches_cap=SP2_MAX_ITER, check=True):
+    """Full form.  ``H`` and ``P`` share the leading dimension ``H.stride(0)``.
+    Returns ``(status, info, branches)``."""
+    lib = load_library()
+    n = H.shape[0]
+    if P.stride(0) != H.stride(0):
+        raise ValueError("H and P must have the same leading dimension")
+    info = sp2_info()
+    br = (ctypes.c_uint8 * max(1, branches_cap))()
+    st = lib.sp2_density_ex(_dev_ptr(H, name="H"), n, H.stride(0), int(n_occ), ctypes.byref(opt),
+                            _dev_ptr(P, name="P"), ctypes.byref(info), br, branches_cap,
+                            c_void_p(workspace.data_ptr()), workspace.numel(), _stream(H.device))
+    if check:
+        _check(st, allow=(SP2_ERR_NOT_CONVERGED,))
+    return st, info, bytes(br[:min(info.n_iter, branches_cap)])
+
+
+def sp2_jvp(workspace, H1, P1):
+    lib = load_library()
+    _check(lib.sp2_jvp(c_void_p(workspace.data_ptr()), workspace.numel(), _dev_ptr(H1, name="H1"),
+                       H1.stride(0), _dev_ptr(P1, name="P1"), _stream(H1.device)))
+    return P1
+
+
+def sp2_vjp(workspace, W, G):
+    lib = load_library()
+    _check(lib.sp2_vjp(c_void_p(workspace.data_ptr()), workspace.numel(), _dev_ptr(W, name="W"),
+                       W.stride(0), _dev_ptr(G, name="G"), _stream(W.device)))
+    return G
+
+
+def sp2_bounds(H, workspace):
+    lib = load_library()
+    lo, hi = c_double(), c_double()
+    _check(lib.sp2_bounds(_dev_ptr(H, name="H"), H.shape[0], H.stride(0), ctypes.byref(lo),
+                          ctypes.byref(hi), c_void_p(workspace.data_ptr()), workspace.numel(),
+                          _stream(H.device)))
+    return lo.value, hi.value
+
+
+def sp2_split(X, precision, hi, lo):
+    lib = load_library()
+    p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    _check(lib.sp2_split(_dev_ptr(X, name="X"), X.shape[0], X.stride(0), p,
+                         _dev_ptr(hi, torch.int16, "hi"), _dev_ptr(lo, torch.int16, "lo"),
+                         _stream(X.device)))
+    return hi, lo
+
+
+def sp2_layer(X, precision, sign, Y, workspace):
+    lib = load_library()
+    p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    if Y.stride(0) != X.stride(0):
+        raise ValueError("X and Y must have the same leading dimension")
+    _check(lib.sp2_layer(_dev_ptr(X, name="X"), X.shape[0], X.stride(0), p, int(sign),
+                         _dev_ptr(Y, name="Y"), c_void_p(workspace.data_ptr()), workspace.numel(),
+                         _stream(X.device)))
+    return Y
+
+
+def sp2_last_error():
+    return load_library().sp2_last_error().decode(errors="replace")

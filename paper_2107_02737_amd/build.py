@@ -1,0 +1,86 @@
+"""Build the gfx950 shared library ``lib/libsp2.so`` from ``csrc/`` with hipcc.
+
+The library is the product: the C ABI of ``include/sp2.h`` with the HIP
+kernels behind it.  It is compiled for gfx950 only.
+"""
+
+import os
+import shutil
+import subprocess
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+LIB_DIR = os.path.join(PKG, "lib")
+LIB_PATH = os.path.join(LIB_DIR, "libsp2.so")
+SOURCES = ["sp2_capi.hip"]
+HEADERS = ["sp2_common.hpp", "sp2_aux.hpp", "sp2_gemm.hpp"]
+
+
+def hipcc():
+    path = os.environ.get("HIPCC") or shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(path):
+        raise RuntimeError("hipcc not found (set HIPCC)")
+    return path
+
+
+def compile_command(out=LIB_PATH):
+    return [
+        hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+        "-mcode-object-version=5",
+        # packed FP32 instructions stay off: the compiler must not form them
+        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+        "-Wall", "-Wno-unused-function",
+        "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+        *[os.path.join(CSRC, s) for s in SOURCES],
+        "-o", out,
+    ]
+
+
+def kernel_resources():
+    """Compile the device code to gfx950 assembly and return, per kernel, its
+    scratch (private segment) bytes, VGPR count and VGPR/SGPR spill counts."""
+    import re
+    import tempfile
+    with tempfile.TemporaryDirectory() as tmp:
+        out = os.path.join(tmp, "sp2.s")
+        cmd = [c for c in compile_command(out) if c not in ("-shared", "-fPIC")]
+        cmd += ["--offload-device-only", "-S"]
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            raise RuntimeError("hipcc failed:\n" + res.stderr)
+        text = open(out).read()
+    kernels = {}
+    meta = text[text.index("amdhsa.kernels:"):]
+    for block in meta.split("\n  - ")[1:]:
+        if ".name:" not in block:
+            continue
+        name = re.search(r"\.name:\s+(\S+)", block).group(1)
+        field = lambda k: int(re.search(r"\." + k + r":\s+(\d+)", block).group(1))  # noqa: E731
+        kernels[name] = {"private_segment_fixed_size": field("private_segment_fixed_size"),
+                         "vgpr_count": field("vgpr_count"),
+                         "vgpr_spill_count": field("vgpr_spill_count"),
+                         "sgpr_spill_count": field("sgpr_spill_count"),
+                         "group_segment_fixed_size": field("group_segment_fixed_size")}
+    return kernels
+
+
+def build(verbose=False):
+    """Compile the library (always, even when one is present) and return its path."""
+    os.makedirs(LIB_DIR, exist_ok=True)
+    tmp = LIB_PATH + ".tmp"
+    cmd = compile_command(tmp)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if verbose or res.returncode != 0:
+        msg = "\n".join(line for line in (res.stdout + res.stderr).splitlines()
+                        if "packed-fp32-ops" not in line)
+        if msg.strip():
+            print(msg)
+    if res.returncode != 0:
+        raise RuntimeError("hipcc failed building libsp2.so:\n" + " ".join(cmd))
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

@@ -1,0 +1,284 @@
+// Bandwidth-bound kernels around the layer products: Gershgorin bounds,
+// the input layer with its fused 16-bit split and trace partials, the plain
+// split, output copies and the one-work-group control steps.
+#pragma once
+
+#include "sp2_common.hpp"
+
+namespace sp2 {
+
+constexpr int kRowThreads = 256;     // threads per Gershgorin block
+constexpr int kRowsPerBlock = 4;     // one wave per row
+
+// Per-row Gershgorin discs in FP64 for rows [0, n) of H: block b writes
+// (min_i lower, max_i upper, any non-finite) over its rows.
+__global__ __launch_bounds__(kRowThreads) void k_gershgorin_rows(const float* __restrict__ H,
+                                                                 int64_t n, int64_t ld,
+                                                                 double* __restrict__ part) {
+  __shared__ double red[3 * kRowsPerBlock];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  const int64_t row = int64_t(blockIdx.x) * kRowsPerBlock + w;
+  double lo = INFINITY, hi = -INFINITY, bad = 0.0;
+  if (row < n) {
+    const float* r = H + row * ld;
+    double s = 0.0;
+    bool finite = true;
+    for (int64_t j = lane; j < n; j += kWave) {
+      const float v = r[j];
+      finite = finite && isfinite(v);
+      if (j != row) s += fabs(static_cast<double>(v));
+    }
+    s = wave_sum(s);
+    const double fin = wave_min(finite ? 1.0 : 0.0);
+    const double d = static_cast<double>(r[row]);
+    lo = d - s;
+    hi = d + s;
+    bad = (fin == 0.0 || !isfinite(s) || !isfinite(d)) ? 1.0 : 0.0;
+  }
+  if (lane == 0) {
+    red[w] = lo;
+    red[kRowsPerBlock + w] = hi;
+    red[2 * kRowsPerBlock + w] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = red[0], b = red[kRowsPerBlock], c = red[2 * kRowsPerBlock];
+    for (int i = 1; i < kRowsPerBlock; ++i) {
+      a = fmin(a, red[i]);
+      b = fmax(b, red[kRowsPerBlock + i]);
+      c = fmax(c, red[2 * kRowsPerBlock + i]);
+    }
+    part[3 * blockIdx.x + 0] = a;
+    part[3 * blockIdx.x + 1] = b;
+    part[3 * blockIdx.x + 2] = c;
+  }
+}
+
+// One work-group: reduce the per-block discs into the bounds, flag NaN/Inf
+// and a degenerate spectrum, and reset the stop state.  `trivial` marks
+// n_occ in {0, n}: nothing to iterate.
+__global__ __launch_bounds__(256) void k_bounds_final(const double* __restrict__ part, int nblocks,
+                                                      Ctrl* ctrl, int trivial) {
+  __shared__ double red[3 * 4];
+  double lo = INFINITY, hi = -INFINITY, bad = 0.0;
+  for (int i = threadIdx.x; i < nblocks; i += 256) {
+    lo = fmin(lo, part[3 * i]);
+    hi = fmax(hi, part[3 * i + 1]);
+    bad = fmax(bad, part[3 * i + 2]);
+  }
+  lo = wave_min(lo);
+  hi = wave_max(hi);
+  bad = wave_max(bad);
+  const int w = threadIdx.x / kWave;
+  if ((threadIdx.x & 63) == 0) {
+    red[w] = lo;
+    red[4 + w] = hi;
+    red[8 + w] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < 4; ++i) {
+      red[0] = fmin(red[0], red[i]);
+      red[4] = fmax(red[4], red[4 + i]);
+      red[8] = fmax(red[8], red[8 + i]);
+    }
+    const double emin = red[0], emax = red[4];
+    const int nonfinite = red[8] != 0.0 || !isfinite(emin) || !isfinite(emax);
+    const int degenerate = !nonfinite && !(emax > emin);
+    ctrl->eps_min = emin;
+    ctrl->eps_max = emax;
+    ctrl->inv_range = (nonfinite || degenerate) ? 0.0 : 1.0 / (emax - emin);
+    ctrl->nonfinite = nonfinite;
+    ctrl->degenerate = degenerate;
+    ctrl->n_iter = 0;
+    ctrl->converged = (trivial && !nonfinite) ? 1 : 0;
+    ctrl->stopped = (nonfinite || degenerate || trivial) ? 1 : 0;
+    ctrl->final_t1 = 0.0;
+    ctrl->final_t2 = 0.0;
+  }
+}
+
+constexpr int kEwThreads = 256;
+
+// Input layer S_0 = (eps_max I - H) / (eps_max - eps_min) (Section II.D),
+// scalars in FP64, stored FP32 into the padded np x np buffer S (zero
+// padding), with optional dual 16-bit split (split: 0 none, 1 bf16, 2 fp16
+// scaled) and one (Tr, ||.||_F^2) partial pair per block.  A degenerate
+// spectrum gives S_0 = I/2.  Each thread handles 4 consecutive columns.
+__global__ __launch_bounds__(kEwThreads) void k_input_layer(const float* __restrict__ H, int64_t n,
+                                                            int64_t ld, int64_t np,
+                                                            const Ctrl* __restrict__ ctrl,
+                                                            float* __restrict__ S,
+                                                            uint16_t* __restrict__ hi,
+                                                            uint16_t* __restrict__ lo, int split,
+                                                            double* __restrict__ parts) {
+  __shared__ double red[2 * (kEwThreads / kWave)];
+  const double emax = ctrl->eps_max;
+  const double inv = ctrl->inv_range;
+  const bool degenerate = ctrl->degenerate != 0;
+  const int64_t quads = np * np / 4;
+  double t1 = 0.0, t2 = 0.0;
+  for (int64_t q = int64_t(blockIdx.x) * kEwThreads + threadIdx.x; q < quads;
+       q += int64_t(gridDim.x) * kEwThreads) {
+    const int64_t i = (4 * q) / np;
+    const int64_t j0 = (4 * q) % np;
+    float v[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int64_t j = j0 + c;
+      float x = 0.0f;
+      if (i < n && j < n) {
+        if (degenerate) {
+          x = (i == j) ? 0.5f : 0.0f;
+        } else {
+          const double h = static_cast<double>(H[i * ld + j]);
+          x = static_cast<float>(((i == j ? emax : 0.0) - h) * inv);
+        }
+      }
+      v[c] = x;
+      const double xd = static_cast<double>(x);
+      t2 += xd * xd;
+      if (i == j) t1 += xd;
+    }
+    *reinterpret_cast<f32x4*>(S + i * np + j0) = f32x4{v[0], v[1], v[2], v[3]};
+    if (split) {
+      uint16_t h4[4], l4[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (split == 1)
+          split_bf16(v[c], h4[c], l4[c]);
+        else
+          split_fp16s(v[c], h4[c], l4[c]);
+      }
+      *reinterpret_cast<uint2*>(hi + i * np + j0) =
+          uint2{uint32_t(h4[0]) | (uint32_t(h4[1]) << 16), uint32_t(h4[2]) | (uint32_t(h4[3]) << 16)};
+      *reinterpret_cast<uint2*>(lo + i * np + j0) =
+          uint2{uint32_t(l4[0]) | (uint32_t(l4[1]) << 16), uint32_t(l4[2]) | (uint32_t(l4[3]) << 16)};
+    }
+  }
+  block_sum2<kEwThreads>(t1, t2, red);
+  if (threadIdx.x == 0) {
+    parts[2 * blockIdx.x] = t1;
+    parts[2 * blockIdx.x + 1] = t2;
+  }
+}
+
+// Dual representation of an n x n FP32 matrix (leading dimension ld) into
+// hi/lo planes with leading dimension ldo; rows/cols in [n, np) are zero.
+// split: 1 bf16, 2 fp16 scaled.
+__global__ __launch_bounds__(kEwThreads) void k_split(const float* __restrict__ X, int64_t n,
+                                                      int64_t ld, int64_t np, int64_t ldo,
+                                                      uint16_t* __restrict__ hi,
+                                                      uint16_t* __restrict__ lo, int split) {
+  const int64_t total = np * np;
+  for (int64_t q = int64_t(blockIdx.x) * kEwThreads + threadIdx.x; q < total;
+       q += int64_t(gridDim.x) * kEwThreads) {
+    const int64_t i = q / np, j = q % np;
+    const float x = (i < n && j < n) ? X[i * ld + j] : 0.0f;
+    uint16_t h, l;
+    if (split == 1)
+      split_bf16(x, h, l);
+    else
+      split_fp16s(x, h, l);
+    hi[i * ldo + j] = h;
+    lo[i * ldo + j] = l;
+  }
+}
+
+// Y[i, j] = alpha * X[i, j] for i, j < n, with independent leading dimensions
+// (pads, unpads and scales a matrix); padding of a larger Y is zeroed when
+// np > n.
+__global__ __launch_bounds__(kEwThreads) void k_copy_scaled(const float* __restrict__ X, int64_t ldx,
+                                                            float* __restrict__ Y, int64_t ldy,
+                                                            int64_t n, int64_t np, float alpha,
+                                                            int symmetrize) {
+  const int64_t total = np * np;
+  for (int64_t q = int64_t(blockIdx.x) * kEwThreads + threadIdx.x; q < total;
+       q += int64_t(gridDim.x) * kEwThreads) {
+    const int64_t i = q / np, j = q % np;
+    float v = 0.0f;
+    if (i < n && j < n) {
+      v = X[i * ldx + j];
+      if (symmetrize) v = 0.5f * (v + X[j * ldx + i]);
+      v *= alpha;
+    }
+    Y[i * ldy + j] = v;
+  }
+}
+
+// P = 0 (value 0) or P = I (value 1), n x n with leading dimension ld.
+__global__ __launch_bounds__(kEwThreads) void k_fill_diag(float* __restrict__ P, int64_t n,
+                                                          int64_t ld, float value) {
+  const int64_t total = n * n;
+  for (int64_t q = int64_t(blockIdx.x) * kEwThreads + threadIdx.x; q < total;
+       q += int64_t(gridDim.x) * kEwThreads) {
+    const int64_t i = q / n, j = q % n;
+    P[i * ld + j] = (i == j) ? value : 0.0f;
+  }
+}
+
+// One work-group after the layer loop: when the network did not stop within
+// max_iter layers, evaluate the stop test on S_{max_iter} and record it.
+__global__ __launch_bounds__(256) void k_finish_loop(Ctrl* ctrl, Hist* hist,
+                                                     const double* __restrict__ parts, int nparts,
+                                                     int max_iter, double tol, int stop_rule,
+                                                     double stall_gate) {
+  __shared__ double red[8];
+  if (ctrl->stopped) return;
+  double t1 = 0.0, t2 = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += 256) {
+    t1 += parts[2 * i];
+    t2 += parts[2 * i + 1];
+  }
+  block_sum2<256>(t1, t2, red);
+  if (threadIdx.x == 0) {
+    const int n = max_iter;
+    const double e = fabs(t1 - t2);
+    bool stop = e < tol;
+    if (!stop && stop_rule == 1 && n >= 2 && e < stall_gate && e >= hist->err[n - 2]) stop = true;
+    hist->t1[n] = t1;
+    hist->t2[n] = t2;
+    hist->err[n] = e;
+    ctrl->n_iter = n;
+    ctrl->converged = stop ? 1 : 0;
+    ctrl->stopped = 1;
+  }
+}
+
+// One work-group: sum (Tr, ||.||_F^2) partials of the returned P into ctrl.
+__global__ __launch_bounds__(256) void k_sum_parts(Ctrl* ctrl, const double* __restrict__ parts,
+                                                   int nparts) {
+  __shared__ double red[8];
+  double t1 = 0.0, t2 = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += 256) {
+    t1 += parts[2 * i];
+    t2 += parts[2 * i + 1];
+  }
+  block_sum2<256>(t1, t2, red);
+  if (threadIdx.x == 0) {
+    ctrl->final_t1 = t1;
+    ctrl->final_t2 = t2;
+  }
+}
+
+// (Tr, ||.||_F^2) partials of an np x np FP32 matrix, one pair per block.
+__global__ __launch_bounds__(kEwThreads) void k_trace_parts(const float* __restrict__ S, int64_t np,
+                                                            double* __restrict__ parts) {
+  __shared__ double red[2 * (kEwThreads / kWave)];
+  double t1 = 0.0, t2 = 0.0;
+  const int64_t total = np * np;
+  for (int64_t q = int64_t(blockIdx.x) * kEwThreads + threadIdx.x; q < total;
+       q += int64_t(gridDim.x) * kEwThreads) {
+    const double v = static_cast<double>(S[q]);
+    t2 += v * v;
+    if (q / np == q % np) t1 += v;
+  }
+  block_sum2<kEwThreads>(t1, t2, red);
+  if (threadIdx.x == 0) {
+    parts[2 * blockIdx.x] = t1;
+    parts[2 * blockIdx.x + 1] = t2;
+  }
+}
+
+}  // namespace sp2

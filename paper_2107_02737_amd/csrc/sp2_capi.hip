@@ -1,0 +1,913 @@
+// Host driver and C ABI of the gfx950 DNN-SP2 solver (declared in sp2.h).
+//
+// One solve: Gershgorin bounds -> input layer (fused split + trace
+// partials) -> layer loop -> optional McWeeny refinement -> P.  Every layer
+// launch decides its own branch and stop from the FP64 trace partials left
+// by the previous launch, so the host never waits between layers; it polls
+// the device stop flag once per chunk of layers while the next chunk is
+// already queued.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "sp2_aux.hpp"
+#include "sp2_common.hpp"
+#include "sp2_gemm.hpp"
+
+using namespace sp2;
+
+namespace {
+
+thread_local std::string g_err;
+
+sp2_status fail(sp2_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(SP2_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));       \
+  } while (0)
+
+#define LAUNCH_TRY()                                                                    \
+  do {                                                                                  \
+    hipError_t e_ = hipGetLastError();                                                  \
+    if (e_ != hipSuccess)                                                               \
+      return fail(SP2_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e_));   \
+  } while (0)
+
+constexpr int64_t kPad = 256;          // matrices are padded to a multiple of this
+constexpr int kBand = 4;               // tile-rows per band of the tile schedule
+constexpr int kChunk = 8;              // layers launched between stop-flag polls
+constexpr int kInitBlocksMax = 1024;   // partial pairs written by the input layer
+constexpr int kF32Tile = 128;
+
+int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+// Tape description kept in the workspace for sp2_jvp / sp2_vjp.
+struct Meta {
+  int64_t n, np;
+  int32_t precision, refine, every, n_iter;
+  int32_t valid;       // 1: tape usable, 2: trivial occupation (P independent of H), 0: none
+  int32_t max_iter;
+  int64_t magic;
+};
+constexpr int64_t kMetaMagic = 0x5350324d45544131LL;
+
+// Workspace layout (byte offsets), derived from n and the options only.
+struct Layout {
+  int64_t n, np;
+  int split_tile;       // 256 or 128 (16-bit split products)
+  int nb_split, ntiles_split, nb_f32, ntiles_f32;
+  int init_blocks, gersh_blocks, max_parts;
+  size_t off_ctrl, off_hist, off_meta, off_parts0, off_parts1, off_gersh;
+  size_t off_slot0;     // first matrix slot
+  size_t slot_bytes;
+  int nslots, ntape, every;
+  size_t total;
+};
+
+int ntiles_of(int nb) { return nb * (nb + 1) / 2; }
+
+int pick_split_tile(int64_t np) {
+  if (const char* s = getenv("SP2_SPLIT_TILE")) {
+    const int t = atoi(s);
+    if (t == 128 || t == 256) return t;
+  }
+  return np >= 8192 ? 256 : 128;
+}
+
+bool make_layout(int64_t n, const sp2_options& o, Layout& L) {
+  if (n <= 0 || n > (int64_t(1) << 20)) return false;
+  L.n = n;
+  L.np = round_up(n, kPad);
+  L.split_tile = pick_split_tile(L.np);
+  L.nb_split = static_cast<int>(L.np / L.split_tile);
+  L.ntiles_split = ntiles_of(L.nb_split);
+  L.nb_f32 = static_cast<int>(L.np / kF32Tile);
+  L.ntiles_f32 = ntiles_of(L.nb_f32);
+  const int64_t quads = L.np * L.np / 4;
+  L.init_blocks = static_cast<int>(std::min<int64_t>(kInitBlocksMax, (quads + kEwThreads - 1) / kEwThreads));
+  L.gersh_blocks = static_cast<int>((n + kRowsPerBlock - 1) / kRowsPerBlock);
+  L.max_parts = std::max({L.ntiles_split, L.ntiles_f32, L.init_blocks, kInitBlocksMax});
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o2 = off;
+    off = round_up(off + bytes, 256);
+    return o2;
+  };
+  L.off_ctrl = take(sizeof(Ctrl));
+  L.off_hist = take(sizeof(Hist));
+  L.off_meta = take(sizeof(Meta));
+  L.off_parts0 = take(size_t(L.max_parts) * 16);
+  L.off_parts1 = take(size_t(L.max_parts) * 16);
+  L.off_gersh = take(size_t(L.gersh_blocks) * 24);
+  L.slot_bytes = size_t(L.np) * size_t(L.np) * 4;
+  L.every = o.checkpoint_every;
+  // slots 0-3: S (FP32), two hi/lo plane pairs (or FP32 ping-pong), S^2 for
+  // the refinement.  With a tape: 4 derivative work slots, `every` segment
+  // slots and the checkpoints S_0, S_k, S_2k, ...
+  L.ntape = L.every > 0 ? o.max_iter / L.every + 1 : 0;
+  L.nslots = 4 + (L.every > 0 ? 4 + L.every + L.ntape : 0);
+  L.off_slot0 = off;
+  L.total = off + L.slot_bytes * size_t(L.nslots);
+  return true;
+}
+
+struct WS {
+  Layout L;
+  char* base;
+  Ctrl* ctrl;
+  Hist* hist;
+  Meta* meta;
+  double* parts[2];
+  double* gersh;
+  float* slotf(int i) const { return reinterpret_cast<float*>(base + L.off_slot0 + L.slot_bytes * size_t(i)); }
+  uint16_t* hi(int pair) const { return reinterpret_cast<uint16_t*>(slotf(1 + pair)); }
+  uint16_t* lo(int pair) const { return hi(pair) + L.np * L.np; }
+  // derivative work slots and tape
+  float* work(int i) const { return slotf(4 + i); }
+  float* seg(int i) const { return slotf(8 + i); }
+  float* tape(int i) const { return slotf(8 + L.every + i); }
+};
+
+void bind(WS& w, void* ws, const Layout& L) {
+  w.L = L;
+  w.base = static_cast<char*>(ws);
+  w.ctrl = reinterpret_cast<Ctrl*>(w.base + L.off_ctrl);
+  w.hist = reinterpret_cast<Hist*>(w.base + L.off_hist);
+  w.meta = reinterpret_cast<Meta*>(w.base + L.off_meta);
+  w.parts[0] = reinterpret_cast<double*>(w.base + L.off_parts0);
+  w.parts[1] = reinterpret_cast<double*>(w.base + L.off_parts1);
+  w.gersh = reinterpret_cast<double*>(w.base + L.off_gersh);
+}
+
+bool options_ok(const sp2_options& o) {
+  return o.precision >= SP2_FP32 && o.precision <= SP2_FP16X3 && o.refine >= SP2_REFINE_NONE &&
+         o.refine <= SP2_REFINE_SPLIT && o.max_iter >= 1 && o.max_iter <= SP2_MAX_ITER &&
+         (o.stop_rule == 0 || o.stop_rule == 1) && o.checkpoint_every >= 0 &&
+         o.checkpoint_every <= SP2_MAX_ITER && o.tol >= 0.0 && o.stall_gate >= 0.0 &&
+         (o.flags & ~SP2_FLAG_TIME_LAYERS) == 0;
+}
+
+int split_kind_of(int precision) {
+  switch (precision) {
+    case SP2_BF16X1: return kBF16X1;
+    case SP2_BF16X3: return kBF16X3;
+    case SP2_FP16X3: return kFP16X3;
+    default: return -1;
+  }
+}
+
+// Split code used by the epilogue / split kernels: 1 bf16, 2 scaled fp16.
+int split_code_of(int precision) {
+  if (precision == SP2_FP16X3) return 2;
+  if (precision == SP2_BF16X1 || precision == SP2_BF16X3) return 1;
+  return 0;
+}
+
+float out_scale_of(int precision) {
+  return precision == SP2_FP16X3 ? 1.0f / float(1u << (2 * kFp16ScaleLog2)) : 1.0f;
+}
+
+// Pinned host mirror of the control block and history, one per thread.
+struct HostMirror {
+  Ctrl ctrl[2];
+  Hist hist;
+  Meta meta;
+};
+thread_local HostMirror* g_host = nullptr;
+
+sp2_status host_mirror(HostMirror** out) {
+  if (!g_host) {
+    void* p = nullptr;
+    HIP_TRY(hipHostMalloc(&p, sizeof(HostMirror), hipHostMallocDefault));
+    g_host = static_cast<HostMirror*>(p);
+  }
+  *out = g_host;
+  return SP2_OK;
+}
+
+Epi make_epi(const Layout& L) {
+  Epi e;
+  memset(&e, 0, sizeof(e));
+  e.np = static_cast<int>(L.np);
+  e.ld_out = L.np;
+  e.n_valid = static_cast<int>(L.np);
+  e.vec_ok = 1;
+  e.alpha = 1.0f;
+  e.beta = 0.0f;
+  e.oscale = 1.0f;
+  return e;
+}
+
+Decide make_decide(const WS& w, int mode, int layer) {
+  Decide d;
+  memset(&d, 0, sizeof(d));
+  d.ctrl = w.ctrl;
+  d.hist = w.hist;
+  d.mode = mode;
+  d.layer = layer;
+  return d;
+}
+
+// Launch a 16-bit split product of planes (a_hi, a_lo) x (b_hi, b_lo)^T.
+sp2_status launch_split(const WS& w, int precision, const uint16_t* ah, const uint16_t* al,
+                        const uint16_t* bh, const uint16_t* bl, const Epi& epi, const Decide& dec,
+                        hipStream_t st) {
+  SplitArgs a;
+  a.a_hi = ah;
+  a.a_lo = al;
+  a.b_hi = bh;
+  a.b_lo = bl;
+  a.epi = epi;
+  a.epi.oscale = out_scale_of(precision);
+  a.dec = dec;
+  a.band = kBand;
+  a.nb = w.L.nb_split;
+  a.ntiles = w.L.ntiles_split;
+  const dim3 grid(a.ntiles);
+  const int kind = split_kind_of(precision);
+  if (w.L.split_tile == 256) {
+    if (kind == kBF16X3) k_sym_split<kBF16X3, 256, 2, 4><<<grid, 512, 0, st>>>(a);
+    else if (kind == kBF16X1) k_sym_split<kBF16X1, 256, 2, 4><<<grid, 512, 0, st>>>(a);
+    else k_sym_split<kFP16X3, 256, 2, 4><<<grid, 512, 0, st>>>(a);
+  } else {
+    if (kind == kBF16X3) k_sym_split<kBF16X3, 128, 2, 2><<<grid, 256, 0, st>>>(a);
+    else if (kind == kBF16X1) k_sym_split<kBF16X1, 128, 2, 2><<<grid, 256, 0, st>>>(a);
+    else k_sym_split<kFP16X3, 128, 2, 2><<<grid, 256, 0, st>>>(a);
+  }
+  LAUNCH_TRY();
+  return SP2_OK;
+}
+
+// Launch an FP32 product sum_s A_s B_s^T (nseg <= 4).
+sp2_status launch_f32(const WS& w, int nseg, const float* const* A, const float* const* B,
+                      const Epi& epi, const Decide& dec, hipStream_t st) {
+  F32Args a;
+  memset(&a, 0, sizeof(a));
+  for (int s = 0; s < nseg; ++s) {
+    a.a[s] = A[s];
+    a.b[s] = B[s];
+  }
+  a.nseg = nseg;
+  a.epi = epi;
+  a.dec = dec;
+  a.band = kBand;
+  a.nb = w.L.nb_f32;
+  a.ntiles = w.L.ntiles_f32;
+  k_sym_f32<kF32Tile, 2, 2><<<dim3(a.ntiles), 256, 0, st>>>(a);
+  LAUNCH_TRY();
+  return SP2_OK;
+}
+
+int nparts_of_layer(const Layout& L, int precision, int layer) {
+  if (layer == 0) return L.init_blocks;
+  return precision == SP2_FP32 ? L.ntiles_f32 : L.ntiles_split;
+}
+
+// Where S_n lives in the forward network (FP32 value and hi/lo planes).
+float* s_f32(const WS& w, int precision, int n) {
+  return precision == SP2_FP32 ? w.slotf(n & 1) : w.slotf(0);
+}
+
+// One forward layer S_n -> S_{n+1}.  mode 1: device decision; mode 2: replay
+// the recorded branch.  src/dst FP32 buffers may alias (split modes only).
+sp2_status launch_layer(const WS& w, int precision, int n, int mode, const float* src, float* dst,
+                        int pair_in, int pair_out, double* parts_out, hipStream_t st,
+                        const sp2_options* o, int64_t n_occ) {
+  Decide d = make_decide(w, mode, n);
+  if (mode == 1) {
+    d.parts_in = w.parts[n & 1];
+    d.nparts_in = nparts_of_layer(w.L, precision, n);
+    d.n_occ = static_cast<double>(n_occ);
+    d.tol = o->tol;
+    d.stall_gate = o->stall_gate;
+    d.stop_rule = o->stop_rule;
+  }
+  Epi e = make_epi(w.L);
+  e.c = src;
+  e.out = dst;
+  e.parts_out = parts_out;
+  if (precision == SP2_FP32) {
+    const float* A[1] = {src};
+    return launch_f32(w, 1, A, A, e, d, st);
+  }
+  e.split_out = split_code_of(precision);
+  e.hi_out = w.hi(pair_out);
+  e.lo_out = w.lo(pair_out);
+  return launch_split(w, precision, w.hi(pair_in), w.lo(pair_in), w.hi(pair_in), w.lo(pair_in), e,
+                      d, st);
+}
+
+sp2_status check_ws(const Layout& L, void* ws, size_t ws_bytes) {
+  if (!ws) return fail(SP2_ERR_WORKSPACE, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(SP2_ERR_WORKSPACE, "workspace not 256-byte aligned");
+  if (ws_bytes < L.total)
+    return fail(SP2_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+  return SP2_OK;
+}
+
+int ew_grid(int64_t elems) {
+  return static_cast<int>(std::min<int64_t>(8192, std::max<int64_t>(1, (elems + kEwThreads - 1) / kEwThreads)));
+}
+
+__global__ void k_write_meta(Meta* m, Meta v) { *m = v; }
+
+// Timing events for SP2_FLAG_TIME_LAYERS: a start and an end event around
+// every layer launch and around the refinement.
+struct LayerTimer {
+  std::vector<hipEvent_t> ev;
+  bool on = false;
+  ~LayerTimer() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+  hipError_t init(int max_iter) {
+    on = true;
+    ev.assign(2 * max_iter + 2, nullptr);
+    for (auto& e : ev) {
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+    }
+    return hipSuccess;
+  }
+  hipError_t mark(int idx, hipStream_t st) { return on ? hipEventRecord(ev[idx], st) : hipSuccess; }
+  // summed milliseconds of pairs (2k, 2k+1) for k in [k0, k1)
+  double sum(int k0, int k1) const {
+    double t = 0.0;
+    for (int k = k0; k < k1; ++k) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]) == hipSuccess) t += ms;
+    }
+    return t;
+  }
+};
+
+// McWeeny refinement P = 3 S^2 - 2 S^3 into `out` (leading dimension ld,
+// n valid rows/cols); writes trace partials into parts[0].
+sp2_status refine(const WS& w, int precision, int refine_mode, int n_iter, const float* S,
+                  float* out, int64_t ld, int64_t n, bool vec_ok, hipStream_t st) {
+  const Layout& L = w.L;
+  float* S2 = w.slotf(3);
+  Epi e1 = make_epi(L);
+  e1.out = S2;
+  Epi e2 = make_epi(L);
+  e2.c = S2;
+  e2.out = out;
+  e2.ld_out = ld;
+  e2.n_valid = static_cast<int>(n);
+  e2.vec_ok = vec_ok;
+  e2.alpha = -2.0f;
+  e2.beta = 3.0f;
+  e2.parts_out = w.parts[0];
+  const Decide d0 = make_decide(w, 0, 0);
+  sp2_status s;
+  if (refine_mode == SP2_REFINE_FP32) {
+    const float* A[1] = {S};
+    if ((s = launch_f32(w, 1, A, A, e1, d0, st))) return s;
+    const float* B[1] = {S2};
+    if ((s = launch_f32(w, 1, A, B, e2, d0, st))) return s;
+    return SP2_OK;
+  }
+  // FP16X3 split refinement: planes of S (pair p) and of S^2 (pair 1-p).
+  const int p = precision == SP2_FP32 ? 0 : (n_iter & 1);
+  if (precision != SP2_FP16X3) {
+    k_split<<<ew_grid(L.np * L.np), kEwThreads, 0, st>>>(S, L.np, L.np, L.np, L.np, w.hi(p), w.lo(p), 2);
+    LAUNCH_TRY();
+  }
+  e1.split_out = 2;
+  e1.hi_out = w.hi(1 - p);
+  e1.lo_out = w.lo(1 - p);
+  if ((s = launch_split(w, SP2_FP16X3, w.hi(p), w.lo(p), w.hi(p), w.lo(p), e1, d0, st))) return s;
+  return launch_split(w, SP2_FP16X3, w.hi(p), w.lo(p), w.hi(1 - p), w.lo(1 - p), e2, d0, st);
+}
+
+sp2_status read_back(const WS& w, HostMirror* hm, bool with_hist, hipStream_t st) {
+  HIP_TRY(hipMemcpyAsync(&hm->ctrl[0], w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+  if (with_hist) HIP_TRY(hipMemcpyAsync(&hm->hist, w.hist, sizeof(Hist), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return SP2_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+void sp2_default_options(sp2_options* opt) {
+  if (!opt) return;
+  memset(opt, 0, sizeof(*opt));
+  opt->precision = SP2_BF16X3;
+  opt->refine = SP2_REFINE_FP32;
+  opt->max_iter = 100;
+  opt->stop_rule = 1;
+  opt->checkpoint_every = 0;
+  opt->tol = 1e-5;
+  opt->stall_gate = 1.0;
+}
+
+const char* sp2_last_error(void) { return g_err.c_str(); }
+
+size_t sp2_workspace_bytes(int64_t n, const sp2_options* opt) {
+  sp2_options o;
+  sp2_default_options(&o);
+  if (opt) o = *opt;
+  if (!options_ok(o)) return 0;
+  Layout L;
+  if (!make_layout(n, o, L)) return 0;
+  return L.total;
+}
+
+sp2_status sp2_density_ex(const float* H, int64_t n, int64_t ld, int64_t n_occ,
+                          const sp2_options* opt, float* P, sp2_info* info, uint8_t* branches,
+                          int32_t branches_cap, void* workspace, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  sp2_options o;
+  sp2_default_options(&o);
+  if (opt) o = *opt;
+  if (!H || !P) return fail(SP2_ERR_INVALID_ARG, "H and P must be non-NULL");
+  if (n <= 0 || ld < n) return fail(SP2_ERR_INVALID_ARG, "need n > 0 and ld >= n");
+  if (n_occ < 0 || n_occ > n) return fail(SP2_ERR_INVALID_ARG, "n_occ must lie in [0, n]");
+  if (!options_ok(o)) return fail(SP2_ERR_INVALID_ARG, "invalid options");
+  if (branches_cap < 0 || (branches_cap > 0 && !branches))
+    return fail(SP2_ERR_INVALID_ARG, "branches buffer missing");
+  Layout L;
+  if (!make_layout(n, o, L)) return fail(SP2_ERR_INVALID_ARG, "matrix order out of range");
+  if (sp2_status s = check_ws(L, workspace, ws_bytes)) return s;
+  HostMirror* hm;
+  if (sp2_status s = host_mirror(&hm)) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  WS w;
+  bind(w, workspace, L);
+  const int prec = o.precision;
+  const bool trivial = n_occ == 0 || n_occ == n;
+  const bool vec_ok = (ld % 4 == 0) && (reinterpret_cast<uintptr_t>(P) % 16 == 0);
+  sp2_status s;
+
+  {
+    Meta none{n, L.np, prec, o.refine, 0, 0, 0, o.max_iter, kMetaMagic};
+    k_write_meta<<<1, 1, 0, st>>>(w.meta, none);
+    LAUNCH_TRY();
+  }
+  // Spectral bounds (FP64 Gershgorin discs) and control reset.
+  k_gershgorin_rows<<<L.gersh_blocks, kRowThreads, 0, st>>>(H, n, ld, w.gersh);
+  LAUNCH_TRY();
+  k_bounds_final<<<1, 256, 0, st>>>(w.gersh, L.gersh_blocks, w.ctrl, trivial ? 1 : 0);
+  LAUNCH_TRY();
+
+  int n_iter = 0;
+  bool n_iter_even_for_refine = false;
+  if (trivial) {
+    k_fill_diag<<<ew_grid(n * n), kEwThreads, 0, st>>>(P, n, ld, n_occ == 0 ? 0.0f : 1.0f);
+    LAUNCH_TRY();
+    if ((s = read_back(w, hm, false, st))) return s;
+    if (hm->ctrl[0].nonfinite) return fail(SP2_ERR_NONFINITE, "H holds NaN or Inf");
+    if (o.checkpoint_every > 0) {
+      Meta m{n, L.np, prec, o.refine, o.checkpoint_every, 0, 2, o.max_iter, kMetaMagic};
+      k_write_meta<<<1, 1, 0, st>>>(w.meta, m);
+      LAUNCH_TRY();
+    }
+    if (info) {
+      memset(info, 0, sizeof(*info));
+      info->converged = 1;
+      info->eps_min = hm->ctrl[0].eps_min;
+      info->eps_max = hm->ctrl[0].eps_max;
+      info->trace = static_cast<double>(n_occ);
+    }
+    return SP2_OK;
+  }
+
+  // Input layer S_0 with its split planes (pair 0) and trace partials.
+  k_input_layer<<<L.init_blocks, kEwThreads, 0, st>>>(H, n, ld, L.np, w.ctrl, w.slotf(0), w.hi(0),
+                                                      w.lo(0), split_code_of(prec), w.parts[0]);
+  LAUNCH_TRY();
+  if (o.checkpoint_every > 0) HIP_TRY(hipMemcpyAsync(w.tape(0), w.slotf(0), L.slot_bytes, hipMemcpyDeviceToDevice, st));
+
+  LayerTimer timer;
+  if (o.flags & SP2_FLAG_TIME_LAYERS) HIP_TRY(timer.init(o.max_iter));
+  const int refine_ev = o.max_iter;   // event pair index of the refinement
+
+  // Layer loop in chunks; poll the stop flag of chunk c while chunk c+1 runs.
+  hipEvent_t ev[2];
+  HIP_TRY(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+  int launched = 0, chunk = 0;
+  bool stopped = false;
+  sp2_status err = SP2_OK;
+  while (!stopped && launched < o.max_iter && err == SP2_OK) {
+    const int end = std::min(o.max_iter, launched + kChunk);
+    for (int k = launched; k < end && err == SP2_OK; ++k) {
+      const float* src = s_f32(w, prec, k);
+      float* dst = s_f32(w, prec, k + 1);
+      if (timer.mark(2 * k, st) != hipSuccess) err = fail(SP2_ERR_DEVICE, "event record failed");
+      if (err == SP2_OK)
+        err = launch_layer(w, prec, k, 1, src, dst, k & 1, (k + 1) & 1, w.parts[(k + 1) & 1], st, &o,
+                           n_occ);
+      if (err == SP2_OK && timer.mark(2 * k + 1, st) != hipSuccess)
+        err = fail(SP2_ERR_DEVICE, "event record failed");
+      if (err == SP2_OK && o.checkpoint_every > 0 && (k + 1) % o.checkpoint_every == 0) {
+        hipError_t e = hipMemcpyAsync(w.tape((k + 1) / o.checkpoint_every), dst, L.slot_bytes,
+                                      hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) err = fail(SP2_ERR_DEVICE, "tape copy: %s", hipGetErrorString(e));
+      }
+    }
+    launched = end;
+    if (err != SP2_OK) break;
+    const int slot = chunk & 1;
+    hipError_t e = hipMemcpyAsync(&hm->ctrl[slot], w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipEventRecord(ev[slot], st);
+    if (e != hipSuccess) { err = fail(SP2_ERR_DEVICE, "poll: %s", hipGetErrorString(e)); break; }
+    if (chunk > 0) {
+      e = hipEventSynchronize(ev[slot ^ 1]);
+      if (e != hipSuccess) { err = fail(SP2_ERR_DEVICE, "poll sync: %s", hipGetErrorString(e)); break; }
+      if (hm->ctrl[slot ^ 1].stopped) stopped = true;
+    }
+    ++chunk;
+  }
+  if (err == SP2_OK) {
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) err = fail(SP2_ERR_DEVICE, "sync: %s", hipGetErrorString(e));
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  if (err != SP2_OK) return err;
+
+  // The freshest control block: the loop has drained, read it again.
+  if ((s = read_back(w, hm, false, st))) return s;
+  if (hm->ctrl[0].nonfinite) return fail(SP2_ERR_NONFINITE, "H holds NaN or Inf");
+  if (!hm->ctrl[0].stopped) {
+    k_finish_loop<<<1, 256, 0, st>>>(w.ctrl, w.hist, w.parts[o.max_iter & 1],
+                                     nparts_of_layer(L, prec, o.max_iter), o.max_iter, o.tol,
+                                     o.stop_rule, o.stall_gate);
+    LAUNCH_TRY();
+    n_iter = o.max_iter;
+  } else {
+    n_iter = hm->ctrl[0].n_iter;
+  }
+  const float* S = s_f32(w, prec, n_iter);
+  if (o.refine == SP2_REFINE_SPLIT && prec == SP2_FP32 && (n_iter & 1)) {
+    // S sits in slot 1, which the split refinement uses for hi/lo planes.
+    HIP_TRY(hipMemcpyAsync(w.slotf(0), S, L.slot_bytes, hipMemcpyDeviceToDevice, st));
+    S = w.slotf(0);
+    n_iter_even_for_refine = true;
+  }
+
+  if (o.refine != SP2_REFINE_NONE && !hm->ctrl[0].degenerate) {
+    HIP_TRY(timer.mark(2 * refine_ev, st));
+    if ((s = refine(w, prec, o.refine, n_iter_even_for_refine ? 0 : n_iter, S, P, ld, n, vec_ok, st)))
+      return s;
+    HIP_TRY(timer.mark(2 * refine_ev + 1, st));
+    k_sum_parts<<<1, 256, 0, st>>>(w.ctrl, w.parts[0],
+                                   o.refine == SP2_REFINE_FP32 ? L.ntiles_f32 : L.ntiles_split);
+    LAUNCH_TRY();
+  } else {
+    k_copy_scaled<<<ew_grid(n * n), kEwThreads, 0, st>>>(S, L.np, P, ld, n, n, 1.0f, 0);
+    LAUNCH_TRY();
+  }
+  if (o.checkpoint_every > 0) {
+    Meta m{n, L.np, prec, o.refine, o.checkpoint_every, n_iter, hm->ctrl[0].degenerate ? 0 : 1,
+           o.max_iter, kMetaMagic};
+    k_write_meta<<<1, 1, 0, st>>>(w.meta, m);
+    LAUNCH_TRY();
+  }
+  if ((s = read_back(w, hm, true, st))) return s;
+  const Ctrl& c = hm->ctrl[0];
+  const bool refined = o.refine != SP2_REFINE_NONE && !c.degenerate;
+  const int32_t nit = c.n_iter;
+  const double t1 = refined ? c.final_t1 : hm->hist.t1[nit];
+  const double t2 = refined ? c.final_t2 : hm->hist.t2[nit];
+  const bool converged = c.converged && !c.degenerate;
+  if (info) {
+    info->n_iter = nit;
+    info->converged = converged ? 1 : 0;
+    info->eps_min = c.eps_min;
+    info->eps_max = c.eps_max;
+    info->trace = t1;
+    info->idem_err = fabs(t1 - t2);
+    info->reserved = 0;
+    info->layer_ms = timer.on ? timer.sum(0, nit) : 0.0;
+    info->refine_ms = (timer.on && refined) ? timer.sum(refine_ev, refine_ev + 1) : 0.0;
+  }
+  for (int k = 0; k < std::min<int32_t>(nit, branches_cap); ++k)
+    branches[k] = hm->hist.branch[k] > 0 ? 1 : 0;
+  sp2_status ret = SP2_OK;
+  if (c.degenerate) ret = fail(SP2_ERR_NOT_CONVERGED, "degenerate spectrum (eps_max == eps_min): no gap");
+  else if (!converged) ret = fail(SP2_ERR_NOT_CONVERGED, "stop test not met within %d layers", o.max_iter);
+  if (info) info->status = ret;
+  return ret;
+}
+
+sp2_status sp2_density(const float* H, int64_t n, int64_t n_occ, double tol, float* P,
+                       int32_t* n_iter, uint8_t* branches, int32_t branches_cap, void* workspace,
+                       size_t ws_bytes, void* stream) {
+  sp2_options o;
+  sp2_default_options(&o);
+  o.tol = tol;
+  sp2_info info;
+  const sp2_status s = sp2_density_ex(H, n, n, n_occ, &o, P, &info, branches, branches_cap,
+                                      workspace, ws_bytes, stream);
+  if (n_iter) *n_iter = (s == SP2_OK || s == SP2_ERR_NOT_CONVERGED) ? info.n_iter : 0;
+  return s;
+}
+
+sp2_status sp2_bounds(const float* H, int64_t n, int64_t ld, double* eps_min, double* eps_max,
+                      void* workspace, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  if (!H || !eps_min || !eps_max) return fail(SP2_ERR_INVALID_ARG, "NULL argument");
+  if (n <= 0 || ld < n) return fail(SP2_ERR_INVALID_ARG, "need n > 0 and ld >= n");
+  sp2_options o;
+  sp2_default_options(&o);
+  Layout L;
+  if (!make_layout(n, o, L)) return fail(SP2_ERR_INVALID_ARG, "matrix order out of range");
+  // only the header part of the workspace is used
+  if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 || ws_bytes < L.off_slot0)
+    return fail(SP2_ERR_WORKSPACE, "workspace missing, misaligned or too small");
+  HostMirror* hm;
+  if (sp2_status s = host_mirror(&hm)) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  WS w;
+  bind(w, workspace, L);
+  k_gershgorin_rows<<<L.gersh_blocks, kRowThreads, 0, st>>>(H, n, ld, w.gersh);
+  LAUNCH_TRY();
+  k_bounds_final<<<1, 256, 0, st>>>(w.gersh, L.gersh_blocks, w.ctrl, 1);
+  LAUNCH_TRY();
+  if (sp2_status s = read_back(w, hm, false, st)) return s;
+  *eps_min = hm->ctrl[0].eps_min;
+  *eps_max = hm->ctrl[0].eps_max;
+  if (hm->ctrl[0].nonfinite) return fail(SP2_ERR_NONFINITE, "H holds NaN or Inf");
+  return SP2_OK;
+}
+
+sp2_status sp2_split(const float* X, int64_t n, int64_t ld, int32_t precision, uint16_t* hi,
+                     uint16_t* lo, void* stream) {
+  g_err.clear();
+  if (!X || !hi || !lo) return fail(SP2_ERR_INVALID_ARG, "NULL argument");
+  if (n <= 0 || ld < n) return fail(SP2_ERR_INVALID_ARG, "need n > 0 and ld >= n");
+  const int code = split_code_of(precision);
+  if (!code) return fail(SP2_ERR_INVALID_ARG, "precision has no 16-bit split");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  k_split<<<ew_grid(n * n), kEwThreads, 0, st>>>(X, n, ld, n, n, hi, lo, code);
+  LAUNCH_TRY();
+  return SP2_OK;
+}
+
+sp2_status sp2_layer(const float* X, int64_t n, int64_t ld, int32_t precision, int32_t sign,
+                     float* Y, void* workspace, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  if (!X || !Y || X == Y) return fail(SP2_ERR_INVALID_ARG, "X and Y must be distinct non-NULL buffers");
+  if (n <= 0 || ld < n) return fail(SP2_ERR_INVALID_ARG, "need n > 0 and ld >= n");
+  if (sign != 1 && sign != -1) return fail(SP2_ERR_INVALID_ARG, "sign must be +1 or -1");
+  sp2_options o;
+  sp2_default_options(&o);
+  o.precision = precision;
+  o.refine = SP2_REFINE_NONE;
+  if (!options_ok(o)) return fail(SP2_ERR_INVALID_ARG, "invalid precision");
+  Layout L;
+  if (!make_layout(n, o, L)) return fail(SP2_ERR_INVALID_ARG, "matrix order out of range");
+  if (sp2_status s = check_ws(L, workspace, ws_bytes)) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  WS w;
+  bind(w, workspace, L);
+  float* Xp = w.slotf(0);
+  k_copy_scaled<<<ew_grid(L.np * L.np), kEwThreads, 0, st>>>(X, ld, Xp, L.np, n, L.np, 1.0f, 0);
+  LAUNCH_TRY();
+  Epi e = make_epi(L);
+  e.c = Xp;
+  e.out = Y;
+  e.ld_out = ld;
+  e.n_valid = static_cast<int>(n);
+  e.vec_ok = (ld % 4 == 0) && (reinterpret_cast<uintptr_t>(Y) % 16 == 0);
+  e.alpha = sign > 0 ? 1.0f : -1.0f;
+  e.beta = sign > 0 ? 0.0f : 2.0f;
+  const Decide d0 = make_decide(w, 0, 0);
+  sp2_status s;
+  if (precision == SP2_FP32) {
+    const float* A[1] = {Xp};
+    s = launch_f32(w, 1, A, A, e, d0, st);
+  } else {
+    k_split<<<ew_grid(L.np * L.np), kEwThreads, 0, st>>>(Xp, L.np, L.np, L.np, L.np, w.hi(0), w.lo(0),
+                                                         split_code_of(precision));
+    LAUNCH_TRY();
+    s = launch_split(w, precision, w.hi(0), w.lo(0), w.hi(0), w.lo(0), e, d0, st);
+  }
+  if (s) return s;
+  HIP_TRY(hipStreamSynchronize(st));
+  return SP2_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Load the tape description, control block and history written by the last
+// forward call on this workspace.
+sp2_status open_tape(void* workspace, size_t ws_bytes, hipStream_t st, WS& w, HostMirror*& hm,
+                     sp2_options& o) {
+  if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256)
+    return fail(SP2_ERR_WORKSPACE, "workspace missing or misaligned");
+  sp2_options d;
+  sp2_default_options(&d);
+  Layout L0;
+  make_layout(256, d, L0);   // header offsets do not depend on n
+  if (ws_bytes < L0.off_parts0) return fail(SP2_ERR_WORKSPACE, "workspace too small");
+  if (sp2_status s = host_mirror(&hm)) return s;
+  HIP_TRY(hipMemcpyAsync(&hm->meta, static_cast<char*>(workspace) + L0.off_meta, sizeof(Meta),
+                         hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const Meta m = hm->meta;
+  if (m.magic != kMetaMagic || m.valid == 0 || m.every <= 0)
+    return fail(SP2_ERR_TAPE, "no derivative tape: run sp2_density_ex with checkpoint_every > 0 first");
+  o = d;
+  o.precision = m.precision;
+  o.refine = m.refine;
+  o.checkpoint_every = m.every;
+  o.max_iter = m.max_iter;
+  Layout L;
+  if (!make_layout(m.n, o, L)) return fail(SP2_ERR_TAPE, "corrupt tape description");
+  if (sp2_status s = check_ws(L, workspace, ws_bytes)) return s;
+  bind(w, workspace, L);
+  return read_back(w, hm, true, st);
+}
+
+// Symmetric two-operand product  out = alpha (X Y + Y X) + beta C  or the
+// branch-coefficient form (mode 2, layer n) of one derivative layer.
+sp2_status sym_pair(const WS& w, const float* X, const float* Y, const float* C, float* out,
+                    float alpha, float beta, int mode, int layer, hipStream_t st) {
+  const float* A[2] = {X, Y};
+  const float* B[2] = {Y, X};
+  Epi e = make_epi(w.L);
+  e.c = C;
+  e.out = out;
+  e.alpha = alpha;
+  e.beta = beta;
+  return launch_f32(w, 2, A, B, e, make_decide(w, mode, layer), st);
+}
+
+// Derivative of the McWeeny step at S in direction D (JVP) or its adjoint
+// (identical map): 3(SD + DS) - 2(S^2 D + S D S + D S^2)
+//   = 3M - (S M + M S) - (S^2 D + D S^2)  with  M = SD + DS.
+sp2_status refine_derivative(const WS& w, const float* S, const float* D, float* out, int64_t ld,
+                             int64_t n, bool vec_ok, hipStream_t st) {
+  float* M = w.work(2);
+  float* S2 = w.work(3);
+  sp2_status s;
+  if ((s = sym_pair(w, S, D, nullptr, M, 1.0f, 0.0f, 0, 0, st))) return s;
+  {
+    const float* A[1] = {S};
+    Epi e = make_epi(w.L);
+    e.out = S2;
+    if ((s = launch_f32(w, 1, A, A, e, make_decide(w, 0, 0), st))) return s;
+  }
+  const float* A[4] = {S, M, S2, D};
+  const float* B[4] = {M, S, D, S2};
+  Epi e = make_epi(w.L);
+  e.c = M;
+  e.out = out;
+  e.ld_out = ld;
+  e.n_valid = static_cast<int>(n);
+  e.vec_ok = vec_ok;
+  e.alpha = -1.0f;
+  e.beta = 3.0f;
+  return launch_f32(w, 4, A, B, e, make_decide(w, 0, 0), st);
+}
+
+// Bring checkpoint `slot` into the forward buffers as iterate S_c (FP32 at
+// dst, hi/lo planes in pair 0 for the split precisions).
+sp2_status load_checkpoint(const WS& w, int prec, int slot, float* dst, hipStream_t st) {
+  HIP_TRY(hipMemcpyAsync(dst, w.tape(slot), w.L.slot_bytes, hipMemcpyDeviceToDevice, st));
+  if (prec != SP2_FP32) {
+    k_split<<<ew_grid(w.L.np * w.L.np), kEwThreads, 0, st>>>(dst, w.L.np, w.L.np, w.L.np, w.L.np,
+                                                              w.hi(0), w.lo(0), split_code_of(prec));
+    LAUNCH_TRY();
+  }
+  return SP2_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sp2_status sp2_jvp(void* workspace, size_t ws_bytes, const float* H1, int64_t ld, float* P1,
+                   void* stream) {
+  g_err.clear();
+  if (!H1 || !P1) return fail(SP2_ERR_INVALID_ARG, "NULL argument");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  WS w;
+  HostMirror* hm;
+  sp2_options o;
+  if (sp2_status s = open_tape(workspace, ws_bytes, st, w, hm, o)) return s;
+  const Layout& L = w.L;
+  const int64_t n = L.n;
+  if (ld < n) return fail(SP2_ERR_INVALID_ARG, "ld < n");
+  const bool vec_ok = (ld % 4 == 0) && (reinterpret_cast<uintptr_t>(P1) % 16 == 0);
+  if (hm->meta.valid == 2) {   // n_occ in {0, n}: P does not depend on H
+    k_fill_diag<<<ew_grid(n * n), kEwThreads, 0, st>>>(P1, n, ld, 0.0f);
+    LAUNCH_TRY();
+    HIP_TRY(hipStreamSynchronize(st));
+    return SP2_OK;
+  }
+  const int prec = o.precision;
+  const int nl = hm->meta.n_iter;
+  const float inv = static_cast<float>(hm->ctrl[0].inv_range);
+  // dS_0 = -H1 / (eps_max - eps_min)  (H1 symmetrised)
+  k_copy_scaled<<<ew_grid(L.np * L.np), kEwThreads, 0, st>>>(H1, ld, w.work(0), L.np, n, L.np, -inv, 1);
+  LAUNCH_TRY();
+  sp2_status s;
+  if ((s = load_checkpoint(w, prec, 0, s_f32(w, prec, 0), st))) return s;
+  for (int k = 0; k < nl; ++k) {
+    const float* S = s_f32(w, prec, k);
+    if ((s = sym_pair(w, S, w.work(k & 1), w.work(k & 1), w.work((k + 1) & 1), 1.0f, 0.0f, 2, k, st)))
+      return s;
+    if (k + 1 < nl || o.refine != SP2_REFINE_NONE)
+      if ((s = launch_layer(w, prec, k, 2, S, s_f32(w, prec, k + 1), k & 1, (k + 1) & 1, nullptr, st,
+                            &o, 0)))
+        return s;
+  }
+  const float* Y = w.work(nl & 1);
+  if (o.refine != SP2_REFINE_NONE) {
+    if ((s = refine_derivative(w, s_f32(w, prec, nl), Y, P1, ld, n, vec_ok, st))) return s;
+  } else {
+    k_copy_scaled<<<ew_grid(n * n), kEwThreads, 0, st>>>(Y, L.np, P1, ld, n, n, 1.0f, 0);
+    LAUNCH_TRY();
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  return SP2_OK;
+}
+
+sp2_status sp2_vjp(void* workspace, size_t ws_bytes, const float* W, int64_t ld, float* G,
+                   void* stream) {
+  g_err.clear();
+  if (!W || !G) return fail(SP2_ERR_INVALID_ARG, "NULL argument");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  WS w;
+  HostMirror* hm;
+  sp2_options o;
+  if (sp2_status s = open_tape(workspace, ws_bytes, st, w, hm, o)) return s;
+  const Layout& L = w.L;
+  const int64_t n = L.n;
+  if (ld < n) return fail(SP2_ERR_INVALID_ARG, "ld < n");
+  if (hm->meta.valid == 2) {
+    k_fill_diag<<<ew_grid(n * n), kEwThreads, 0, st>>>(G, n, ld, 0.0f);
+    LAUNCH_TRY();
+    HIP_TRY(hipStreamSynchronize(st));
+    return SP2_OK;
+  }
+  const int prec = o.precision;
+  const int nl = hm->meta.n_iter;
+  const int k = L.every;
+  const float inv = static_cast<float>(hm->ctrl[0].inv_range);
+  sp2_status s;
+  // G_L = sym(W)
+  k_copy_scaled<<<ew_grid(L.np * L.np), kEwThreads, 0, st>>>(W, ld, w.work(0), L.np, n, L.np, 1.0f, 1);
+  LAUNCH_TRY();
+  int cur = 0;
+  if (o.refine != SP2_REFINE_NONE) {
+    // recompute S_L from its last checkpoint, then apply the refinement adjoint
+    const int c = (nl / k) * k;
+    if ((s = load_checkpoint(w, prec, c / k, s_f32(w, prec, c), st))) return s;
+    for (int m = c; m < nl; ++m)
+      if ((s = launch_layer(w, prec, m, 2, s_f32(w, prec, m), s_f32(w, prec, m + 1), (m - c) & 1,
+                            (m - c + 1) & 1, nullptr, st, &o, 0)))
+        return s;
+    if ((s = refine_derivative(w, s_f32(w, prec, nl), w.work(0), w.work(1), L.np, L.np, true, st)))
+      return s;
+    cur = 1;
+  }
+  const int nseg = (nl + k - 1) / k;
+  for (int j = nseg - 1; j >= 0; --j) {
+    const int c = j * k, e = std::min(c + k, nl);
+    if ((s = load_checkpoint(w, prec, j, w.seg(0), st))) return s;
+    for (int m = 1; m < e - c; ++m)
+      if ((s = launch_layer(w, prec, c + m - 1, 2, w.seg(m - 1), w.seg(m), (m - 1) & 1, m & 1, nullptr,
+                            st, &o, 0)))
+        return s;
+    for (int nn = e - 1; nn >= c; --nn) {
+      if ((s = sym_pair(w, w.seg(nn - c), w.work(cur), w.work(cur), w.work(1 - cur), 1.0f, 0.0f, 2, nn,
+                        st)))
+        return s;
+      cur = 1 - cur;
+    }
+  }
+  // dTr(WP)/dH = -G_0 / (eps_max - eps_min)
+  k_copy_scaled<<<ew_grid(n * n), kEwThreads, 0, st>>>(w.work(cur), L.np, G, ld, n, n, -inv, 0);
+  LAUNCH_TRY();
+  HIP_TRY(hipStreamSynchronize(st));
+  return SP2_OK;
+}
+
+}  // extern "C"

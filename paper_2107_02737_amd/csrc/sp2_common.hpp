@@ -1,0 +1,207 @@
+// Shared device-side definitions of the gfx950 DNN-SP2 kernels: vector
+// types, the device control block, reductions and the 16-bit split.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sp2.h"
+
+namespace sp2 {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(8))) _Float16 f16x8;
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+typedef __attribute__((ext_vector_type(4))) uint32_t u32x4;
+typedef __attribute__((ext_vector_type(2))) uint32_t u32x2;
+
+constexpr int kWave = 64;
+constexpr int kMaxIter = SP2_MAX_ITER;
+constexpr int kFp16ScaleLog2 = 14;   // 2^14 X keeps the FP16 residual normal
+
+// Device control block: one per workspace.  Written by the bound pass, the
+// layer kernels (work-group 0 only) and the one-work-group control kernels.
+struct Ctrl {
+  double eps_min, eps_max;   // Gershgorin bounds of H
+  double inv_range;          // 1 / (eps_max - eps_min)
+  double final_t1, final_t2; // traces of the returned P
+  int32_t nonfinite;         // H holds NaN/Inf
+  int32_t degenerate;        // eps_max == eps_min
+  int32_t stopped;           // stop test passed (or nothing to iterate)
+  int32_t n_iter;            // layers applied when stopped
+  int32_t converged;
+  int32_t pad[7];
+};
+
+// Per-layer history: traces of every examined approximation S_k and the
+// sign of every applied layer (+1: S^2, -1: 2S - S^2).
+struct Hist {
+  double t1[kMaxIter + 1];
+  double t2[kMaxIter + 1];
+  double err[kMaxIter + 1];
+  int32_t branch[kMaxIter];
+};
+
+// Parameters of the trace-driven stop / branch decision (Section II.D-E).
+struct Decide {
+  Ctrl* ctrl;
+  Hist* hist;
+  const double* parts_in;   // (Tr, ||.||_F^2) partial pairs of S_n
+  int nparts_in;
+  int layer;                // n: this launch turns S_n into S_{n+1}
+  int mode;                 // 0: fixed coefficients, 1: decide, 2: replay hist->branch
+  double n_occ, tol, stall_gate;
+  int stop_rule;
+};
+
+// ---------------------------------------------------------------------------
+// Reductions (fixed order, so every work-group and every run agrees bitwise)
+// ---------------------------------------------------------------------------
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+__device__ inline double wave_min(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = fmin(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+
+__device__ inline double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+
+// Block-wide sum of two doubles; every thread receives the totals.  `red`
+// must hold 2 * (blockDim / 64) doubles of LDS.
+template <int NT>
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* red) {
+  constexpr int NW = NT / kWave;
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int w = threadIdx.x / kWave;
+  __syncthreads();
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    red[w] = a;
+    red[NW + w] = b;
+  }
+  __syncthreads();
+  double sa = 0.0, sb = 0.0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    sa += red[i];
+    sb += red[NW + i];
+  }
+  a = sa;
+  b = sb;
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Branch and stop decision, taken redundantly (and identically) by every
+// work-group of a layer launch before it multiplies.  Returns +1 (S^2), -1
+// (2S - S^2), or 0 when the network has stopped.
+// ---------------------------------------------------------------------------
+
+template <int NT>
+__device__ __forceinline__ int decide_layer(const Decide& d, double* red) {
+  if (d.mode == 2) return d.hist->branch[d.layer];
+  if (d.mode != 1) return 1;
+  // One read of the stop flag per work-group, shared through LDS, so that
+  // all of its waves take the same exit.
+  __shared__ int s_stopped;
+  if (threadIdx.x == 0) s_stopped = __atomic_load_n(&d.ctrl->stopped, __ATOMIC_RELAXED);
+  double t1 = 0.0, t2 = 0.0;
+  for (int i = threadIdx.x; i < d.nparts_in; i += NT) {
+    t1 += d.parts_in[2 * i];
+    t2 += d.parts_in[2 * i + 1];
+  }
+  block_sum2<NT>(t1, t2, red);   // its barriers publish s_stopped
+  if (s_stopped) return 0;
+  const int n = d.layer;
+  const double e = fabs(t1 - t2);
+  bool stop = e < d.tol;
+  if (!stop && d.stop_rule == 1 && n >= 2 && e < d.stall_gate && e >= d.hist->err[n - 2])
+    stop = true;
+  // Trace-closest sign: Tr(S^2) = t2 versus Tr(2S - S^2) = 2 t1 - t2; ties take S^2.
+  const int sign = (fabs(t2 - d.n_occ) <= fabs(2.0 * t1 - t2 - d.n_occ)) ? 1 : -1;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    d.hist->t1[n] = t1;
+    d.hist->t2[n] = t2;
+    d.hist->err[n] = e;
+    if (stop) {
+      d.ctrl->n_iter = n;
+      d.ctrl->converged = 1;
+      __atomic_store_n(&d.ctrl->stopped, 1, __ATOMIC_RELAXED);
+    } else {
+      d.hist->branch[n] = sign;
+    }
+  }
+  return stop ? 0 : sign;
+}
+
+// ---------------------------------------------------------------------------
+// 16-bit dual representation X = X0 + X1 (Eq. 20-21), round to nearest even.
+// ---------------------------------------------------------------------------
+
+__device__ inline void split_bf16(float x, uint16_t& hi, uint16_t& lo) {
+  const __bf16 h = static_cast<__bf16>(x);
+  const __bf16 l = static_cast<__bf16>(x - static_cast<float>(h));
+  hi = __builtin_bit_cast(uint16_t, h);
+  lo = __builtin_bit_cast(uint16_t, l);
+}
+
+__device__ inline void split_fp16s(float x, uint16_t& hi, uint16_t& lo) {
+  // ldexp keeps the sign of zero (a contracted multiply-add with +0 would not)
+  const float xs = ldexpf(x, kFp16ScaleLog2);
+  const _Float16 h = static_cast<_Float16>(xs);
+  const _Float16 l = static_cast<_Float16>(xs - static_cast<float>(h));
+  hi = __builtin_bit_cast(uint16_t, h);
+  lo = __builtin_bit_cast(uint16_t, l);
+}
+
+// ---------------------------------------------------------------------------
+// Upper-triangle tile schedule.  Work-group b runs on XCD (b mod 8); the
+// remap gives each XCD a contiguous run of logical tiles, and the logical
+// order walks bands of `band` tile-rows column by column so that tiles that
+// run together on one XCD share row panels in its L2.
+// ---------------------------------------------------------------------------
+
+__device__ inline int xcd_remap(int b, int ntiles) {
+  const int xcd = b & 7, local = b >> 3;
+  const int per = ntiles >> 3, rem = ntiles & 7;
+  return xcd * per + (xcd < rem ? xcd : rem) + local;
+}
+
+__device__ __forceinline__ void tile_of(int logical, int nb, int band, int& ti, int& tj) {
+  int r0 = 0;
+  for (;;) {
+    if (r0 >= nb) {   // out of range: cannot happen with grid == tile count
+      ti = tj = 0;
+      return;
+    }
+    const int r1 = min(r0 + band, nb) - 1;
+    int count = 0;
+    for (int j = r0; j < nb; ++j) count += min(r1, j) - r0 + 1;
+    if (logical < count) {
+      for (int j = r0; j < nb; ++j) {
+        const int c = min(r1, j) - r0 + 1;
+        if (logical < c) {
+          ti = r0 + logical;
+          tj = j;
+          return;
+        }
+        logical -= c;
+      }
+    }
+    logical -= count;
+    r0 += band;
+  }
+}
+
+}  // namespace sp2

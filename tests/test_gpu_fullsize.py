@@ -1,0 +1,59 @@
+"""Full-size parity at the benchmark's workload (water box, N = 6144,
+n_occ = 4096) in the launch configuration bench.py times: stored samples of
+the exact density matrix (written by tests/golden/make_golden.py from the
+FP64 oracle) and properties that hold at any size."""
+
+import math
+import os
+
+import numpy as np
+import pytest
+
+from gpu_util import banner
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "water_m1024_seed0.npz")
+
+# 3x the FP32-storage emulation of a 256-molecule box of the same model
+# (the error is set by the mapped gap, which the larger box shares).
+TOL = {"bf16x3": 5e-5, "fp16x3": 3e-6, "fp32": 3e-6}
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+
+    import paper_2107_02737_amd as pk
+    from workloads import water_box_hamiltonian
+    gold = np.load(GOLDEN)
+    h32 = water_box_hamiltonian(int(gold["molecules"]), seed=int(gold["seed"])).astype(np.float32)
+    assert abs(float(h32.astype(np.float64).sum()) - float(gold["h_sum"])) < 1e-6 * abs(float(gold["h_sum"]))
+    pk.load_library()
+    return pk, gold, torch.from_numpy(h32).to("cuda")
+
+
+@pytest.mark.parametrize("precision", ["bf16x3", "fp16x3", "fp32"])
+def test_water_6144(setup, precision):
+    import torch
+    pk, gold, H = setup
+    n, n_occ = int(gold["n"]), int(gold["n_occ"])
+    banner(f"water N={n} {precision} refine=fp32")
+    P, info = pk.density(H, n_occ, precision=precision, refine="fp32", return_info=True)
+    assert info["converged"] == 1
+    assert info["eps_min"] == pytest.approx(float(gold["eps_min"]), rel=1e-12)
+    assert info["eps_max"] == pytest.approx(float(gold["eps_max"]), rel=1e-12)
+    pi = torch.from_numpy(np.asarray(gold["pair_i"], dtype=np.int64)).cuda()
+    pj = torch.from_numpy(np.asarray(gold["pair_j"], dtype=np.int64)).cuda()
+    d = P[pi, pj].double().cpu().numpy() - gold["pair_val"]
+    est = math.sqrt(n * float(np.mean(d * d)))
+    diag = torch.diagonal(P).double().cpu().numpy() - gold["diag"]
+    pp = P @ P
+    idem = float(torch.linalg.norm((pp - P).double()).item()) / math.sqrt(n)
+    print(f"  n_iter={info['n_iter']} est ||P-P_ref||_F/sqrt(N)={est:.3e} "
+          f"diag rms={np.sqrt(np.mean(diag ** 2)):.2e} idem={idem:.2e} "
+          f"trace_err={abs(info['trace'] - n_occ):.2e}", flush=True)
+    assert torch.equal(P, P.T)
+    assert est <= TOL[precision]
+    assert abs(info["trace"] - n_occ) < 0.05
+    assert idem < 1e-4
