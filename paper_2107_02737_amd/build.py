@@ -37,6 +37,20 @@ def compile_command(out=LIB_PATH):
     ]
 
 
+def _hot_loop_scratch(text, name):
+    """Scratch (spill) instructions between the kernel's first and last MFMA
+    instruction, i.e. inside its matrix-core loop.  -1 if it has no MFMA."""
+    start = text.find("\n" + name + ":")
+    if start < 0:
+        return -1
+    end = text.find(".Lfunc_end", start)
+    lines = text[start:end].splitlines()
+    idx = [i for i, line in enumerate(lines) if "v_mfma" in line]
+    if not idx:
+        return -1
+    return sum("scratch_" in line for line in lines[idx[0]:idx[-1] + 1])
+
+
 def kernel_resources():
     """Compile the device code to gfx950 assembly and return, per kernel, its
     scratch (private segment) bytes, VGPR count and VGPR/SGPR spill counts."""
@@ -57,7 +71,8 @@ def kernel_resources():
             continue
         name = re.search(r"\.name:\s+(\S+)", block).group(1)
         field = lambda k: int(re.search(r"\." + k + r":\s+(\d+)", block).group(1))  # noqa: E731
-        kernels[name] = {"private_segment_fixed_size": field("private_segment_fixed_size"),
+        kernels[name] = {"hot_loop_scratch": _hot_loop_scratch(text, name),
+                         "private_segment_fixed_size": field("private_segment_fixed_size"),
                          "vgpr_count": field("vgpr_count"),
                          "vgpr_spill_count": field("vgpr_spill_count"),
                          "sgpr_spill_count": field("sgpr_spill_count"),

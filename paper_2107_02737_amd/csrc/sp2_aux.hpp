@@ -151,10 +151,11 @@ __global__ __launch_bounds__(kEwThreads) void k_input_layer(const float* __restr
         else
           split_fp16s(v[c], h4[c], l4[c]);
       }
-      *reinterpret_cast<uint2*>(hi + i * np + j0) =
-          uint2{uint32_t(h4[0]) | (uint32_t(h4[1]) << 16), uint32_t(h4[2]) | (uint32_t(h4[3]) << 16)};
-      *reinterpret_cast<uint2*>(lo + i * np + j0) =
-          uint2{uint32_t(l4[0]) | (uint32_t(l4[1]) << 16), uint32_t(l4[2]) | (uint32_t(l4[3]) << 16)};
+      const int64_t o = plane_off(i, j0, np);   // 4 consecutive columns stay contiguous
+      *reinterpret_cast<u32x2*>(hi + o) =
+          u32x2{uint32_t(h4[0]) | (uint32_t(h4[1]) << 16), uint32_t(h4[2]) | (uint32_t(h4[3]) << 16)};
+      *reinterpret_cast<u32x2*>(lo + o) =
+          u32x2{uint32_t(l4[0]) | (uint32_t(l4[1]) << 16), uint32_t(l4[2]) | (uint32_t(l4[3]) << 16)};
     }
   }
   block_sum2<kEwThreads>(t1, t2, red);
@@ -165,12 +166,14 @@ __global__ __launch_bounds__(kEwThreads) void k_input_layer(const float* __restr
 }
 
 // Dual representation of an n x n FP32 matrix (leading dimension ld) into
-// hi/lo planes with leading dimension ldo; rows/cols in [n, np) are zero.
-// split: 1 bf16, 2 fp16 scaled.
+// hi/lo planes; rows/cols in [n, np) are zero.  split: 1 bf16, 2 fp16
+// scaled.  tiled: planes in the K-tiled layout of an np x np matrix (np a
+// multiple of 256); otherwise row-major with leading dimension ldo.
 __global__ __launch_bounds__(kEwThreads) void k_split(const float* __restrict__ X, int64_t n,
                                                       int64_t ld, int64_t np, int64_t ldo,
                                                       uint16_t* __restrict__ hi,
-                                                      uint16_t* __restrict__ lo, int split) {
+                                                      uint16_t* __restrict__ lo, int split,
+                                                      int tiled) {
   const int64_t total = np * np;
   for (int64_t q = int64_t(blockIdx.x) * kEwThreads + threadIdx.x; q < total;
        q += int64_t(gridDim.x) * kEwThreads) {
@@ -181,8 +184,9 @@ __global__ __launch_bounds__(kEwThreads) void k_split(const float* __restrict__ 
       split_bf16(x, h, l);
     else
       split_fp16s(x, h, l);
-    hi[i * ldo + j] = h;
-    lo[i * ldo + j] = l;
+    const int64_t o = tiled ? plane_off(i, j, np) : i * ldo + j;
+    hi[o] = h;
+    lo[o] = l;
   }
 }
 

@@ -53,6 +53,8 @@ constexpr int kBand = 4;               // tile-rows per band of the tile schedul
 constexpr int kChunk = 8;              // layers launched between stop-flag polls
 constexpr int kInitBlocksMax = 1024;   // partial pairs written by the input layer
 constexpr int kF32Tile = 128;
+constexpr size_t kPartialBytes = size_t(64) << 20;   // split-K tail accumulators
+constexpr int kMaxTailTiles = 1024;                   // arrival counters
 
 int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
@@ -69,10 +71,9 @@ constexpr int64_t kMetaMagic = 0x5350324d45544131LL;
 // Workspace layout (byte offsets), derived from n and the options only.
 struct Layout {
   int64_t n, np;
-  int split_tile;       // 256 or 128 (16-bit split products)
   int nb_split, ntiles_split, nb_f32, ntiles_f32;
   int init_blocks, gersh_blocks, max_parts;
-  size_t off_ctrl, off_hist, off_meta, off_parts0, off_parts1, off_gersh;
+  size_t off_ctrl, off_hist, off_meta, off_parts0, off_parts1, off_gersh, off_counter, off_partial;
   size_t off_slot0;     // first matrix slot
   size_t slot_bytes;
   int nslots, ntape, every;
@@ -81,20 +82,11 @@ struct Layout {
 
 int ntiles_of(int nb) { return nb * (nb + 1) / 2; }
 
-int pick_split_tile(int64_t np) {
-  if (const char* s = getenv("SP2_SPLIT_TILE")) {
-    const int t = atoi(s);
-    if (t == 128 || t == 256) return t;
-  }
-  return np >= 8192 ? 256 : 128;
-}
-
 bool make_layout(int64_t n, const sp2_options& o, Layout& L) {
   if (n <= 0 || n > (int64_t(1) << 20)) return false;
   L.n = n;
   L.np = round_up(n, kPad);
-  L.split_tile = pick_split_tile(L.np);
-  L.nb_split = static_cast<int>(L.np / L.split_tile);
+  L.nb_split = static_cast<int>(L.np / 256);
   L.ntiles_split = ntiles_of(L.nb_split);
   L.nb_f32 = static_cast<int>(L.np / kF32Tile);
   L.ntiles_f32 = ntiles_of(L.nb_f32);
@@ -114,6 +106,8 @@ bool make_layout(int64_t n, const sp2_options& o, Layout& L) {
   L.off_parts0 = take(size_t(L.max_parts) * 16);
   L.off_parts1 = take(size_t(L.max_parts) * 16);
   L.off_gersh = take(size_t(L.gersh_blocks) * 24);
+  L.off_counter = take(size_t(kMaxTailTiles) * 4);
+  L.off_partial = take(kPartialBytes);
   L.slot_bytes = size_t(L.np) * size_t(L.np) * 4;
   L.every = o.checkpoint_every;
   // slots 0-3: S (FP32), two hi/lo plane pairs (or FP32 ping-pong), S^2 for
@@ -134,6 +128,8 @@ struct WS {
   Meta* meta;
   double* parts[2];
   double* gersh;
+  int* counter;
+  float* partial;
   float* slotf(int i) const { return reinterpret_cast<float*>(base + L.off_slot0 + L.slot_bytes * size_t(i)); }
   uint16_t* hi(int pair) const { return reinterpret_cast<uint16_t*>(slotf(1 + pair)); }
   uint16_t* lo(int pair) const { return hi(pair) + L.np * L.np; }
@@ -152,6 +148,52 @@ void bind(WS& w, void* ws, const Layout& L) {
   w.parts[0] = reinterpret_cast<double*>(w.base + L.off_parts0);
   w.parts[1] = reinterpret_cast<double*>(w.base + L.off_parts1);
   w.gersh = reinterpret_cast<double*>(w.base + L.off_gersh);
+  w.counter = reinterpret_cast<int*>(w.base + L.off_counter);
+  w.partial = reinterpret_cast<float*>(w.base + L.off_partial);
+}
+
+// Compute units of the current device (cached per device).
+int device_cus() {
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cache[dev]) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+      cus = 256;
+    cache[dev] = cus;
+  }
+  return cache[dev];
+}
+
+// Split-K tail plan for ntiles tiles on `slots` concurrent work-groups:
+// whole rounds of tiles run unsplit; the tiles of the last partial round are
+// split along K so that their pieces fill the machine.
+Decomp plan_decomp(const WS& w, int nb, int slots, int ksteps, size_t piece_bytes) {
+  Decomp d;
+  memset(&d, 0, sizeof(d));
+  d.nb = nb;
+  d.ntiles = nb * (nb + 1) / 2;
+  d.band = kBand;
+  d.nfull = d.ntiles;
+  d.nsplit = 1;
+  d.partial = w.partial;
+  d.counter = w.counter;
+  if (const char* e = getenv("SP2_NO_SPLITK"))
+    if (atoi(e)) return d;
+  const int r = slots > 0 ? d.ntiles % slots : 0;
+  if (r == 0) return d;
+  int s = std::min(slots / r, ksteps / 4);
+  s = std::min<int64_t>(s, int64_t(kPartialBytes / piece_bytes) / r);
+  if (s < 2 || r > kMaxTailTiles) return d;
+  d.nfull = d.ntiles - r;
+  d.nsplit = s;
+  return d;
+}
+
+__global__ void k_zero_i32(int* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
 }
 
 bool options_ok(const sp2_options& o) {
@@ -223,11 +265,48 @@ Decide make_decide(const WS& w, int mode, int layer) {
   return d;
 }
 
-// Launch a 16-bit split product of planes (a_hi, a_lo) x (b_hi, b_lo)^T.
+// Resident work-groups per CU of a kernel (cached per kernel).
+template <class K>
+int wgs_per_cu(K kernel, int threads) {
+  struct Entry { const void* k; int n; };
+  static Entry cache[32];
+  static int used = 0;
+  const void* key = reinterpret_cast<const void*>(kernel);
+  for (int i = 0; i < used; ++i)
+    if (cache[i].k == key) return cache[i].n;
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, threads, 0) != hipSuccess || n <= 0)
+    n = 1;
+  if (used < 32) cache[used++] = Entry{key, n};
+  return n;
+}
+
+sp2_status reset_counters(const WS& w, hipStream_t st) {
+  k_zero_i32<<<(kMaxTailTiles + 255) / 256, 256, 0, st>>>(w.counter, kMaxTailTiles);
+  LAUNCH_TRY();
+  return SP2_OK;
+}
+
+template <int KIND>
+sp2_status launch_split_t(const WS& w, SplitArgs a, hipStream_t st) {
+  constexpr int NT = 256;
+  constexpr size_t piece = size_t(NT) * 4 * 4 * 16 * 4;   // one 256x256 FP32 accumulator
+  auto kern = k_sym_split<KIND>;
+  const int slots = device_cus() * wgs_per_cu(kern, NT);
+  a.dc = plan_decomp(w, static_cast<int>(w.L.np / 256), slots, static_cast<int>(w.L.np / 32), piece);
+  const int grid = a.dc.nfull + (a.dc.ntiles - a.dc.nfull) * a.dc.nsplit;
+  kern<<<grid, NT, 0, st>>>(a);
+  LAUNCH_TRY();
+  return SP2_OK;
+}
+
+// Launch a 16-bit split product of planes (a_hi, a_lo) x (b_hi, b_lo)^T
+// (planes in the K-tiled layout).
 sp2_status launch_split(const WS& w, int precision, const uint16_t* ah, const uint16_t* al,
                         const uint16_t* bh, const uint16_t* bl, const Epi& epi, const Decide& dec,
                         hipStream_t st) {
   SplitArgs a;
+  memset(&a, 0, sizeof(a));
   a.a_hi = ah;
   a.a_lo = al;
   a.b_hi = bh;
@@ -235,22 +314,10 @@ sp2_status launch_split(const WS& w, int precision, const uint16_t* ah, const ui
   a.epi = epi;
   a.epi.oscale = out_scale_of(precision);
   a.dec = dec;
-  a.band = kBand;
-  a.nb = w.L.nb_split;
-  a.ntiles = w.L.ntiles_split;
-  const dim3 grid(a.ntiles);
   const int kind = split_kind_of(precision);
-  if (w.L.split_tile == 256) {
-    if (kind == kBF16X3) k_sym_split<kBF16X3, 256, 2, 4><<<grid, 512, 0, st>>>(a);
-    else if (kind == kBF16X1) k_sym_split<kBF16X1, 256, 2, 4><<<grid, 512, 0, st>>>(a);
-    else k_sym_split<kFP16X3, 256, 2, 4><<<grid, 512, 0, st>>>(a);
-  } else {
-    if (kind == kBF16X3) k_sym_split<kBF16X3, 128, 2, 2><<<grid, 256, 0, st>>>(a);
-    else if (kind == kBF16X1) k_sym_split<kBF16X1, 128, 2, 2><<<grid, 256, 0, st>>>(a);
-    else k_sym_split<kFP16X3, 128, 2, 2><<<grid, 256, 0, st>>>(a);
-  }
-  LAUNCH_TRY();
-  return SP2_OK;
+  if (kind == kBF16X3) return launch_split_t<kBF16X3>(w, a, st);
+  if (kind == kBF16X1) return launch_split_t<kBF16X1>(w, a, st);
+  return launch_split_t<kFP16X3>(w, a, st);
 }
 
 // Launch an FP32 product sum_s A_s B_s^T (nseg <= 4).
@@ -265,10 +332,12 @@ sp2_status launch_f32(const WS& w, int nseg, const float* const* A, const float*
   a.nseg = nseg;
   a.epi = epi;
   a.dec = dec;
-  a.band = kBand;
-  a.nb = w.L.nb_f32;
-  a.ntiles = w.L.ntiles_f32;
-  k_sym_f32<kF32Tile, 2, 2><<<dim3(a.ntiles), 256, 0, st>>>(a);
+  auto kern = k_sym_f32<kF32Tile, 2, 2>;
+  constexpr size_t piece = size_t(256) * 2 * 2 * 16 * 4;
+  const int slots = device_cus() * wgs_per_cu(kern, 256);
+  a.dc = plan_decomp(w, w.L.nb_f32, slots, static_cast<int>(w.L.np / 16) * nseg, piece);
+  const int grid = a.dc.nfull + (a.dc.ntiles - a.dc.nfull) * a.dc.nsplit;
+  kern<<<grid, 256, 0, st>>>(a);
   LAUNCH_TRY();
   return SP2_OK;
 }
@@ -384,7 +453,7 @@ sp2_status refine(const WS& w, int precision, int refine_mode, int n_iter, const
   // FP16X3 split refinement: planes of S (pair p) and of S^2 (pair 1-p).
   const int p = precision == SP2_FP32 ? 0 : (n_iter & 1);
   if (precision != SP2_FP16X3) {
-    k_split<<<ew_grid(L.np * L.np), kEwThreads, 0, st>>>(S, L.np, L.np, L.np, L.np, w.hi(p), w.lo(p), 2);
+    k_split<<<ew_grid(L.np * L.np), kEwThreads, 0, st>>>(S, L.np, L.np, L.np, L.np, w.hi(p), w.lo(p), 2, 1);
     LAUNCH_TRY();
   }
   e1.split_out = 2;
@@ -454,6 +523,7 @@ sp2_status sp2_density_ex(const float* H, int64_t n, int64_t ld, int64_t n_occ,
   hipStream_t st = static_cast<hipStream_t>(stream);
   WS w;
   bind(w, workspace, L);
+  if (sp2_status s0 = reset_counters(w, st)) return s0;
   const int prec = o.precision;
   const bool trivial = n_occ == 0 || n_occ == n;
   const bool vec_ok = (ld % 4 == 0) && (reinterpret_cast<uintptr_t>(P) % 16 == 0);
@@ -661,7 +731,7 @@ sp2_status sp2_split(const float* X, int64_t n, int64_t ld, int32_t precision, u
   const int code = split_code_of(precision);
   if (!code) return fail(SP2_ERR_INVALID_ARG, "precision has no 16-bit split");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  k_split<<<ew_grid(n * n), kEwThreads, 0, st>>>(X, n, ld, n, n, hi, lo, code);
+  k_split<<<ew_grid(n * n), kEwThreads, 0, st>>>(X, n, ld, n, n, hi, lo, code, 0);
   LAUNCH_TRY();
   return SP2_OK;
 }
@@ -683,6 +753,7 @@ sp2_status sp2_layer(const float* X, int64_t n, int64_t ld, int32_t precision, i
   hipStream_t st = static_cast<hipStream_t>(stream);
   WS w;
   bind(w, workspace, L);
+  if (sp2_status s0 = reset_counters(w, st)) return s0;
   float* Xp = w.slotf(0);
   k_copy_scaled<<<ew_grid(L.np * L.np), kEwThreads, 0, st>>>(X, ld, Xp, L.np, n, L.np, 1.0f, 0);
   LAUNCH_TRY();
@@ -701,7 +772,7 @@ sp2_status sp2_layer(const float* X, int64_t n, int64_t ld, int32_t precision, i
     s = launch_f32(w, 1, A, A, e, d0, st);
   } else {
     k_split<<<ew_grid(L.np * L.np), kEwThreads, 0, st>>>(Xp, L.np, L.np, L.np, L.np, w.hi(0), w.lo(0),
-                                                         split_code_of(precision));
+                                                         split_code_of(precision), 1);
     LAUNCH_TRY();
     s = launch_split(w, precision, w.hi(0), w.lo(0), w.hi(0), w.lo(0), e, d0, st);
   }
@@ -741,6 +812,7 @@ sp2_status open_tape(void* workspace, size_t ws_bytes, hipStream_t st, WS& w, Ho
   if (!make_layout(m.n, o, L)) return fail(SP2_ERR_TAPE, "corrupt tape description");
   if (sp2_status s = check_ws(L, workspace, ws_bytes)) return s;
   bind(w, workspace, L);
+  if (sp2_status s0 = reset_counters(w, st)) return s0;
   return read_back(w, hm, true, st);
 }
 
@@ -792,7 +864,7 @@ sp2_status load_checkpoint(const WS& w, int prec, int slot, float* dst, hipStrea
   HIP_TRY(hipMemcpyAsync(dst, w.tape(slot), w.L.slot_bytes, hipMemcpyDeviceToDevice, st));
   if (prec != SP2_FP32) {
     k_split<<<ew_grid(w.L.np * w.L.np), kEwThreads, 0, st>>>(dst, w.L.np, w.L.np, w.L.np, w.L.np,
-                                                              w.hi(0), w.lo(0), split_code_of(prec));
+                                                              w.hi(0), w.lo(0), split_code_of(prec), 1);
     LAUNCH_TRY();
   }
   return SP2_OK;

@@ -166,6 +166,28 @@ __device__ inline void split_fp16s(float x, uint16_t& hi, uint16_t& lo) {
 }
 
 // ---------------------------------------------------------------------------
+// K-tiled layout of the 16-bit planes.  The plane of an np x np matrix is
+// stored as blocks of 256 rows x 32 columns (16 KB each), block (I, K) at
+// element (I * np/32 + K) * 8192; inside a block, row r is 64 contiguous
+// bytes whose four 16-byte chunks are permuted by plane_swz(r).  One K step
+// of a 256-row panel is then one contiguous 16 KB block that the product
+// kernel copies verbatim into LDS, where the permutation makes the MFMA
+// fragment reads bank-conflict free.
+// ---------------------------------------------------------------------------
+
+constexpr int kPlaneRows = 256;
+constexpr int kPlaneCols = 32;
+
+__device__ __forceinline__ int plane_swz(int r) { return ((r >> 1) & 3) ^ ((r >> 3) & 1); }
+
+// Element offset of (i, k) in the tiled plane of an np x np matrix.
+__device__ __forceinline__ int64_t plane_off(int64_t i, int64_t k, int64_t np) {
+  const int64_t blk = (i >> 8) * (np >> 5) + (k >> 5);
+  const int r = static_cast<int>(i & 255), c = static_cast<int>(k & 31);
+  return (blk * 256 + r) * 32 + (((c >> 3) ^ plane_swz(r)) << 3) + (c & 7);
+}
+
+// ---------------------------------------------------------------------------
 // Upper-triangle tile schedule.  Work-group b runs on XCD (b mod 8); the
 // remap gives each XCD a contiguous run of logical tiles, and the logical
 // order walks bands of `band` tile-rows column by column so that tiles that

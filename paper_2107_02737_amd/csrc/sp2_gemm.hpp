@@ -42,13 +42,28 @@ struct Epi {
   int np;
 };
 
+// Work decomposition of one launch.  Work-groups [0, nfull) each compute a
+// whole tile (logical tiles 0 .. nfull-1).  The remaining tiles ("tail",
+// the last partial round of the machine) are split along K into nsplit
+// pieces, one per work-group; every piece stores its FP32 partial
+// accumulator, and the last piece to arrive at the tile's counter sums all
+// pieces in a fixed order and runs the epilogue.  No work-group ever waits
+// for another.
+struct Decomp {
+  int nb, ntiles, band;
+  int nfull;        // whole-tile work-groups
+  int nsplit;       // K pieces per tail tile (1: no tail)
+  float* partial;   // (ntiles - nfull) * nsplit accumulators of NT * MI*NI*16 floats
+  int* counter;     // one arrival counter per tail tile, zero between launches
+};
+
 struct SplitArgs {
   const uint16_t* a_hi;
   const uint16_t* a_lo;
   const uint16_t* b_hi;
   const uint16_t* b_lo;
   Epi epi;
-  int nb, ntiles, band;
+  Decomp dc;
   Decide dec;
 };
 
@@ -57,9 +72,83 @@ struct F32Args {
   const float* b[4];
   int nseg;
   Epi epi;
-  int nb, ntiles, band;
+  Decomp dc;
   Decide dec;
 };
+
+// Tile and K range [k0, k1) (in K steps out of ksteps) of this work-group.
+__device__ __forceinline__ void work_of(const Decomp& dc, int ksteps, int& tile, int& ti, int& tj,
+                                        int& k0, int& k1, int& tail, int& piece) {
+  const int b = blockIdx.x;
+  if (b < dc.nfull) {
+    tile = xcd_remap(b, dc.nfull);
+    k0 = 0;
+    k1 = ksteps;
+    tail = -1;
+    piece = 0;
+  } else {
+    const int j = b - dc.nfull;
+    tail = j / dc.nsplit;
+    piece = j - tail * dc.nsplit;
+    tile = dc.nfull + tail;
+    k0 = static_cast<int>((int64_t(ksteps) * piece) / dc.nsplit);
+    k1 = static_cast<int>((int64_t(ksteps) * (piece + 1)) / dc.nsplit);
+  }
+  tile_of(tile, dc.nb, dc.band, ti, tj);
+}
+
+// Tail handling after the K loop: store this piece's accumulator; the last
+// piece to arrive reloads all pieces of the tile in piece order, sums them
+// into acc and returns true (it then runs the epilogue).
+template <int NT, int MI, int NI>
+__device__ __forceinline__ bool reduce_tail(f32x16 (&acc)[MI][NI], const Decomp& dc, int tail,
+                                            int piece) {
+  constexpr int ACC = MI * NI * 16;
+  __shared__ int s_last;
+  const int tid = threadIdx.x;
+  float* mine = dc.partial + (int64_t(tail) * dc.nsplit + piece) * (NT * ACC);
+#pragma clang loop unroll(full)
+  for (int mi = 0; mi < MI; ++mi)
+#pragma clang loop unroll(full)
+    for (int ni = 0; ni < NI; ++ni)
+#pragma clang loop unroll(full)
+      for (int r4 = 0; r4 < 4; ++r4) {
+        const int v = (mi * NI + ni) * 4 + r4;
+        *reinterpret_cast<f32x4*>(mine + (int64_t(v) * NT + tid) * 4) =
+            f32x4{acc[mi][ni][4 * r4], acc[mi][ni][4 * r4 + 1], acc[mi][ni][4 * r4 + 2],
+                  acc[mi][ni][4 * r4 + 3]};
+      }
+  __threadfence();   // release the piece device-wide before counting it
+  __syncthreads();
+  if (tid == 0) s_last = atomicAdd(dc.counter + tail, 1) == dc.nsplit - 1;
+  __syncthreads();
+  if (!s_last) return false;
+  __threadfence();   // acquire the other pieces
+#pragma clang loop unroll(full)
+  for (int mi = 0; mi < MI; ++mi)
+#pragma clang loop unroll(full)
+    for (int ni = 0; ni < NI; ++ni)
+#pragma clang loop unroll(full)
+      for (int r = 0; r < 16; ++r) acc[mi][ni][r] = 0.0f;
+  for (int q = 0; q < dc.nsplit; ++q) {
+    const float* src = dc.partial + (int64_t(tail) * dc.nsplit + q) * (NT * ACC);
+#pragma clang loop unroll(full)
+    for (int mi = 0; mi < MI; ++mi)
+#pragma clang loop unroll(full)
+      for (int ni = 0; ni < NI; ++ni)
+#pragma clang loop unroll(full)
+        for (int r4 = 0; r4 < 4; ++r4) {
+          const int v = (mi * NI + ni) * 4 + r4;
+          const f32x4 x = *reinterpret_cast<const f32x4*>(src + (int64_t(v) * NT + tid) * 4);
+          acc[mi][ni][4 * r4] += x[0];
+          acc[mi][ni][4 * r4 + 1] += x[1];
+          acc[mi][ni][4 * r4 + 2] += x[2];
+          acc[mi][ni][4 * r4 + 3] += x[3];
+        }
+  }
+  if (tid == 0) dc.counter[tail] = 0;   // ready for the next launch
+  return true;
+}
 
 __device__ __forceinline__ void split_value(float v, int kind, uint16_t& h, uint16_t& l) {
   if (kind == 1)
@@ -74,7 +163,7 @@ __device__ __forceinline__ void split_value(float v, int kind, uint16_t& h, uint
 template <int NT, int BM, int TM, int TN, int MI, int NI>
 __device__ __forceinline__ void sym_epilogue(const f32x16 (&acc)[MI][NI], const Epi& p, float alpha,
                                     float beta, int ti, int tj, int wm, int wn, int lane,
-                                    double* red) {
+                                    double* red, int tile) {
   const int64_t np = p.np;
   const bool diag = ti == tj;
   double t1 = 0.0, t2 = 0.0;
@@ -125,7 +214,8 @@ __device__ __forceinline__ void sym_epilogue(const f32x16 (&acc)[MI][NI], const 
             if (gi != gj) p.out[gj * p.ld_out + gi] = v[e];
           }
         }
-        // dual 16-bit representation of the result for the next layer
+        // dual 16-bit representation of the result for the next layer, in
+        // the K-tiled plane layout (the mirrored 4-element run is contiguous)
         if (p.split_out) {
           uint16_t h[4], l[4];
 #pragma clang loop unroll(full)
@@ -133,22 +223,25 @@ __device__ __forceinline__ void sym_epilogue(const f32x16 (&acc)[MI][NI], const 
           if (!diag) {
 #pragma clang loop unroll(full)
             for (int e = 0; e < 4; ++e) {
-              p.hi_out[(gi0 + e) * np + gj] = h[e];
-              p.lo_out[(gi0 + e) * np + gj] = l[e];
+              const int64_t o = plane_off(gi0 + e, gj, np);
+              p.hi_out[o] = h[e];
+              p.lo_out[o] = l[e];
             }
-            *reinterpret_cast<u32x2*>(p.hi_out + gj * np + gi0) =
+            const int64_t om = plane_off(gj, gi0, np);
+            *reinterpret_cast<u32x2*>(p.hi_out + om) =
                 u32x2{uint32_t(h[0]) | (uint32_t(h[1]) << 16), uint32_t(h[2]) | (uint32_t(h[3]) << 16)};
-            *reinterpret_cast<u32x2*>(p.lo_out + gj * np + gi0) =
+            *reinterpret_cast<u32x2*>(p.lo_out + om) =
                 u32x2{uint32_t(l[0]) | (uint32_t(l[1]) << 16), uint32_t(l[2]) | (uint32_t(l[3]) << 16)};
           } else {
 #pragma clang loop unroll(full)
             for (int e = 0; e < 4; ++e) {
               if (!keep[e]) continue;
               const int64_t gi = gi0 + e;
-              p.hi_out[gi * np + gj] = h[e];
-              p.lo_out[gi * np + gj] = l[e];
-              p.hi_out[gj * np + gi] = h[e];
-              p.lo_out[gj * np + gi] = l[e];
+              const int64_t o = plane_off(gi, gj, np), om = plane_off(gj, gi, np);
+              p.hi_out[o] = h[e];
+              p.lo_out[o] = l[e];
+              p.hi_out[om] = h[e];
+              p.lo_out[om] = l[e];
             }
           }
         }
@@ -158,33 +251,191 @@ __device__ __forceinline__ void sym_epilogue(const f32x16 (&acc)[MI][NI], const 
   if (p.parts_out) {
     block_sum2<NT>(t1, t2, red);
     if (threadIdx.x == 0) {
-      p.parts_out[2 * blockIdx.x] = t1;
-      p.parts_out[2 * blockIdx.x + 1] = t2;
+      p.parts_out[2 * tile] = t1;
+      p.parts_out[2 * tile + 1] = t2;
+    }
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// LDS-staged epilogue of the 256 x 256 split tile (4 waves of 128 x 128).
+// Two passes, one per 128-row half: the two waves that own the half write
+// their final values (alpha*acc + beta*C) into a padded [128][257] FP32 LDS
+// image and accumulate the trace partials; then all 256 threads copy the
+// half out in 8-element runs -- rows of the tile (direct) and rows of the
+// mirrored tile (columns of the image) -- as FP32 and, when requested, as
+// the hi/lo pair in the K-tiled plane layout.  On diagonal tiles only
+// elements on or above the diagonal are used, each also mirrored, so the
+// result is exactly symmetric.
+// ---------------------------------------------------------------------------
+
+constexpr int kEpiLd = 257;   // padded LDS row (floats)
+
+__device__ __forceinline__ void store_run8(const Epi& p, int64_t row, int64_t col0, const float (&v)[8],
+                                           int first, int last) {
+  // elements [first, last) of the run (row, col0 .. col0+7)
+  const int64_t np = p.np;
+  if (row >= p.n_valid) return;
+  if (first == 0 && last == 8 && col0 + 8 <= p.n_valid && p.vec_ok) {
+    float* o = p.out + row * p.ld_out + col0;
+    *reinterpret_cast<f32x4*>(o) = f32x4{v[0], v[1], v[2], v[3]};
+    *reinterpret_cast<f32x4*>(o + 4) = f32x4{v[4], v[5], v[6], v[7]};
+  } else {
+    for (int e = first; e < last; ++e)
+      if (col0 + e < p.n_valid) p.out[row * p.ld_out + col0 + e] = v[e];
+  }
+  if (p.split_out) {
+    uint16_t h[8], l[8];
+#pragma clang loop unroll(full)
+    for (int e = 0; e < 8; ++e) split_value(v[e], p.split_out, h[e], l[e]);
+    const int64_t o = plane_off(row, col0, np);   // a run of 8 never crosses a chunk
+    if (first == 0 && last == 8) {
+      u32x4 hv, lv;
+#pragma clang loop unroll(full)
+      for (int e = 0; e < 4; ++e) {
+        hv[e] = uint32_t(h[2 * e]) | (uint32_t(h[2 * e + 1]) << 16);
+        lv[e] = uint32_t(l[2 * e]) | (uint32_t(l[2 * e + 1]) << 16);
+      }
+      *reinterpret_cast<u32x4*>(p.hi_out + o) = hv;
+      *reinterpret_cast<u32x4*>(p.lo_out + o) = lv;
+    } else {
+      for (int e = first; e < last; ++e) {
+        p.hi_out[o + e] = h[e];
+        p.lo_out[o + e] = l[e];
+      }
+    }
+  }
+}
+
+template <int NT, int MI, int NI>
+__device__ __forceinline__ void sym_epilogue_lds(const f32x16 (&acc)[MI][NI], const Epi& p, float alpha,
+                                                 float beta, int ti, int tj, int wm, int wn, int lane,
+                                                 double* red, int tile, float* img) {
+  constexpr int BM = 256, TM = 128, TN = 128;
+  const int64_t np = p.np;
+  const bool diag = ti == tj;
+  const int tid = threadIdx.x;
+  double t1 = 0.0, t2 = 0.0;
+  for (int half = 0; half < 2; ++half) {
+    __syncthreads();   // the image (and before it, the operand ring) is free
+    if (wm == half) {
+#pragma clang loop unroll(full)
+      for (int mi = 0; mi < MI; ++mi)
+#pragma clang loop unroll(full)
+        for (int ni = 0; ni < NI; ++ni) {
+          const int cl = wn * TN + ni * 32 + (lane & 31);
+#pragma clang loop unroll(full)
+          for (int q = 0; q < 4; ++q)
+#pragma clang loop unroll(full)
+            for (int e = 0; e < 4; ++e)
+              img[(mi * 32 + 8 * q + 4 * (lane >> 5) + e) * kEpiLd + cl] = acc[mi][ni][4 * q + e] * p.oscale;
+        }
+    }
+    __syncthreads();
+    // direct runs: 128 rows x 32 runs of 8 columns; mirrored runs: 256 rows
+    // (tile columns) x 16 runs of 8 rows of the half.  C is symmetric, so the
+    // mirrored run reads it at the mirrored position.
+    for (int task = tid; task < 8192; task += NT) {
+      float v[8], c[8];
+      int64_t row, col0;
+      int first = 0, last = 8;
+      bool direct = task < 4096;
+      if (direct) {
+        const int rh = task >> 5, c0 = (task & 31) * 8;
+        const int rl = half * TM + rh;
+#pragma clang loop unroll(full)
+        for (int e = 0; e < 8; ++e) v[e] = img[rh * kEpiLd + c0 + e];
+        if (diag) first = rl <= c0 ? 0 : (rl >= c0 + 8 ? 8 : rl - c0);   // columns >= row
+        row = int64_t(ti) * BM + rl;
+        col0 = int64_t(tj) * BM + c0;
+      } else {
+        const int t = task - 4096;
+        const int cl = t >> 4, r0 = (t & 15) * 8;   // image column, first image row of the run
+#pragma clang loop unroll(full)
+        for (int e = 0; e < 8; ++e) v[e] = img[(r0 + e) * kEpiLd + cl];
+        const int rl0 = half * TM + r0;
+        if (diag) last = rl0 + 8 <= cl ? 8 : (rl0 >= cl ? 0 : cl - rl0);   // rows < column
+        row = int64_t(tj) * BM + cl;
+        col0 = int64_t(ti) * BM + rl0;
+      }
+      if (first >= last) continue;
+      if (beta != 0.0f) {
+        const float* cp = p.c + row * np + col0;
+        if (first == 0 && last == 8) {
+          const f32x4 a = *reinterpret_cast<const f32x4*>(cp);
+          const f32x4 b = *reinterpret_cast<const f32x4*>(cp + 4);
+#pragma clang loop unroll(full)
+          for (int e = 0; e < 4; ++e) {
+            c[e] = a[e];
+            c[4 + e] = b[e];
+          }
+        } else {
+#pragma clang loop unroll(full)
+          for (int e = 0; e < 8; ++e) c[e] = (e >= first && e < last) ? cp[e] : 0.0f;
+        }
+#pragma clang loop unroll(full)
+        for (int e = 0; e < 8; ++e) v[e] = alpha * v[e] + beta * c[e];
+      } else {
+#pragma clang loop unroll(full)
+        for (int e = 0; e < 8; ++e) v[e] = alpha * v[e];
+      }
+      if (direct) {   // each unordered pair is counted once, from its upper element
+#pragma clang loop unroll(full)
+        for (int e = 0; e < 8; ++e) {
+          if (e < first) continue;
+          const double d = static_cast<double>(v[e]);
+          if (row == col0 + e) {
+            t1 += d;
+            t2 += d * d;
+          } else {
+            t2 += 2.0 * d * d;
+          }
+        }
+      }
+      store_run8(p, row, col0, v, first, last);
+    }
+  }
+  if (p.parts_out) {
+    block_sum2<NT>(t1, t2, red);
+    if (threadIdx.x == 0) {
+      p.parts_out[2 * tile] = t1;
+      p.parts_out[2 * tile + 1] = t2;
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// 16-bit split product.  Block tile BM x BM, WM x WN waves, wave tile
-// (BM/WM) x (BM/WN) of 32x32 MFMA blocks; K staged 32 at a time through a
-// double-buffered, swizzled LDS (A hi, A lo, B hi, B lo planes).
+// 16-bit split product.  256 x 256 output tile per work-group of 4 waves
+// (2 x 2, each 128 x 128 = 4 x 4 blocks of 32x32 MFMA), one wave per SIMD
+// with the 256 accumulators in AGPRs.  K advances 32 at a time through a
+// two-stage LDS ring filled by global_load_lds DMA straight from the
+// K-tiled planes (16 KB per plane and K step).  Fragments are double
+// buffered in registers: the barrier of each K step sits between two MFMA
+// clusters whose operands are already loaded, and the LDS reads of the next
+// half step are interleaved 1:3 (1:2 for one product) with the MFMAs.
 // ---------------------------------------------------------------------------
 
-template <int KIND, int BM, int WM, int WN>
-__global__ __launch_bounds__(WM* WN* kWave) void k_sym_split(SplitArgs p) {
-  constexpr int NT = WM * WN * kWave;
-  constexpr int BK = 32;
-  constexpr int TM = BM / WM, TN = BM / WN;
-  constexpr int MI = TM / 32, NI = TN / 32;
-  constexpr bool kLo = KIND != kBF16X1;
-  constexpr int NARR = kLo ? 4 : 2;
-  constexpr int ARR = BM * BK;          // 16-bit elements per staged plane
-  constexpr int CPA = ARR / 8;          // 16-byte chunks per plane
-  constexpr int CPT = CPA / NT;         // chunks per thread per plane
-  static_assert(CPA % NT == 0, "tile / thread mismatch");
-  static_assert(MI >= 1 && NI >= 1, "wave tile too small");
+// One 16-byte chunk per lane from global memory into LDS at m0 + 16 * lane.
+// Issued as inline assembly so that the compiler does not wait on it before
+// every LDS read; the kernel waits for the DMA explicitly (vmcnt) before
+// the barrier that publishes a stage.
+__device__ __forceinline__ void dma_chunk(uint32_t off, const void* base, uint32_t m0) {
+  asm volatile("s_mov_b32 m0, %2\n\tglobal_load_lds_dwordx4 %0, %1" ::"v"(off), "s"(base), "s"(m0)
+               : "memory", "m0");
+}
 
-  __shared__ __attribute__((aligned(16))) uint16_t lds[2 * NARR * ARR];
+__device__ __forceinline__ void wait_vmem_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
+
+template <int KIND>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void k_sym_split(SplitArgs p) {
+  constexpr int BM = 256, NT = 256, BK = 32, MI = 4, NI = 4, TM = 128, TN = 128;
+  constexpr bool kLo = KIND != kBF16X1;
+  constexpr int PLANE_B = BM * BK * 2;   // bytes of one plane per stage (16 KB)
+  constexpr int STAGE_B = 4 * PLANE_B;   // A hi, A lo, B hi, B lo
+  // two operand stages (128 KB), reused as the [128][257] FP32 epilogue image
+  __shared__ __attribute__((aligned(1024))) uint16_t lds[128 * kEpiLd * 2];
   __shared__ double red[2 * (NT / kWave)];
 
   const int sign = decide_layer<NT>(p.dec, red);
@@ -194,123 +445,135 @@ __global__ __launch_bounds__(WM* WN* kWave) void k_sym_split(SplitArgs p) {
     alpha = sign > 0 ? 1.0f : -1.0f;
     beta = sign > 0 ? 0.0f : 2.0f;
   }
-
-  int ti, tj;
-  tile_of(xcd_remap(blockIdx.x, p.ntiles), p.nb, p.band, ti, tj);
   const int64_t np = p.epi.np;
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
-  const int wm = wid / WN, wn = wid % WN;
+  const int KT = static_cast<int>(np / BK);
+  int tile, ti, tj, kb, ke, tail, piece;
+  work_of(p.dc, KT, tile, ti, tj, kb, ke, tail, piece);
+  const int tid = threadIdx.x, lane = tid & (kWave - 1);
+  const int w = __builtin_amdgcn_readfirstlane(tid / kWave);
+  const int wm = w >> 1, wn = w & 1;
 
-  // Row panels of A (tile row ti) and B (tile row tj); plane order in LDS:
-  // A hi, [A lo], B hi, [B lo].
-  const int64_t offa = int64_t(ti) * BM * np, offb = int64_t(tj) * BM * np;
-  const uint16_t* g0 = p.a_hi + offa;
-  const uint16_t* g1 = kLo ? p.a_lo + offa : p.b_hi + offb;
-  const uint16_t* g2 = kLo ? p.b_hi + offb : nullptr;
-  const uint16_t* g3 = kLo ? p.b_lo + offb : nullptr;
-
-  // This thread's 16-byte chunks: element offset in the panel and in LDS.
-  int64_t goff[CPT];
-  int loff[CPT];
-#pragma clang loop unroll(full)
-  for (int i = 0; i < CPT; ++i) {
-    const int q = tid + NT * i;
-    const int row = q >> 2, c = q & 3;
-    goff[i] = int64_t(row) * np + c * 8;
-    loff[i] = row * BK + ((c ^ swz(row)) * 8);
+  // DMA: plane block (panel P, K step kt) starts at element (P*KT + kt)*8192;
+  // this wave copies its 1 KB pieces (i*4 + w), i = 0..3, of each plane.
+  const uint16_t* ga_hi = p.a_hi + int64_t(ti) * KT * 8192;
+  const uint16_t* ga_lo = kLo ? p.a_lo + int64_t(ti) * KT * 8192 : nullptr;
+  const uint16_t* gb_hi = p.b_hi + int64_t(tj) * KT * 8192;
+  const uint16_t* gb_lo = kLo ? p.b_lo + int64_t(tj) * KT * 8192 : nullptr;
+  const uint32_t lds0 = static_cast<uint32_t>(
+      reinterpret_cast<uintptr_t>((__attribute__((address_space(3))) uint16_t*)(lds)));
+#define SP2_DMA_STAGE(STAGE, KTI)                                                         \
+  {                                                                                       \
+    const int64_t kofs_ = int64_t(KTI) * 8192;                                            \
+    const uint32_t m0s_ = lds0 + (STAGE) * STAGE_B + w * 1024;                            \
+    _Pragma("clang loop unroll(full)") for (int i = 0; i < 4; ++i) {                      \
+      const uint32_t off_ = static_cast<uint32_t>(((i * 4 + w) * 64 + lane) * 16);        \
+      dma_chunk(off_, ga_hi + kofs_, m0s_ + 0 * PLANE_B + i * 4096);                      \
+      dma_chunk(off_, gb_hi + kofs_, m0s_ + 2 * PLANE_B + i * 4096);                      \
+      if constexpr (kLo) {                                                                \
+        dma_chunk(off_, ga_lo + kofs_, m0s_ + 1 * PLANE_B + i * 4096);                    \
+        dma_chunk(off_, gb_lo + kofs_, m0s_ + 3 * PLANE_B + i * 4096);                    \
+      }                                                                                   \
+    }                                                                                     \
   }
 
-  u32x4 st0[CPT], st1[CPT], st2[CPT], st3[CPT];
+  // Fragment addresses (bytes within a stage).  Row r of a 32-row block,
+  // h = lane/32; half step s reads logical chunk 2s + h, stored at
+  // (2s + h) ^ plane_swz(r) (plane_swz only sees the low 5 bits of the row).
+  const int r = lane & 31, h = lane >> 5, sw = plane_swz(r);
+  const int fa0 = (wm * TM + r) * 64 + ((h ^ sw) << 4);
+  const int fa1 = (wm * TM + r) * 64 + (((2 + h) ^ sw) << 4);
+  const int fb0 = (wn * TN + r) * 64 + ((h ^ sw) << 4);
+  const int fb1 = (wn * TN + r) * 64 + (((2 + h) ^ sw) << 4);
+  const char* L = reinterpret_cast<const char*>(lds);
+
   f32x16 acc[MI][NI];
 #pragma clang loop unroll(full)
   for (int mi = 0; mi < MI; ++mi)
 #pragma clang loop unroll(full)
     for (int ni = 0; ni < NI; ++ni)
 #pragma clang loop unroll(full)
-      for (int r = 0; r < 16; ++r) acc[mi][ni][r] = 0.0f;
+      for (int q = 0; q < 16; ++q) acc[mi][ni][q] = 0.0f;
 
-#define SP2_GLOAD(KT)                                                                   \
-  _Pragma("unroll") for (int i = 0; i < CPT; ++i) {                                     \
-    const int64_t o = goff[i] + int64_t(KT) * BK;                                       \
-    st0[i] = *reinterpret_cast<const u32x4*>(g0 + o);                                   \
-    st1[i] = *reinterpret_cast<const u32x4*>(g1 + o);                                   \
-    if constexpr (kLo) {                                                                \
-      st2[i] = *reinterpret_cast<const u32x4*>(g2 + o);                                 \
-      st3[i] = *reinterpret_cast<const u32x4*>(g3 + o);                                 \
-    }                                                                                   \
-  }
-#define SP2_LSTORE(BUF)                                                                 \
-  _Pragma("unroll") for (int i = 0; i < CPT; ++i) {                                     \
-    uint16_t* d = lds + (BUF) * NARR * ARR + loff[i];                                   \
-    *reinterpret_cast<u32x4*>(d) = st0[i];                                              \
-    *reinterpret_cast<u32x4*>(d + ARR) = st1[i];                                        \
-    if constexpr (kLo) {                                                                \
-      *reinterpret_cast<u32x4*>(d + 2 * ARR) = st2[i];                                  \
-      *reinterpret_cast<u32x4*>(d + 3 * ARR) = st3[i];                                  \
-    }                                                                                   \
+  u32x4 Ah0[MI], Al0[MI], Bh0[NI], Bl0[NI];
+  u32x4 Ah1[MI], Al1[MI], Bh1[NI], Bl1[NI];
+
+#define SP2_FRAG(AH, AL, BH, BL, STAGE, FA, FB)                                           \
+  {                                                                                       \
+    const char* S_ = L + (STAGE) * STAGE_B;                                               \
+    _Pragma("clang loop unroll(full)") for (int mi = 0; mi < MI; ++mi)                    \
+      AH[mi] = *reinterpret_cast<const u32x4*>(S_ + 0 * PLANE_B + (FA) + mi * 2048); \
+    _Pragma("clang loop unroll(full)") for (int ni = 0; ni < NI; ++ni)                    \
+      BH[ni] = *reinterpret_cast<const u32x4*>(S_ + 2 * PLANE_B + (FB) + ni * 2048); \
+    if constexpr (kLo) {                                                                  \
+      _Pragma("clang loop unroll(full)") for (int ni = 0; ni < NI; ++ni)                  \
+        BL[ni] = *reinterpret_cast<const u32x4*>(S_ + 3 * PLANE_B + (FB) + ni * 2048); \
+      _Pragma("clang loop unroll(full)") for (int mi = 0; mi < MI; ++mi)                  \
+        AL[mi] = *reinterpret_cast<const u32x4*>(S_ + 1 * PLANE_B + (FA) + mi * 2048); \
+    }                                                                                     \
   }
 
-  const int KT = static_cast<int>(np / BK);
-  SP2_GLOAD(0);
-  SP2_LSTORE(0);
+#define SP2_MFMA1(X, Y)                                                                   \
+  _Pragma("clang loop unroll(full)") for (int mi = 0; mi < MI; ++mi)                      \
+  _Pragma("clang loop unroll(full)") for (int ni = 0; ni < NI; ++ni) {                    \
+    if constexpr (KIND == kFP16X3)                                                        \
+      acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_f16(                               \
+          __builtin_bit_cast(f16x8, X[mi]), __builtin_bit_cast(f16x8, Y[ni]), acc[mi][ni], 0, 0, 0); \
+    else                                                                                  \
+      acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(                              \
+          __builtin_bit_cast(bf16x8, X[mi]), __builtin_bit_cast(bf16x8, Y[ni]), acc[mi][ni], 0, 0, 0); \
+  }
+  // hi*hi first for every block, then hi*lo, then lo*hi: an accumulator is
+  // revisited only every 16 MFMAs.
+#define SP2_MFMA(AH, AL, BH, BL)                                                          \
+  SP2_MFMA1(AH, BH)                                                                       \
+  if constexpr (kLo) {                                                                    \
+    SP2_MFMA1(AH, BL)                                                                     \
+    SP2_MFMA1(AL, BH)                                                                     \
+  }
+#define SP2_INTERLEAVE()                                                                  \
+  if constexpr (kLo) {                                                                    \
+    _Pragma("clang loop unroll(full)") for (int g = 0; g < 16; ++g) {                    \
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);                                  \
+      __builtin_amdgcn_sched_group_barrier(0x008, 3, 0);                                  \
+    }                                                                                     \
+  } else {                                                                                \
+    _Pragma("clang loop unroll(full)") for (int g = 0; g < 8; ++g) {                     \
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);                                  \
+      __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);                                  \
+    }                                                                                     \
+  }
+
+  SP2_DMA_STAGE(0, kb);
+  wait_vmem_all();
   __syncthreads();
-  for (int kt = 0; kt < KT; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < KT) {
-      SP2_GLOAD(kt + 1);
-    }
-    const uint16_t* L = lds + buf * NARR * ARR;
-#pragma clang loop unroll(full)
-    for (int s = 0; s < 2; ++s) {
-      const int c = 2 * s + (lane >> 5);
-      u32x4 ah[MI], al[MI], bh[NI], bl[NI];
-#pragma clang loop unroll(full)
-      for (int mi = 0; mi < MI; ++mi) {
-        const int row = wm * TM + mi * 32 + (lane & 31);
-        const int off = row * BK + ((c ^ swz(row)) * 8);
-        ah[mi] = *reinterpret_cast<const u32x4*>(L + off);
-        if constexpr (kLo) al[mi] = *reinterpret_cast<const u32x4*>(L + ARR + off);
-      }
-#pragma clang loop unroll(full)
-      for (int ni = 0; ni < NI; ++ni) {
-        const int row = wn * TN + ni * 32 + (lane & 31);
-        const int off = row * BK + ((c ^ swz(row)) * 8);
-        bh[ni] = *reinterpret_cast<const u32x4*>(L + (kLo ? 2 : 1) * ARR + off);
-        if constexpr (kLo) bl[ni] = *reinterpret_cast<const u32x4*>(L + 3 * ARR + off);
-      }
-#pragma clang loop unroll(full)
-      for (int mi = 0; mi < MI; ++mi)
-#pragma clang loop unroll(full)
-        for (int ni = 0; ni < NI; ++ni) {
-          if constexpr (KIND == kFP16X3) {
-            const f16x8 a0 = __builtin_bit_cast(f16x8, ah[mi]);
-            const f16x8 b0 = __builtin_bit_cast(f16x8, bh[ni]);
-            acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a0, b0, acc[mi][ni], 0, 0, 0);
-            acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                a0, __builtin_bit_cast(f16x8, bl[ni]), acc[mi][ni], 0, 0, 0);
-            acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                __builtin_bit_cast(f16x8, al[mi]), b0, acc[mi][ni], 0, 0, 0);
-          } else {
-            const bf16x8 a0 = __builtin_bit_cast(bf16x8, ah[mi]);
-            const bf16x8 b0 = __builtin_bit_cast(bf16x8, bh[ni]);
-            acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[mi][ni], 0, 0, 0);
-            if constexpr (kLo) {
-              acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                  a0, __builtin_bit_cast(bf16x8, bl[ni]), acc[mi][ni], 0, 0, 0);
-              acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                  __builtin_bit_cast(bf16x8, al[mi]), b0, acc[mi][ni], 0, 0, 0);
-            }
-          }
-        }
-    }
-    if (kt + 1 < KT) {
-      SP2_LSTORE(buf ^ 1);
-    }
+  if (kb + 1 < ke) SP2_DMA_STAGE(1, kb + 1);
+  SP2_FRAG(Ah0, Al0, Bh0, Bl0, 0, fa0, fb0);
+  for (int kt = kb; kt < ke; ++kt) {
+    const int st = (kt - kb) & 1;
+    // first half step of K tile kt from registers; fetch its second half
+    SP2_FRAG(Ah1, Al1, Bh1, Bl1, st, fa1, fb1);
+    SP2_MFMA(Ah0, Al0, Bh0, Bl0);
+    SP2_INTERLEAVE();
+    // stage st^1 (K tile kt+1) has landed for this wave; after the barrier
+    // it has for all waves, and stage st is free for K tile kt+2
+    wait_vmem_all();
     __syncthreads();
+    if (kt + 2 < ke) SP2_DMA_STAGE(st, kt + 2);
+    // second half step of kt from registers; fetch the first half of kt+1
+    SP2_FRAG(Ah0, Al0, Bh0, Bl0, st ^ 1, fa0, fb0);
+    SP2_MFMA(Ah1, Al1, Bh1, Bl1);
+    SP2_INTERLEAVE();
   }
-#undef SP2_GLOAD
-#undef SP2_LSTORE
-  sym_epilogue<NT, BM, TM, TN, MI, NI>(acc, p.epi, alpha, beta, ti, tj, wm, wn, lane, red);
+  wait_vmem_all();
+  __syncthreads();
+#undef SP2_DMA_STAGE
+#undef SP2_FRAG
+#undef SP2_MFMA1
+#undef SP2_MFMA
+#undef SP2_INTERLEAVE
+  if (tail >= 0 && !reduce_tail<NT, MI, NI>(acc, p.dc, tail, piece)) return;
+  sym_epilogue_lds<NT, MI, NI>(acc, p.epi, alpha, beta, ti, tj, wm, wn, lane, red, tile,
+                               reinterpret_cast<float*>(lds));
 }
 
 // ---------------------------------------------------------------------------
@@ -341,9 +604,11 @@ __global__ __launch_bounds__(WM* WN* kWave) void k_sym_f32(F32Args p) {
     beta = sign > 0 ? 0.0f : 2.0f;
   }
 
-  int ti, tj;
-  tile_of(xcd_remap(blockIdx.x, p.ntiles), p.nb, p.band, ti, tj);
   const int64_t np = p.epi.np;
+  const int KT = static_cast<int>(np / BK);
+  const int IT = KT * p.nseg;
+  int tile, ti, tj, ib, ie, tail, piece;
+  work_of(p.dc, IT, tile, ti, tj, ib, ie, tail, piece);
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
   const int wm = wid / WN, wn = wid % WN;
 
@@ -365,8 +630,6 @@ __global__ __launch_bounds__(WM* WN* kWave) void k_sym_f32(F32Args p) {
 #pragma clang loop unroll(full)
       for (int r = 0; r < 16; ++r) acc[mi][ni][r] = 0.0f;
 
-  const int KT = static_cast<int>(np / BK);
-  const int IT = KT * p.nseg;
   const int64_t offa = int64_t(ti) * BM * np, offb = int64_t(tj) * BM * np;
 
 #define SP2_GLOAD32(IT_)                                                                \
@@ -386,12 +649,12 @@ __global__ __launch_bounds__(WM* WN* kWave) void k_sym_f32(F32Args p) {
     *reinterpret_cast<u32x4*>(d + ARR) = sb[i];                                         \
   }
 
-  SP2_GLOAD32(0);
+  SP2_GLOAD32(ib);
   SP2_LSTORE32(0);
   __syncthreads();
-  for (int it = 0; it < IT; ++it) {
-    const int buf = it & 1;
-    if (it + 1 < IT) {
+  for (int it = ib; it < ie; ++it) {
+    const int buf = (it - ib) & 1;
+    if (it + 1 < ie) {
       SP2_GLOAD32(it + 1);
     }
     const float* LA = lds + (buf * 2) * ARR;
@@ -421,14 +684,15 @@ __global__ __launch_bounds__(WM* WN* kWave) void k_sym_f32(F32Args p) {
           acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[mi][k >> 2][k & 3],
                                                              bf[ni][k >> 2][k & 3], acc[mi][ni], 0,
                                                              0, 0);
-    if (it + 1 < IT) {
+    if (it + 1 < ie) {
       SP2_LSTORE32(buf ^ 1);
     }
     __syncthreads();
   }
 #undef SP2_GLOAD32
 #undef SP2_LSTORE32
-  sym_epilogue<NT, BM, TM, TN, MI, NI>(acc, p.epi, alpha, beta, ti, tj, wm, wn, lane, red);
+  if (tail >= 0 && !reduce_tail<NT, MI, NI>(acc, p.dc, tail, piece)) return;
+  sym_epilogue<NT, BM, TM, TN, MI, NI>(acc, p.epi, alpha, beta, ti, tj, wm, wn, lane, red, tile);
 }
 
 }  // namespace sp2

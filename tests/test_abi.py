@@ -55,7 +55,7 @@ def test_workspace_bytes(lib):
     n = 6144
     b = _lib.sp2_workspace_bytes(n, o)
     assert b >= 4 * n * n * 4                   # four padded FP32 slots
-    assert b < 4 * n * n * 4 + (1 << 20)
+    assert b < 4 * n * n * 4 + (65 << 20)      # + split-K partial accumulators
     o.checkpoint_every = 4
     bt = _lib.sp2_workspace_bytes(n, o)
     assert bt - b == (4 + 4 + 100 // 4 + 1) * n * n * 4

@@ -111,17 +111,23 @@ def _layer_reference(x32, precision, sign):
     return r, bound
 
 
-CASES = [(256, 256, None), (300, 300, None), (1000, 1003, None), (520, 520, "256")]
+# (n, ld, split tile, split-K tail): at these sizes the tiles do not fill the
+# machine, so by default every tile is split along K and reduced by its last
+# piece; "nosplit" forces whole-tile work-groups only.
+CASES = [(256, 256, None, True), (300, 300, None, True), (1000, 1003, None, True),
+         (520, 520, "256", True), (1000, 1000, None, False), (768, 768, "256", False)]
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16x1", "bf16x3", "fp16x3"])
-@pytest.mark.parametrize("n,ld,tile", CASES)
+@pytest.mark.parametrize("n,ld,tile,splitk", CASES)
 @pytest.mark.parametrize("sign", [1, -1])
-def test_layer_matches_oracle_product(pk, precision, n, ld, tile, sign, monkeypatch):
+def test_layer_matches_oracle_product(pk, precision, n, ld, tile, splitk, sign, monkeypatch):
     import torch
-    banner(f"layer {precision} n={n} ld={ld} tile={tile} sign={sign}")
+    banner(f"layer {precision} n={n} ld={ld} tile={tile} splitk={splitk} sign={sign}")
     if tile:
         monkeypatch.setenv("SP2_SPLIT_TILE", tile)
+    if not splitk:
+        monkeypatch.setenv("SP2_NO_SPLITK", "1")
     rng = np.random.default_rng(n + 3)
     q, _ = np.linalg.qr(rng.standard_normal((n, n)))
     x = (q * rng.uniform(0.0, 1.0, n)) @ q.T
