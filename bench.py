@@ -32,6 +32,9 @@ METRIC = "SP2 density-matrix solves/s + effective TFLOPS at N=6144; error vs FP6
 PEAK_TFLOPS = {"bf16x3": 2500.0, "fp16x3": 2500.0, "bf16x1": 2500.0, "fp32": 157.3}
 PRODUCTS = {"bf16x3": 3, "fp16x3": 3, "bf16x1": 1, "fp32": 1}
 GOLDEN = os.path.join(ROOT, "tests", "golden", "water_m1024_seed0.npz")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_sym_split_bf16x3_water6144_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2107_02737_amd", "csrc", f)
+                  for f in ("sp2_common.hpp", "sp2_gemm.hpp")]
 
 
 def parse():
@@ -45,7 +48,42 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-layers", type=int, default=4,
                     help="FP64 oracle layers timed for the CPU baseline sample")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (calibrates HBM traffic counters)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain device copy of known size: 1 GiB read + 1 GiB written per launch.
+    Its FETCH_SIZE / WRITE_SIZE counter readings calibrate the traffic figures
+    reported for the layer kernel."""
+    import torch
+    n = (1 << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_per_launch": 4 * n, "launches": 3}), flush=True)
+
+
+def measured_traffic(precision):
+    """HBM bytes per layer launch from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, calibrated against a plain copy), or None when
+    the summary is for another precision or the kernel source has changed
+    since the counters were taken."""
+    import hashlib
+    if precision != "bf16x3" or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    sha = hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SOURCES)).hexdigest()
+    fields = {}
+    for line in open(TRAFFIC_PROFILE):
+        if ":" in line and not line.startswith(("|", " ", "#")):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("kernel_source_sha256") != sha:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def timed_solves(pk, H, n_occ, precision, refine, steps, warmup, time_layers):
@@ -134,6 +172,9 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver has no "
               "multi-GPU path in this build.", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     import torch
 
     import paper_2107_02737_amd as pk
@@ -185,7 +226,7 @@ def main():
         "effective_tflops": eff_flop / sec / 1e12,
         "error_vs_oracle": err,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": measured_traffic(args.precision),
                      "kernel": f"k_sym_split ({args.precision} layer product)"
                                if args.precision != "fp32" else "k_sym_f32 (fp32 layer product)",
                      "layer_ms": layer_ms,
