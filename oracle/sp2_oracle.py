@@ -329,11 +329,17 @@ def daleckii_krein_jvp(h, h1, rec):
     return v @ (gam * (v.T @ x1 @ v)) @ v.T
 
 
-def dmpt_response(h, n_occ, h1):
+def dmpt_response(h, n_occ, h1, eig=None):
     """First-order density-matrix perturbation theory at the exact step
     function: in the eigenbasis of ``H`` the response couples occupied ``i``
-    and virtual ``a`` states only, ``(V^T P_1 V)_ia = (V^T H_1 V)_ia / (w_i - w_a)``."""
-    w, v = np.linalg.eigh(np.asarray(h, dtype=np.float64))
+    and virtual ``a`` states only, ``(V^T P_1 V)_ia = (V^T H_1 V)_ia / (w_i - w_a)``.
+    The map is self-adjoint, so for a symmetric ``W`` the same call gives the
+    gradient of ``Tr(W P)`` with respect to ``H``.  ``eig = (w, V)`` reuses an
+    eigendecomposition of ``H`` (ascending ``w``) instead of computing one."""
+    if eig is None:
+        w, v = np.linalg.eigh(np.asarray(h, dtype=np.float64))
+    else:
+        w, v = eig
     hv = v.T @ np.asarray(h1, dtype=np.float64) @ v
     m = np.zeros_like(hv)
     occ = slice(0, n_occ)

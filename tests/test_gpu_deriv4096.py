@@ -1,0 +1,128 @@
+"""Full-size derivative parity: water box of 682 molecules zero-padded to
+N = 4096, n_occ = 2728, with the tape checkpointing every 4th iterate.  The
+GPU's JVP response P1 = dP/dH [H1] and adjoint G = d Tr(W P)/dH are compared
+with stored samples of FP64 density-matrix perturbation theory (written by
+tests/golden/make_golden.py from the oracle; the stored central finite
+difference of Tr(W P) pins that theory), plus properties that hold at any
+size: the dot test <W, P1> = <G, H1>, Tr P1 = 0, and the occupied-occupied
+block P P1 P = 0.  Also the literal half-filling n_occ = N/2 of this
+workload, which falls inside the exactly degenerate -0.5 level (zero gap):
+the solver must report that it did not converge."""
+
+import math
+import os
+
+import numpy as np
+import pytest
+
+from gpu_util import banner
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "water_m682_n4096_deriv.npz")
+
+# P against the exact step function: the c3 tolerances (same model, same gap).
+P_TOL = {"fp32": 3e-6, "bf16x3": 5e-5}
+# Derivative against perturbation theory (relative, sampled): the network
+# stops at e_n < 1e-5, ~1e-6 away from the step function; FP32 / split
+# rounding of the iterates adds the rest (observed on the small water box:
+# 2e-5 FP32, 1.1e-4 BF16x3).
+D_TOL = {"fp32": 1e-4, "bf16x3": 1e-3}
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+
+    import paper_2107_02737_amd as pk
+    from workloads import symmetric_normal, water_box_hamiltonian
+    g = np.load(GOLDEN)
+    n, m = int(g["n"]), int(g["molecules"])
+    h = water_box_hamiltonian(m, seed=int(g["seed"]), n_pad=n).astype(np.float32)
+    h1 = symmetric_normal(n, int(g["seed_h1"]), std=float(g["h1_std"]), n_real=6 * m).astype(np.float32)
+    w = symmetric_normal(n, int(g["seed_w"]), n_real=6 * m).astype(np.float32)
+    for a, key in ((h, "h_sum"), (h1, "h1_sum"), (w, "w_sum")):
+        assert abs(float(a.astype(np.float64).sum()) - float(g[key])) <= 1e-9 * float(np.abs(a).sum())
+    pk.load_library()
+    dev = {k: torch.from_numpy(v).to("cuda") for k, v in (("H", h), ("H1", h1), ("W", w))}
+    return pk, g, dev
+
+
+def _sampled(t, g, prefix):
+    """(sampled relative error, estimated ||t - ref||_F / sqrt(N)) over the
+    stored diagonal and pairs."""
+    import torch
+    pi = torch.from_numpy(np.asarray(g["pair_i"], dtype=np.int64)).cuda()
+    pj = torch.from_numpy(np.asarray(g["pair_j"], dtype=np.int64)).cuda()
+    got = np.concatenate([torch.diagonal(t).double().cpu().numpy(),
+                          t[pi, pj].double().cpu().numpy()])
+    ref = np.concatenate([g[f"{prefix}_diag"], g[f"{prefix}_pair"]])
+    d = got - ref
+    n = int(g["n"])
+    pd = d[n:]
+    return float(np.linalg.norm(d) / np.linalg.norm(ref)), math.sqrt(n * float(np.mean(pd * pd)))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_deriv_4096(setup, precision):
+    import torch
+    pk, g, dev = setup
+    n, n_occ = int(g["n"]), int(g["n_occ"])
+    banner(f"water N={n} derivatives {precision} refine=fp32 checkpoint 4")
+    P, info = pk.density(dev["H"], n_occ, precision=precision, refine="fp32", checkpoint_every=4,
+                         return_info=True)
+    assert info["converged"] == 1
+    assert info["eps_min"] == pytest.approx(float(g["eps_min"]), rel=1e-12)
+    assert info["eps_max"] == pytest.approx(float(g["eps_max"]), rel=1e-12)
+    _, p_err = _sampled(P, g, "p")
+    P1 = torch.empty_like(P)
+    pk.sp2_jvp(info["workspace"], dev["H1"], P1)
+    G = torch.empty_like(P)
+    pk.sp2_vjp(info["workspace"], dev["W"], G)
+    torch.cuda.synchronize()
+    j_rel, _ = _sampled(P1, g, "p1")
+    g_rel, _ = _sampled(G, g, "g")
+    w_p1 = float((dev["W"].double() * P1.double()).sum().item())
+    g_h1 = float((G.double() * dev["H1"].double()).sum().item())
+    tr_p1 = float(torch.trace(P1.double()).item())
+    p1_fro = float(torch.linalg.norm(P1.double()).item())
+    occ = (P.double() @ P1.double()) @ P.double()
+    occ_rel = float(torch.linalg.norm(occ).item()) / p1_fro
+    print(f"  n_iter={info['n_iter']} P err~{p_err:.2e} jvp rel={j_rel:.2e} vjp rel={g_rel:.2e} "
+          f"<W,P1>={w_p1:.8e} (DMPT {float(g['w_dot_p1']):.8e}, FD {float(g['w_dot_p1_fd']):.8e}) "
+          f"<G,H1>={g_h1:.8e} TrP1={tr_p1:.2e} |PP1P|/|P1|={occ_rel:.2e}", flush=True)
+    assert p_err <= P_TOL[precision]
+    assert j_rel <= D_TOL[precision]
+    assert g_rel <= D_TOL[precision]
+    # Inner products are sums of N^2 terms of both signs: their error is
+    # bounded on the Cauchy-Schwarz scale |W| |P1| (resp. |G| |H1|), not on
+    # their (much smaller) value.
+    w_fro = float(torch.linalg.norm(dev["W"].double()).item())
+    h1_fro = float(torch.linalg.norm(dev["H1"].double()).item())
+    cs = max(w_fro * float(g["p1_fro"]), float(g["g_fro"]) * h1_fro)
+    print(f"  inner-product errors / Cauchy-Schwarz scale: DMPT {abs(w_p1 - float(g['w_dot_p1'])) / cs:.2e} "
+          f"FD {abs(w_p1 - float(g['w_dot_p1_fd'])) / cs:.2e} dot test {abs(w_p1 - g_h1) / cs:.2e}",
+          flush=True)
+    assert abs(w_p1 - float(g["w_dot_p1"])) <= D_TOL[precision] * cs
+    assert abs(w_p1 - float(g["w_dot_p1_fd"])) <= D_TOL[precision] * cs
+    # properties at any size
+    assert abs(w_p1 - g_h1) <= 1e-4 * cs
+    assert abs(tr_p1) <= D_TOL[precision] * p1_fro
+    assert occ_rel <= D_TOL[precision]
+    assert abs(p1_fro - float(g["p1_fro"])) <= D_TOL[precision] * float(g["p1_fro"])
+
+
+def test_half_filling_in_degenerate_level_does_not_converge(setup):
+    pk, g, dev = setup
+    n = int(g["n"])
+    banner(f"water N={n} n_occ={n // 2} (inside the degenerate level)")
+    opt = pk.make_options("bf16x3", "fp32", max_iter=60)
+    P = dev["H"].new_empty(dev["H"].shape)
+    st, info, br = pk.sp2_density_ex(dev["H"], n // 2, opt, P, pk.allocate_workspace(n, opt))
+    print(f"  status={st} n_iter={info.n_iter} trace={info.trace:.4f} idem_err={info.idem_err:.3e}",
+          flush=True)
+    assert st == 3 and info.converged == 0 and info.n_iter == 60
+    # the degenerate manifold cannot be split: the trace approaches n_occ, the
+    # idempotency error stays large
+    assert info.idem_err > 1.0

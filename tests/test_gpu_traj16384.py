@@ -1,0 +1,135 @@
+"""Full-size trajectory workload: water box of 2730 molecules zero-padded to
+N = 16384, n_occ = 10920, H(t) = H0 + a_t H_p (a_t = 0.01 sin(0.1 t)) formed
+on the device in FP32 exactly as the stored values assume (one FP32 product,
+one FP32 sum).  The steps are independent solves; the test runs the first
+and the last step of the 100-step sequence, the adjoint on the last step
+with the tape checkpointing every 4th iterate, and a few steps in between
+for the drift of Tr P and of the idempotency.  Compared with stored samples
+of the exact density matrix and of perturbation theory (FP64 oracle,
+tests/golden/make_golden.py) and with properties that hold at any size."""
+
+import math
+import os
+
+import numpy as np
+import pytest
+
+from gpu_util import banner
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "water_m2730_n16384_traj.npz")
+P_TOL = 5e-5          # BF16x3 + FP32 refinement, as at N = 6144 (same model and gap)
+G_TOL = 3e-3          # adjoint of the split network against perturbation theory
+
+
+def coefficient(t):
+    return np.float32(0.01 * math.sin(0.1 * t))
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+
+    import paper_2107_02737_amd as pk
+    from workloads import symmetric_normal, trajectory_perturbation, water_box_hamiltonian
+    if not os.path.exists(GOLDEN):
+        pytest.skip("stored trajectory values missing (tests/golden/make_golden.py traj16384)")
+    g = np.load(GOLDEN)
+    n, m = int(g["n"]), int(g["molecules"])
+    banner(f"trajectory N={n}: generating H0, H_p, W on the host")
+    h0 = water_box_hamiltonian(m, seed=int(g["seed"]), n_pad=n, dtype=np.float32)
+    assert abs(float(h0.astype(np.float64).sum()) - float(g["h0_sum"])) <= 1e-9 * float(np.abs(h0).sum())
+    H0 = torch.from_numpy(h0).to("cuda")
+    del h0
+    hp = trajectory_perturbation(n, int(g["seed_hp"]), n_real=6 * m, dtype=np.float32)
+    Hp = torch.from_numpy(hp).to("cuda")
+    del hp
+    w = symmetric_normal(n, int(g["seed_w"]), n_real=6 * m, dtype=np.float32)
+    W = torch.from_numpy(w).to("cuda")
+    del w
+    pk.load_library()
+    return pk, g, H0, Hp, W
+
+
+def hamiltonian_at(H0, Hp, t):
+    import torch
+    return torch.add(H0, torch.mul(Hp, float(coefficient(t))))
+
+
+def _sampled_err(t, g, prefix):
+    import torch
+    n = int(g["n"])
+    pi = torch.from_numpy(np.asarray(g["pair_i"], dtype=np.int64)).cuda()
+    pj = torch.from_numpy(np.asarray(g["pair_j"], dtype=np.int64)).cuda()
+    pair = t[pi, pj].double().cpu().numpy() - g[f"{prefix}_pair"]
+    diag = torch.diagonal(t).double().cpu().numpy() - g[f"{prefix}_diag"]
+    rel = math.sqrt((np.sum(pair ** 2) + np.sum(diag ** 2)) /
+                    (np.sum(g[f"{prefix}_pair"] ** 2) + np.sum(g[f"{prefix}_diag"] ** 2)))
+    return math.sqrt(n * float(np.mean(pair * pair))), rel
+
+
+def _idempotency(P):
+    return float(torch_norm(P @ P - P)) / math.sqrt(P.shape[0])
+
+
+def torch_norm(x):
+    import torch
+    return torch.linalg.norm(x.double()).item()
+
+
+def test_trajectory_first_and_last_step(setup):
+    import torch
+    pk, g, H0, Hp, W = setup
+    n, n_occ = int(g["n"]), int(g["n_occ"])
+    for t in (0, 99):
+        banner(f"trajectory N={n} t={t} bf16x3 refine=fp32")
+        H = hamiltonian_at(H0, Hp, t)
+        assert abs(float(H.double().sum().item()) - float(g[f"t{t}_h_sum"])) <= 1e-6 * n
+        P, info = pk.density(H, n_occ, precision="bf16x3", refine="fp32",
+                             checkpoint_every=4 if t == 99 else 0, return_info=True)
+        assert info["converged"] == 1
+        assert info["eps_min"] == pytest.approx(float(g[f"t{t}_eps_min"]), rel=1e-11)
+        assert info["eps_max"] == pytest.approx(float(g[f"t{t}_eps_max"]), rel=1e-11)
+        err, _ = _sampled_err(P, g, f"t{t}_p")
+        idem = _idempotency(P)
+        print(f"  n_iter={info['n_iter']} P err~{err:.2e} idem={idem:.2e} "
+              f"trace_err={abs(info['trace'] - n_occ):.2e}", flush=True)
+        assert err <= P_TOL and idem < 1e-4 and abs(info["trace"] - n_occ) < 0.1
+        assert torch.equal(P, P.T)
+        if t == 99:
+            banner(f"trajectory N={n} t=99 adjoint")
+            G = torch.empty_like(P)
+            pk.sp2_vjp(info["workspace"], W, G)
+            torch.cuda.synchronize()
+            _, g_rel = _sampled_err(G, g, "t99_g")
+            g_fro = torch_norm(G)
+            print(f"  adjoint rel (sampled)={g_rel:.2e} |G|={g_fro:.6e} "
+                  f"(PT {float(g['t99_g_fro']):.6e})", flush=True)
+            assert g_rel <= G_TOL
+            assert abs(g_fro - float(g["t99_g_fro"])) <= G_TOL * float(g["t99_g_fro"])
+            assert torch.equal(G, G.T)
+        del P, info, H
+
+
+def test_trajectory_drift(setup):
+    """A few consecutive steps: Tr P and the idempotency must not drift."""
+    pk, g, H0, Hp, W = setup
+    n, n_occ = int(g["n"]), int(g["n_occ"])
+    opt = pk.make_options("bf16x3", "fp32")
+    ws = pk.allocate_workspace(n, opt)
+    traces, idems = [], []
+    for t in range(1, 6):
+        banner(f"trajectory N={n} step t={t}")
+        H = hamiltonian_at(H0, Hp, t)
+        P = H.new_empty(H.shape)
+        st, info, _ = pk.sp2_density_ex(H, n_occ, opt, P, ws)
+        assert st == 0
+        traces.append(info.trace - n_occ)
+        idems.append(_idempotency(P))
+        print(f"  n_iter={info.n_iter} Tr P - n_occ={traces[-1]:.2e} idem={idems[-1]:.2e}",
+              flush=True)
+        del P, H
+    assert max(abs(x) for x in traces) < 0.1
+    assert max(idems) < 1e-4
