@@ -48,6 +48,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-layers", type=int, default=4,
                     help="FP64 oracle layers timed for the CPU baseline sample")
+    ap.add_argument("--trajectory", type=int, default=0, metavar="STEPS",
+                    help="instead of the benchmark: run STEPS steps of the N=16384 trajectory "
+                         "workload H(t) = H0 + 0.01 sin(0.1 t) H_p (adjoint on the last step) "
+                         "and print per-step times and the drift of Tr P and idempotency")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM traffic counters)")
     return ap.parse_args()
@@ -86,6 +90,65 @@ def measured_traffic(precision):
     return float(fields["traffic_bytes_per_launch"])
 
 
+def trajectory(steps, precision, refine):
+    """Trajectory workload: water box of 2730 molecules zero-padded to
+    N = 16384, n_occ = 10920; H(t) = H0 + fl32(a_t H_p), a_t = 0.01 sin(0.1 t),
+    formed on the device; every step an independent split-precision solve,
+    the last one with the tape (checkpoint every 4th iterate) and the adjoint
+    d Tr(W P)/dH.  Solve times from HIP events on the solve's stream."""
+    import torch
+
+    import paper_2107_02737_amd as pk
+    from workloads import symmetric_normal, trajectory_perturbation, water_box_hamiltonian
+    m, n, n_occ = 2730, 16384, 10920
+    t0 = time.perf_counter()
+    H0 = torch.from_numpy(water_box_hamiltonian(m, seed=0, n_pad=n, dtype=np.float32)).cuda()
+    Hp = torch.from_numpy(trajectory_perturbation(n, 3, n_real=6 * m, dtype=np.float32)).cuda()
+    W = torch.from_numpy(symmetric_normal(n, 1, n_real=6 * m, dtype=np.float32)).cuda()
+    print(f"# trajectory inputs ready ({time.perf_counter() - t0:.0f} s)", file=sys.stderr, flush=True)
+    pk.load_library()
+    opt = pk.make_options(precision, refine)
+    opt_tape = pk.make_options(precision, refine, checkpoint_every=4)
+    ws = pk.allocate_workspace(n, opt_tape)
+    P = torch.empty_like(H0)
+    times, drift_tr, drift_idem, layers = [], [], [], []
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    adj_ms = None
+    for t in range(steps):
+        H = torch.add(H0, torch.mul(Hp, float(np.float32(0.01 * math.sin(0.1 * t)))))
+        last = t == steps - 1
+        torch.cuda.synchronize()
+        ev0.record()
+        st, info, _ = pk.sp2_density_ex(H, n_occ, opt_tape if last else opt, P, ws)
+        ev1.record()
+        torch.cuda.synchronize()
+        times.append(ev0.elapsed_time(ev1))
+        layers.append(info.n_iter)
+        drift_tr.append(info.trace - n_occ)
+        drift_idem.append(float(torch.linalg.norm((P @ P - P).double()).item()) / math.sqrt(n))
+        if last:
+            G = torch.empty_like(P)
+            ev0.record()
+            pk.sp2_vjp(ws, W, G)
+            ev1.record()
+            torch.cuda.synchronize()
+            adj_ms = ev0.elapsed_time(ev1)
+        if t % 10 == 0 or last:
+            print(f"# t={t} status={st} n_iter={info.n_iter} {times[-1]:.1f} ms "
+                  f"TrP-n={drift_tr[-1]:.2e} idem={drift_idem[-1]:.2e}", file=sys.stderr, flush=True)
+        del H
+    tt = np.array(times)
+    print(json.dumps({
+        "workload": f"trajectory: water box {m} molecules zero-padded to N={n}, n_occ={n_occ}, "
+                    f"H(t)=H0+0.01 sin(0.1t) H_p, {steps} steps, {precision} + {refine} refinement",
+        "steps": steps, "ms_per_step_mean": float(tt.mean()), "ms_p10": float(np.percentile(tt, 10)),
+        "ms_p90": float(np.percentile(tt, 90)), "layers": [min(layers), max(layers)],
+        "trace_drift": [float(min(drift_tr)), float(max(drift_tr))],
+        "idempotency": [float(min(drift_idem)), float(max(drift_idem))],
+        "adjoint_ms_last_step": adj_ms,
+        "solve_ms_last_step_with_tape": float(tt[-1])}), flush=True)
+
+
 def timed_solves(pk, H, n_occ, precision, refine, steps, warmup, time_layers):
     import torch
     opt = pk.make_options(precision, refine, time_layers=time_layers)
@@ -95,12 +158,20 @@ def timed_solves(pk, H, n_occ, precision, refine, steps, warmup, time_layers):
         pk.sp2_density_ex(H, n_occ, opt, P, ws)
     torch.cuda.synchronize()
     infos = []
+    stream = torch.cuda.current_stream()
+    events = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
-    for _ in range(steps):
+    events[0].record(stream)
+    for k in range(steps):
         st, info, br = pk.sp2_density_ex(H, n_occ, opt, P, ws)
+        events[k + 1].record(stream)
         infos.append(info.as_dict())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    # per-solve durations between consecutive events on the solve stream
+    per = np.array([events[k].elapsed_time(events[k + 1]) for k in range(steps)])
+    for d, ms in zip(infos, per):
+        d["solve_ms"] = float(ms)
     return P, infos, (t1 - t0) / steps
 
 
@@ -175,6 +246,9 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
+    if args.trajectory:
+        trajectory(args.trajectory, args.precision, args.refine)
+        return
     import torch
 
     import paper_2107_02737_amd as pk
@@ -192,6 +266,7 @@ def main():
     P, infos, sec = timed_solves(pk, H, n_occ, args.precision, args.refine, args.steps,
                                  args.warmup, True)
     n_iter = infos[-1]["n_iter"]
+    solve_ms = np.array([d["solve_ms"] for d in infos])
     prods = PRODUCTS[args.precision]
     nref = 2 if args.refine != "none" else 0
     eff_flop = (n_iter * prods + nref) * 2.0 * n ** 3
@@ -223,6 +298,8 @@ def main():
                    "n": n, "n_occ": n_occ, "precision": args.precision, "refine": args.refine,
                    "parallelism": "single GPU"},
         "n_iter": n_iter,
+        "solve_ms": {"median": float(np.median(solve_ms)), "p10": float(np.percentile(solve_ms, 10)),
+                     "p90": float(np.percentile(solve_ms, 90)), "source": "HIP events per solve"},
         "effective_tflops": eff_flop / sec / 1e12,
         "error_vs_oracle": err,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
