@@ -408,33 +408,55 @@ __device__ __forceinline__ void sym_epilogue_lds(const f32x16 (&acc)[MI][NI], co
 // ---------------------------------------------------------------------------
 // 16-bit split product.  256 x 256 output tile per work-group of 4 waves
 // (2 x 2, each 128 x 128 = 4 x 4 blocks of 32x32 MFMA), one wave per SIMD
-// with the 256 accumulators in AGPRs.  K advances 32 at a time through a
-// two-stage LDS ring filled by global_load_lds DMA straight from the
-// K-tiled planes (16 KB per plane and K step).  Fragments are double
-// buffered in registers: the barrier of each K step sits between two MFMA
-// clusters whose operands are already loaded, and the LDS reads of the next
-// half step are interleaved 1:3 (1:2 for one product) with the MFMAs.
+// with the 256 accumulators in AGPRs.  K advances 16 at a time through a
+// four-slot LDS ring (32 KB per slot: A hi, A lo, B hi, B lo) filled by
+// global_load_lds DMA straight from the K-tiled planes, four K steps ahead:
+// while one slot is consumed, up to three (96 KB) are in flight, and each
+// wave waits only for the oldest of its outstanding copies.  Fragments are
+// double buffered in registers: one barrier per K step, between the MFMA
+// clusters, and the LDS reads of the next K step are interleaved 1:3 (1:2
+// for one product) with the MFMAs of the current one.
 // ---------------------------------------------------------------------------
 
 // One 16-byte chunk per lane from global memory into LDS at m0 + 16 * lane.
 // Issued as inline assembly so that the compiler does not wait on it before
 // every LDS read; the kernel waits for the DMA explicitly (vmcnt) before
-// the barrier that publishes a stage.
+// the barrier that publishes a slot.
 __device__ __forceinline__ void dma_chunk(uint32_t off, const void* base, uint32_t m0) {
   asm volatile("s_mov_b32 m0, %2\n\tglobal_load_lds_dwordx4 %0, %1" ::"v"(off), "s"(base), "s"(m0)
                : "memory", "m0");
 }
 
-__device__ __forceinline__ void wait_vmem_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
+__device__ __forceinline__ void wait_vmem_all() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Wait until at most `later` K steps of this wave's DMA (C copies each) are
+// outstanding, and for its own LDS reads.
+template <int C>
+__device__ __forceinline__ void wait_ring(int later) {
+  static_assert(C == 4 || C == 8, "copies per K step");
+  if (later >= 3) {
+    if constexpr (C == 8) asm volatile("s_waitcnt vmcnt(24) lgkmcnt(0)" ::: "memory");
+    else asm volatile("s_waitcnt vmcnt(12) lgkmcnt(0)" ::: "memory");
+  } else if (later == 2) {
+    if constexpr (C == 8) asm volatile("s_waitcnt vmcnt(16) lgkmcnt(0)" ::: "memory");
+    else asm volatile("s_waitcnt vmcnt(8) lgkmcnt(0)" ::: "memory");
+  } else if (later == 1) {
+    if constexpr (C == 8) asm volatile("s_waitcnt vmcnt(8) lgkmcnt(0)" ::: "memory");
+    else asm volatile("s_waitcnt vmcnt(4) lgkmcnt(0)" ::: "memory");
+  } else {
+    asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+  }
+}
 
 template <int KIND>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void k_sym_split(SplitArgs p) {
-  constexpr int BM = 256, NT = 256, BK = 32, MI = 4, NI = 4, TM = 128, TN = 128;
+  constexpr int BM = 256, NT = 256, BK = 16, NS = 4, MI = 4, NI = 4, TM = 128, TN = 128;
   constexpr bool kLo = KIND != kBF16X1;
-  constexpr int PLANE_B = BM * BK * 2;   // bytes of one plane per stage (16 KB)
-  constexpr int STAGE_B = 4 * PLANE_B;   // A hi, A lo, B hi, B lo
-  // two operand stages (128 KB), reused as the [128][257] FP32 epilogue image
+  constexpr int PLANE_B = BM * BK * 2;   // bytes of one plane per K step (8 KB)
+  constexpr int SLOT_B = 4 * PLANE_B;    // A hi, A lo, B hi, B lo
+  static_assert(NS * SLOT_B <= 128 * kEpiLd * 4, "ring exceeds the LDS image");
+  // four operand slots (128 KB), reused as the [128][257] FP32 epilogue image
   __shared__ __attribute__((aligned(1024))) uint16_t lds[128 * kEpiLd * 2];
   __shared__ double red[2 * (NT / kWave)];
 
@@ -448,24 +470,28 @@ void k_sym_split(SplitArgs p) {
   const int64_t np = p.epi.np;
   const int KT = static_cast<int>(np / BK);
   int tile, ti, tj, kb, ke, tail, piece;
-  work_of(p.dc, KT, tile, ti, tj, kb, ke, tail, piece);
+  work_of(p.dc, KT / 2, tile, ti, tj, kb, ke, tail, piece);
+  kb *= 2;
+  ke *= 2;
   const int tid = threadIdx.x, lane = tid & (kWave - 1);
   const int w = __builtin_amdgcn_readfirstlane(tid / kWave);
   const int wm = w >> 1, wn = w & 1;
 
-  // DMA: plane block (panel P, K step kt) starts at element (P*KT + kt)*8192;
-  // this wave copies its 1 KB pieces (i*4 + w), i = 0..3, of each plane.
-  const uint16_t* ga_hi = p.a_hi + int64_t(ti) * KT * 8192;
-  const uint16_t* ga_lo = kLo ? p.a_lo + int64_t(ti) * KT * 8192 : nullptr;
-  const uint16_t* gb_hi = p.b_hi + int64_t(tj) * KT * 8192;
-  const uint16_t* gb_lo = kLo ? p.b_lo + int64_t(tj) * KT * 8192 : nullptr;
+  // DMA: plane block (panel P, K step kt) starts at element (P*KT + kt)*4096;
+  // this wave copies the 1 KB pieces (i*4 + w), i = 0..1, of each plane.
+  const uint16_t* ga_hi = p.a_hi + int64_t(ti) * KT * 4096;
+  const uint16_t* ga_lo = kLo ? p.a_lo + int64_t(ti) * KT * 4096 : nullptr;
+  const uint16_t* gb_hi = p.b_hi + int64_t(tj) * KT * 4096;
+  const uint16_t* gb_lo = kLo ? p.b_lo + int64_t(tj) * KT * 4096 : nullptr;
   const uint32_t lds0 = static_cast<uint32_t>(
       reinterpret_cast<uintptr_t>((__attribute__((address_space(3))) uint16_t*)(lds)));
-#define SP2_DMA_STAGE(STAGE, KTI)                                                         \
+  // Per K step every wave issues kCopies copies (2 per plane).
+  constexpr int kCopies = kLo ? 8 : 4;
+#define SP2_DMA_STAGE(SLOT, KTI)                                                          \
   {                                                                                       \
-    const int64_t kofs_ = int64_t(KTI) * 8192;                                            \
-    const uint32_t m0s_ = lds0 + (STAGE) * STAGE_B + w * 1024;                            \
-    _Pragma("clang loop unroll(full)") for (int i = 0; i < 4; ++i) {                      \
+    const int64_t kofs_ = int64_t(KTI) * 4096;                                            \
+    const uint32_t m0s_ = lds0 + (SLOT) * SLOT_B + w * 1024;                              \
+    _Pragma("clang loop unroll(full)") for (int i = 0; i < 2; ++i) {                      \
       const uint32_t off_ = static_cast<uint32_t>(((i * 4 + w) * 64 + lane) * 16);        \
       dma_chunk(off_, ga_hi + kofs_, m0s_ + 0 * PLANE_B + i * 4096);                      \
       dma_chunk(off_, gb_hi + kofs_, m0s_ + 2 * PLANE_B + i * 4096);                      \
@@ -476,14 +502,12 @@ void k_sym_split(SplitArgs p) {
     }                                                                                     \
   }
 
-  // Fragment addresses (bytes within a stage).  Row r of a 32-row block,
-  // h = lane/32; half step s reads logical chunk 2s + h, stored at
-  // (2s + h) ^ plane_swz(r) (plane_swz only sees the low 5 bits of the row).
+  // Fragment addresses (bytes within a slot).  Row r of a 32-row block,
+  // h = lane/32 reads logical chunk h, stored at h ^ plane_swz(r)
+  // (plane_swz only sees rows bits 2-3, which a multiple of 32 rows keeps).
   const int r = lane & 31, h = lane >> 5, sw = plane_swz(r);
-  const int fa0 = (wm * TM + r) * 64 + ((h ^ sw) << 4);
-  const int fa1 = (wm * TM + r) * 64 + (((2 + h) ^ sw) << 4);
-  const int fb0 = (wn * TN + r) * 64 + ((h ^ sw) << 4);
-  const int fb1 = (wn * TN + r) * 64 + (((2 + h) ^ sw) << 4);
+  const int fa = (wm * TM + r) * 32 + ((h ^ sw) << 4);
+  const int fb = (wn * TN + r) * 32 + ((h ^ sw) << 4);
   const char* L = reinterpret_cast<const char*>(lds);
 
   f32x16 acc[MI][NI];
@@ -497,18 +521,18 @@ void k_sym_split(SplitArgs p) {
   u32x4 Ah0[MI], Al0[MI], Bh0[NI], Bl0[NI];
   u32x4 Ah1[MI], Al1[MI], Bh1[NI], Bl1[NI];
 
-#define SP2_FRAG(AH, AL, BH, BL, STAGE, FA, FB)                                           \
+#define SP2_FRAG(AH, AL, BH, BL, SLOT)                                                    \
   {                                                                                       \
-    const char* S_ = L + (STAGE) * STAGE_B;                                               \
+    const char* S_ = L + (SLOT) * SLOT_B;                                                 \
     _Pragma("clang loop unroll(full)") for (int mi = 0; mi < MI; ++mi)                    \
-      AH[mi] = *reinterpret_cast<const u32x4*>(S_ + 0 * PLANE_B + (FA) + mi * 2048); \
+      AH[mi] = *reinterpret_cast<const u32x4*>(S_ + 0 * PLANE_B + fa + mi * 1024);        \
     _Pragma("clang loop unroll(full)") for (int ni = 0; ni < NI; ++ni)                    \
-      BH[ni] = *reinterpret_cast<const u32x4*>(S_ + 2 * PLANE_B + (FB) + ni * 2048); \
+      BH[ni] = *reinterpret_cast<const u32x4*>(S_ + 2 * PLANE_B + fb + ni * 1024);        \
     if constexpr (kLo) {                                                                  \
       _Pragma("clang loop unroll(full)") for (int ni = 0; ni < NI; ++ni)                  \
-        BL[ni] = *reinterpret_cast<const u32x4*>(S_ + 3 * PLANE_B + (FB) + ni * 2048); \
+        BL[ni] = *reinterpret_cast<const u32x4*>(S_ + 3 * PLANE_B + fb + ni * 1024);      \
       _Pragma("clang loop unroll(full)") for (int mi = 0; mi < MI; ++mi)                  \
-        AL[mi] = *reinterpret_cast<const u32x4*>(S_ + 1 * PLANE_B + (FA) + mi * 2048); \
+        AL[mi] = *reinterpret_cast<const u32x4*>(S_ + 1 * PLANE_B + fa + mi * 1024);      \
     }                                                                                     \
   }
 
@@ -542,27 +566,30 @@ void k_sym_split(SplitArgs p) {
       __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);                                  \
     }                                                                                     \
   }
+  // One K step: K step K is in registers (CUR); publish K + 1, refill the
+  // slot K came from with K + 4, compute K while reading K + 1 into NXT.
+  // After the last step the NXT reads fetch a stale slot that is never used.
+#define SP2_STEP(K, CAH, CAL, CBH, CBL, NAH, NAL, NBH, NBL)                               \
+  {                                                                                       \
+    const int k_ = (K);                                                                   \
+    wait_ring<kCopies>(min(k_ + 3, ke - 1) - (k_ + 1));                                   \
+    __syncthreads();                                                                      \
+    if (k_ + 4 < ke) SP2_DMA_STAGE((k_ - kb) & (NS - 1), k_ + 4);                         \
+    SP2_FRAG(NAH, NAL, NBH, NBL, (k_ + 1 - kb) & (NS - 1));                               \
+    SP2_MFMA(CAH, CAL, CBH, CBL);                                                         \
+    SP2_INTERLEAVE();                                                                     \
+  }
 
-  SP2_DMA_STAGE(0, kb);
-  wait_vmem_all();
+  // K ranges are whole pairs of K steps (work_of splits in units of 32).
+#pragma clang loop unroll(full)
+  for (int s = 0; s < NS; ++s)
+    if (kb + s < ke) SP2_DMA_STAGE(s, kb + s);
+  wait_ring<kCopies>(min(kb + 3, ke - 1) - kb);
   __syncthreads();
-  if (kb + 1 < ke) SP2_DMA_STAGE(1, kb + 1);
-  SP2_FRAG(Ah0, Al0, Bh0, Bl0, 0, fa0, fb0);
-  for (int kt = kb; kt < ke; ++kt) {
-    const int st = (kt - kb) & 1;
-    // first half step of K tile kt from registers; fetch its second half
-    SP2_FRAG(Ah1, Al1, Bh1, Bl1, st, fa1, fb1);
-    SP2_MFMA(Ah0, Al0, Bh0, Bl0);
-    SP2_INTERLEAVE();
-    // stage st^1 (K tile kt+1) has landed for this wave; after the barrier
-    // it has for all waves, and stage st is free for K tile kt+2
-    wait_vmem_all();
-    __syncthreads();
-    if (kt + 2 < ke) SP2_DMA_STAGE(st, kt + 2);
-    // second half step of kt from registers; fetch the first half of kt+1
-    SP2_FRAG(Ah0, Al0, Bh0, Bl0, st ^ 1, fa0, fb0);
-    SP2_MFMA(Ah1, Al1, Bh1, Bl1);
-    SP2_INTERLEAVE();
+  SP2_FRAG(Ah0, Al0, Bh0, Bl0, 0);
+  for (int kt = kb; kt < ke; kt += 2) {
+    SP2_STEP(kt, Ah0, Al0, Bh0, Bl0, Ah1, Al1, Bh1, Bl1);
+    SP2_STEP(kt + 1, Ah1, Al1, Bh1, Bl1, Ah0, Al0, Bh0, Bl0);
   }
   wait_vmem_all();
   __syncthreads();
@@ -571,6 +598,7 @@ void k_sym_split(SplitArgs p) {
 #undef SP2_MFMA1
 #undef SP2_MFMA
 #undef SP2_INTERLEAVE
+#undef SP2_STEP
   if (tail >= 0 && !reduce_tail<NT, MI, NI>(acc, p.dc, tail, piece)) return;
   sym_epilogue_lds<NT, MI, NI>(acc, p.epi, alpha, beta, ti, tj, wm, wn, lane, red, tile,
                                reinterpret_cast<float*>(lds));
