@@ -11,3 +11,5 @@ Parity status per function is stated in ``oracle/sp2_oracle.py``.
 
 from .sp2_oracle import *  # noqa: F401,F403
 from . import precision_emulation  # noqa: F401,E402
+from . import lanczos  # noqa: F401,E402
+from .lanczos import lanczos_bounds  # noqa: F401,E402

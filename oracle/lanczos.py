@@ -1,0 +1,105 @@
+"""Lanczos refinement of the spectral bounds -- TEST INFRASTRUCTURE ONLY.
+
+The paper maps the spectrum of H onto [0, 1] before the first layer
+(Section II.D) without saying how the bounds are estimated.  Gershgorin discs
+(``sp2_oracle.gershgorin_bounds``) are always valid but loose; the tighter
+the interval, the larger the mapped HOMO-LUMO gap and the fewer layers the
+network needs.  This module is the plain FP64 reference of the optional
+tightening step: ``k`` steps of the symmetric Lanczos recurrence (Golub and
+Van Loan, Matrix Computations, Section 10.1) from a pseudo-random start
+vector, the extreme Ritz values of the tridiagonal matrix, each widened by
+its Ritz residual norm ``|beta_k s_k|`` and a relative safety margin, then
+clipped to the Gershgorin interval.
+
+Start vector: ``u_i = (z_i >> 11) * 2^-53 - 1/2`` with ``z_i`` the
+SplitMix64 output (Steele, Lea and Flood, OOPSLA 2014) of state
+``seed + (i + 1) * 0x9E3779B97F4A7C15``, normalised; both sides of the
+comparison implement this generator from its published definition.
+
+Pins (tests/test_oracle_lanczos.py): SplitMix64's published first outputs
+for seed 0; the Lanczos relation ``H V = V T + beta_k v_{k+1} e_k^T`` and
+orthonormality of ``V`` on small inputs; Ritz values equal to the
+eigenvalues when ``k = N`` on a matrix with N distinct eigenvalues; the
+residual formula against ``||H y - theta y||`` computed explicitly; and
+enclosure of the spectrum (``numpy.linalg.eigvalsh``) on every workload.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+from .sp2_oracle import gershgorin_bounds
+
+SPLITMIX_GAMMA = 0x9E3779B97F4A7C15
+_M64 = (1 << 64) - 1
+
+
+def splitmix64(seed, count):
+    """The first ``count`` SplitMix64 outputs of state ``seed`` (Python ints)."""
+    out = []
+    for i in range(count):
+        z = (seed + (i + 1) * SPLITMIX_GAMMA) & _M64
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+        out.append(z ^ (z >> 31))
+    return out
+
+
+def start_vector(n, seed=0):
+    """Normalised start vector ``u / ||u||`` with ``u_i`` uniform in [-1/2, 1/2)."""
+    u = np.array([(z >> 11) * 2.0 ** -53 - 0.5 for z in splitmix64(seed, n)])
+    return u / np.linalg.norm(u)
+
+
+def lanczos(h, steps, seed=0, return_vectors=False):
+    """``steps`` steps of the Lanczos recurrence on the symmetric ``h`` (FP64,
+    no reorthogonalisation): ``w = H v_j - alpha_j v_j - beta_{j-1} v_{j-1}``,
+    ``alpha_j = v_j . H v_j``, ``beta_j = ||w||``, ``v_{j+1} = w / beta_j``.
+    Stops early when ``beta_j`` vanishes (an invariant subspace was found).
+    Returns ``(alpha, beta)`` (``beta[-1]`` couples to the next, unused
+    vector), plus the Lanczos vectors ``V`` (N x (k+1)) if asked."""
+    h = np.asarray(h, dtype=np.float64)
+    n = h.shape[0]
+    v = start_vector(n, seed)
+    v_prev = np.zeros(n)
+    b_prev = 0.0
+    alpha, beta, vecs = [], [], [v]
+    for _ in range(steps):
+        w = h @ v
+        a = float(v @ w)
+        w = w - a * v - b_prev * v_prev
+        b = float(np.linalg.norm(w))
+        alpha.append(a)
+        beta.append(b)
+        if not b > 1e-300:
+            break
+        v_prev, v = v, w / b
+        b_prev = b
+        vecs.append(v)
+    if return_vectors:
+        return np.array(alpha), np.array(beta), np.array(vecs).T
+    return np.array(alpha), np.array(beta)
+
+
+def ritz_extremes(alpha, beta):
+    """Smallest and largest eigenvalue of the Lanczos tridiagonal matrix and
+    the residual norm ``|beta_k s_k|`` of each Ritz pair (``s_k``: last entry
+    of the normalised eigenvector).  Returns ``(th_min, r_min, th_max, r_max)``."""
+    k = len(alpha)
+    t = np.diag(alpha) + np.diag(beta[:k - 1], 1) + np.diag(beta[:k - 1], -1)
+    th, s = np.linalg.eigh(t)
+    r = np.abs(beta[k - 1] * s[-1, :])
+    return float(th[0]), float(r[0]), float(th[-1]), float(r[-1])
+
+
+def lanczos_bounds(h, steps, seed=0, margin=0.01):
+    """Refined spectral bounds: ``[th_min - r_min - m, th_max + r_max + m]``
+    with ``m = margin * (th_max - th_min)``, clipped to the Gershgorin
+    interval (which stays the answer when ``steps`` is 0)."""
+    g_lo, g_hi = gershgorin_bounds(h)
+    if steps <= 0 or not g_hi > g_lo:
+        return g_lo, g_hi
+    alpha, beta = lanczos(h, steps, seed)
+    th_lo, r_lo, th_hi, r_hi = ritz_extremes(alpha, beta)
+    m = margin * (th_hi - th_lo)
+    return max(g_lo, th_lo - r_lo - m), min(g_hi, th_hi + r_hi + m)

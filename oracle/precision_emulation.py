@@ -39,12 +39,13 @@ def square_emulated(x, mode):
 
 
 def sp2_emulated(h, n_occ, mode, tol=1e-5, max_iter=100, stop_rule=1, stall_gate=1.0,
-                 refine=True):
+                 refine=True, bounds=None):
     """FP32-stored DNN-SP2 with the layer squares of ``mode``; the traces,
-    bounds and decisions are FP64 as on the GPU.  Returns ``(P, n_iter)``."""
+    bounds and decisions are FP64 as on the GPU.  ``bounds`` overrides the
+    Gershgorin bounds.  Returns ``(P, n_iter)``."""
     h = np.asarray(h, dtype=np.float32)
     n = h.shape[0]
-    lo_b, hi_b = gershgorin_bounds(h.astype(np.float64))
+    lo_b, hi_b = gershgorin_bounds(h.astype(np.float64)) if bounds is None else bounds
     s = ((hi_b * np.eye(n) - h.astype(np.float64)) / (hi_b - lo_b)).astype(np.float32)
     errs = []
     layers = 0
