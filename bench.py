@@ -45,6 +45,10 @@ def parse():
     ap.add_argument("--precision", default="bf16x3", choices=list(PRODUCTS))
     ap.add_argument("--refine", default="fp32", choices=["none", "fp32", "split"])
     ap.add_argument("--no-fp32-compare", action="store_true")
+    ap.add_argument("--bound-steps", type=int, default=0,
+                    help="Lanczos steps tightening the Gershgorin bounds (0: Gershgorin only)")
+    ap.add_argument("--compare-bound-steps", type=int, default=32,
+                    help="also time solves with this many Lanczos bound steps (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-layers", type=int, default=4,
                     help="FP64 oracle layers timed for the CPU baseline sample")
@@ -149,9 +153,9 @@ def trajectory(steps, precision, refine):
         "solve_ms_last_step_with_tape": float(tt[-1])}), flush=True)
 
 
-def timed_solves(pk, H, n_occ, precision, refine, steps, warmup, time_layers):
+def timed_solves(pk, H, n_occ, precision, refine, steps, warmup, time_layers, bound_steps=0):
     import torch
-    opt = pk.make_options(precision, refine, time_layers=time_layers)
+    opt = pk.make_options(precision, refine, time_layers=time_layers, bound_steps=bound_steps)
     ws = pk.allocate_workspace(H.shape[0], opt, H.device)
     P = torch.empty_like(H)
     for _ in range(warmup):
@@ -264,7 +268,7 @@ def main():
     pk.load_library()
 
     P, infos, sec = timed_solves(pk, H, n_occ, args.precision, args.refine, args.steps,
-                                 args.warmup, True)
+                                 args.warmup, True, args.bound_steps)
     n_iter = infos[-1]["n_iter"]
     solve_ms = np.array([d["solve_ms"] for d in infos])
     prods = PRODUCTS[args.precision]
@@ -296,6 +300,8 @@ def main():
         "config": {"workload": f"tight-binding water box, {m} molecules, N={n}, n_occ={n_occ}, "
                                f"seed {int(gold['seed'])}, H fp32 on device",
                    "n": n, "n_occ": n_occ, "precision": args.precision, "refine": args.refine,
+                   "bounds": "gershgorin" if args.bound_steps == 0
+                   else f"lanczos {args.bound_steps} steps",
                    "parallelism": "single GPU"},
         "n_iter": n_iter,
         "solve_ms": {"median": float(np.median(solve_ms)), "p10": float(np.percentile(solve_ms, 10)),
@@ -309,6 +315,15 @@ def main():
                      "layer_ms": layer_ms,
                      "refine_ms": float(np.mean([d["refine_ms"] for d in infos]))},
     }
+    if args.compare_bound_steps and args.compare_bound_steps != args.bound_steps:
+        Pl, linfo, lsec = timed_solves(pk, H, n_occ, args.precision, args.refine, 5, 1, True,
+                                       args.compare_bound_steps)
+        lerr = sampled_error(Pl, gold)
+        out["with_lanczos_bounds" if args.compare_bound_steps else "with_gershgorin_bounds"] = {
+            "bound_steps": args.compare_bound_steps, "solves_per_s": 1.0 / lsec,
+            "n_iter": linfo[-1]["n_iter"], "eps": [linfo[-1]["eps_min"], linfo[-1]["eps_max"]],
+            "fro_over_sqrt_n_est": lerr["fro_over_sqrt_n_est"]}
+        del Pl
     if not args.no_fp32_compare and args.precision != "fp32":
         _, finfo, fsec = timed_solves(pk, H, n_occ, "fp32", args.refine, 3, 1, True)
         f_layer_ms = float(np.mean([d["layer_ms"] / max(1, d["n_iter"]) for d in finfo]))

@@ -63,6 +63,8 @@ typedef enum { SP2_FP32 = 0, SP2_BF16X1 = 1, SP2_BF16X3 = 2, SP2_FP16X3 = 3 } sp
 typedef enum { SP2_REFINE_NONE = 0, SP2_REFINE_FP32 = 1, SP2_REFINE_SPLIT = 2 } sp2_refine;
 
 #define SP2_MAX_ITER 256
+#define SP2_MIN_BOUND_STEPS 8
+#define SP2_MAX_BOUND_STEPS 64
 #define SP2_FLAG_TIME_LAYERS 1
 
 typedef struct {
@@ -75,6 +77,10 @@ typedef struct {
                                iterate in the workspace for sp2_jvp / sp2_vjp */
   int32_t flags;            /* bit SP2_FLAG_TIME_LAYERS: time every layer launch with HIP
                                events on `stream` (fills sp2_info.layer_ms/refine_ms) */
+  int32_t bound_steps;      /* 0 (default): Gershgorin bounds.  k in SP2_MIN_BOUND_STEPS..
+                               SP2_MAX_BOUND_STEPS: tighten them with k Lanczos steps (see
+                               sp2_spectral_bounds) */
+  int32_t bound_seed;       /* SplitMix64 state of the Lanczos start vector (default 0) */
   double tol;               /* stop when e_n = |Tr S_n - ||S_n||_F^2| < tol (default 1e-5) */
   double stall_gate;        /* default 1.0 */
 } sp2_options;
@@ -84,8 +90,8 @@ typedef struct {
   int32_t converged;   /* 1 if the stop test passed */
   int32_t status;      /* sp2_status of the call */
   int32_t reserved;
-  double eps_min;      /* Gershgorin lower bound of spectrum(H), FP64 */
-  double eps_max;      /* Gershgorin upper bound */
+  double eps_min;      /* lower spectral bound used by the input layer, FP64 */
+  double eps_max;      /* upper spectral bound */
   double trace;        /* Tr P of the returned P, FP64 sum of FP32 entries */
   double idem_err;     /* |Tr P - ||P||_F^2| of the returned P */
   double layer_ms;     /* with SP2_FLAG_TIME_LAYERS: summed event time of the n_iter applied
@@ -151,6 +157,28 @@ sp2_status sp2_vjp(void* workspace, size_t ws_bytes, const float* W, int64_t ld,
  * SP2_ERR_NONFINITE when H holds NaN/Inf. */
 sp2_status sp2_bounds(const float* H, int64_t n, int64_t ld, double* eps_min, double* eps_max,
                       void* workspace, size_t ws_bytes, void* stream);
+
+/* Tightened spectral bounds (the paper maps the spectrum onto [0, 1] in
+ * Section II.D without fixing how the bounds are estimated).  Starting from
+ * the Gershgorin interval of sp2_bounds, `steps` (SP2_MIN_BOUND_STEPS..SP2_MAX_BOUND_STEPS)
+ * steps of the symmetric Lanczos recurrence run in FP64 (products of the
+ * FP32 H with FP64 vectors) from the start vector u / |u|,
+ * u_i = (z_i >> 11) 2^-53 - 1/2, z_i the SplitMix64 output of state
+ * seed + (i+1) 0x9E3779B97F4A7C15.  The extreme eigenvalues th of the
+ * Lanczos tridiagonal matrix, widened by their Ritz residual norms
+ * |beta_k s_k| and by 1% of th_max - th_min, replace the Gershgorin bounds
+ * where tighter.  This is what sp2_density_ex runs when opt->bound_steps > 0.
+ * The widened Ritz interval is an estimate, not a proof: a Ritz value that
+ * has not converged can sit inside the spectrum by more than its residual,
+ * which is why fewer than SP2_MIN_BOUND_STEPS steps are refused (16 or more
+ * are advisable for broad spectra).  A layer sequence started from an
+ * interval that misses part of the spectrum ends in SP2_ERR_NOT_CONVERGED
+ * rather than in a silently wrong P.
+ * Outputs are host doubles; blocks until done.  Returns SP2_ERR_NONFINITE
+ * when H holds NaN/Inf, SP2_ERR_INVALID_ARG for steps outside the range. */
+sp2_status sp2_spectral_bounds(const float* H, int64_t n, int64_t ld, int32_t steps,
+                               int32_t seed, double* eps_min, double* eps_max, void* workspace,
+                               size_t ws_bytes, void* stream);
 
 /* Dual representation of Eq. (20)-(21): hi = R[X], lo = R[X - hi] with
  * round-to-nearest-even R into bfloat16 (precision SP2_BF16X3/SP2_BF16X1)

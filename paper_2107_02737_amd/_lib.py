@@ -39,12 +39,14 @@ SP2_MAX_ITER = 256
 
 # Every symbol include/sp2.h declares.
 EXPORTED = ["sp2_default_options", "sp2_workspace_bytes", "sp2_density", "sp2_density_ex",
-            "sp2_jvp", "sp2_vjp", "sp2_bounds", "sp2_split", "sp2_layer", "sp2_last_error"]
+            "sp2_jvp", "sp2_vjp", "sp2_bounds", "sp2_spectral_bounds", "sp2_split", "sp2_layer",
+            "sp2_last_error"]
 
 
 class sp2_options(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("refine", c_int32), ("max_iter", c_int32),
                 ("stop_rule", c_int32), ("checkpoint_every", c_int32), ("flags", c_int32),
+                ("bound_steps", c_int32), ("bound_seed", c_int32),
                 ("tol", c_double), ("stall_gate", c_double)]
 
 
@@ -95,6 +97,10 @@ def load_library(path=None):
     lib.sp2_bounds.argtypes = [vp, c_int64, c_int64, ctypes.POINTER(c_double),
                                ctypes.POINTER(c_double), vp, c_size_t, vp]
     lib.sp2_bounds.restype = c_int32
+    lib.sp2_spectral_bounds.argtypes = [vp, c_int64, c_int64, c_int32, c_int32,
+                                        ctypes.POINTER(c_double), ctypes.POINTER(c_double), vp,
+                                        c_size_t, vp]
+    lib.sp2_spectral_bounds.restype = c_int32
     lib.sp2_split.argtypes = [vp, c_int64, c_int64, c_int32, vp, vp, vp]
     lib.sp2_split.restype = c_int32
     lib.sp2_layer.argtypes = [vp, c_int64, c_int64, c_int32, c_int32, vp, vp, c_size_t, vp]
@@ -130,7 +136,8 @@ SP2_FLAG_TIME_LAYERS = 1
 
 
 def make_options(precision="bf16x3", refine="fp32", max_iter=100, stop_rule=1,
-                 checkpoint_every=0, tol=1e-5, stall_gate=1.0, time_layers=False):
+                 checkpoint_every=0, tol=1e-5, stall_gate=1.0, time_layers=False,
+                 bound_steps=0, bound_seed=0):
     lib = load_library()
     o = sp2_options()
     lib.sp2_default_options(ctypes.byref(o))
@@ -142,6 +149,8 @@ def make_options(precision="bf16x3", refine="fp32", max_iter=100, stop_rule=1,
     o.tol = float(tol)
     o.stall_gate = float(stall_gate)
     o.flags = SP2_FLAG_TIME_LAYERS if time_layers else 0
+    o.bound_steps = int(bound_steps)
+    o.bound_seed = int(bound_seed)
     return o
 
 
@@ -217,6 +226,16 @@ def sp2_bounds(H, workspace):
     _check(lib.sp2_bounds(_dev_ptr(H, name="H"), H.shape[0], H.stride(0), ctypes.byref(lo),
                           ctypes.byref(hi), c_void_p(workspace.data_ptr()), workspace.numel(),
                           _stream(H.device)))
+    return lo.value, hi.value
+
+
+def sp2_spectral_bounds(H, steps, workspace, seed=0):
+    lib = load_library()
+    lo, hi = c_double(), c_double()
+    _check(lib.sp2_spectral_bounds(_dev_ptr(H, name="H"), H.shape[0], H.stride(0), int(steps),
+                                   int(seed), ctypes.byref(lo), ctypes.byref(hi),
+                                   c_void_p(workspace.data_ptr()), workspace.numel(),
+                                   _stream(H.device)))
     return lo.value, hi.value
 
 

@@ -17,6 +17,7 @@
 #include "sp2_aux.hpp"
 #include "sp2_common.hpp"
 #include "sp2_gemm.hpp"
+#include "sp2_lanczos.hpp"
 
 using namespace sp2;
 
@@ -74,6 +75,8 @@ struct Layout {
   int nb_split, ntiles_split, nb_f32, ntiles_f32;
   int init_blocks, gersh_blocks, max_parts;
   size_t off_ctrl, off_hist, off_meta, off_parts0, off_parts1, off_gersh, off_counter, off_partial;
+  size_t off_lz, off_lzvec, off_lzpart;   // Lanczos state, 3 vectors of n doubles, partials
+  int lz_blocks;
   size_t off_slot0;     // first matrix slot
   size_t slot_bytes;
   int nslots, ntape, every;
@@ -108,6 +111,10 @@ bool make_layout(int64_t n, const sp2_options& o, Layout& L) {
   L.off_gersh = take(size_t(L.gersh_blocks) * 24);
   L.off_counter = take(size_t(kMaxTailTiles) * 4);
   L.off_partial = take(kPartialBytes);
+  L.lz_blocks = static_cast<int>((n + kLzRowsPerBlock - 1) / kLzRowsPerBlock);
+  L.off_lz = take(sizeof(LzState));
+  L.off_lzvec = take(size_t(3) * size_t(n) * 8);
+  L.off_lzpart = take(size_t(L.lz_blocks) * 8);
   L.slot_bytes = size_t(L.np) * size_t(L.np) * 4;
   L.every = o.checkpoint_every;
   // slots 0-3: S (FP32), two hi/lo plane pairs (or FP32 ping-pong), S^2 for
@@ -130,6 +137,9 @@ struct WS {
   double* gersh;
   int* counter;
   float* partial;
+  LzState* lz;
+  double* lzv;      // v, v_prev, w: n doubles each
+  double* lzpart;
   float* slotf(int i) const { return reinterpret_cast<float*>(base + L.off_slot0 + L.slot_bytes * size_t(i)); }
   uint16_t* hi(int pair) const { return reinterpret_cast<uint16_t*>(slotf(1 + pair)); }
   uint16_t* lo(int pair) const { return hi(pair) + L.np * L.np; }
@@ -150,6 +160,30 @@ void bind(WS& w, void* ws, const Layout& L) {
   w.gersh = reinterpret_cast<double*>(w.base + L.off_gersh);
   w.counter = reinterpret_cast<int*>(w.base + L.off_counter);
   w.partial = reinterpret_cast<float*>(w.base + L.off_partial);
+  w.lz = reinterpret_cast<LzState*>(w.base + L.off_lz);
+  w.lzv = reinterpret_cast<double*>(w.base + L.off_lzvec);
+  w.lzpart = reinterpret_cast<double*>(w.base + L.off_lzpart);
+}
+
+// Lanczos tightening of the Gershgorin bounds already in ctrl (no host
+// round trip; a NaN H or a degenerate spectrum leaves ctrl as it is).
+sp2_status refine_bounds(const WS& w, const float* H, int64_t n, int64_t ld, int steps,
+                         int32_t seed, hipStream_t st) {
+  double* v = w.lzv;
+  double* vp = w.lzv + n;
+  double* wv = w.lzv + 2 * n;
+  k_lz_start<<<1, kLzThreads, 0, st>>>(v, vp, n, static_cast<uint64_t>(static_cast<uint32_t>(seed)),
+                                       w.lz);
+  LAUNCH_TRY();
+  for (int j = 0; j < steps; ++j) {
+    k_lz_matvec<<<w.L.lz_blocks, 256, 0, st>>>(H, n, ld, v, wv, w.lzpart, w.lz);
+    LAUNCH_TRY();
+    k_lz_update<<<1, kLzThreads, 0, st>>>(wv, v, vp, w.lzpart, w.L.lz_blocks, n, w.lz, j);
+    LAUNCH_TRY();
+  }
+  k_lz_bounds<<<1, 64, 0, st>>>(w.lz, w.ctrl, kLzMargin);
+  LAUNCH_TRY();
+  return SP2_OK;
 }
 
 // Compute units of the current device (cached per device).
@@ -201,7 +235,9 @@ bool options_ok(const sp2_options& o) {
          o.refine <= SP2_REFINE_SPLIT && o.max_iter >= 1 && o.max_iter <= SP2_MAX_ITER &&
          (o.stop_rule == 0 || o.stop_rule == 1) && o.checkpoint_every >= 0 &&
          o.checkpoint_every <= SP2_MAX_ITER && o.tol >= 0.0 && o.stall_gate >= 0.0 &&
-         (o.flags & ~SP2_FLAG_TIME_LAYERS) == 0;
+         (o.flags & ~SP2_FLAG_TIME_LAYERS) == 0 &&
+         (o.bound_steps == 0 ||
+          (o.bound_steps >= SP2_MIN_BOUND_STEPS && o.bound_steps <= SP2_MAX_BOUND_STEPS));
 }
 
 int split_kind_of(int precision) {
@@ -539,6 +575,8 @@ sp2_status sp2_density_ex(const float* H, int64_t n, int64_t ld, int64_t n_occ,
   LAUNCH_TRY();
   k_bounds_final<<<1, 256, 0, st>>>(w.gersh, L.gersh_blocks, w.ctrl, trivial ? 1 : 0);
   LAUNCH_TRY();
+  if (!trivial && o.bound_steps > 0)
+    if ((s = refine_bounds(w, H, n, ld, o.bound_steps, o.bound_seed, st))) return s;
 
   int n_iter = 0;
   bool n_iter_even_for_refine = false;
@@ -716,6 +754,38 @@ sp2_status sp2_bounds(const float* H, int64_t n, int64_t ld, double* eps_min, do
   LAUNCH_TRY();
   k_bounds_final<<<1, 256, 0, st>>>(w.gersh, L.gersh_blocks, w.ctrl, 1);
   LAUNCH_TRY();
+  if (sp2_status s = read_back(w, hm, false, st)) return s;
+  *eps_min = hm->ctrl[0].eps_min;
+  *eps_max = hm->ctrl[0].eps_max;
+  if (hm->ctrl[0].nonfinite) return fail(SP2_ERR_NONFINITE, "H holds NaN or Inf");
+  return SP2_OK;
+}
+
+sp2_status sp2_spectral_bounds(const float* H, int64_t n, int64_t ld, int32_t steps,
+                               int32_t seed, double* eps_min, double* eps_max, void* workspace,
+                               size_t ws_bytes, void* stream) {
+  g_err.clear();
+  if (!H || !eps_min || !eps_max) return fail(SP2_ERR_INVALID_ARG, "NULL argument");
+  if (n <= 0 || ld < n) return fail(SP2_ERR_INVALID_ARG, "need n > 0 and ld >= n");
+  if (steps < SP2_MIN_BOUND_STEPS || steps > SP2_MAX_BOUND_STEPS)
+    return fail(SP2_ERR_INVALID_ARG, "steps must lie in [%d, %d]", SP2_MIN_BOUND_STEPS,
+                SP2_MAX_BOUND_STEPS);
+  sp2_options o;
+  sp2_default_options(&o);
+  Layout L;
+  if (!make_layout(n, o, L)) return fail(SP2_ERR_INVALID_ARG, "matrix order out of range");
+  if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 || ws_bytes < L.off_slot0)
+    return fail(SP2_ERR_WORKSPACE, "workspace missing, misaligned or too small");
+  HostMirror* hm;
+  if (sp2_status s = host_mirror(&hm)) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  WS w;
+  bind(w, workspace, L);
+  k_gershgorin_rows<<<L.gersh_blocks, kRowThreads, 0, st>>>(H, n, ld, w.gersh);
+  LAUNCH_TRY();
+  k_bounds_final<<<1, 256, 0, st>>>(w.gersh, L.gersh_blocks, w.ctrl, 1);
+  LAUNCH_TRY();
+  if (sp2_status s = refine_bounds(w, H, n, ld, steps, seed, st)) return s;
   if (sp2_status s = read_back(w, hm, false, st)) return s;
   *eps_min = hm->ctrl[0].eps_min;
   *eps_max = hm->ctrl[0].eps_max;

@@ -28,7 +28,7 @@ def _as_matrix(H, symmetrize):
 
 def density(H, n_occ, tol=1e-5, precision="bf16x3", refine="fp32", max_iter=100, stop_rule=1,
             stall_gate=1.0, checkpoint_every=0, symmetrize=False, return_info=False,
-            workspace=None, time_layers=False):
+            workspace=None, time_layers=False, bound_steps=0, bound_seed=0):
     """Density matrix of the symmetric ``H`` with ``n_occ`` occupied states.
 
     Returns ``P`` (FP32, same device), or ``(P, info)`` with ``info`` holding
@@ -38,7 +38,7 @@ def density(H, n_occ, tol=1e-5, precision="bf16x3", refine="fp32", max_iter=100,
     H = _as_matrix(H, symmetrize)
     n = H.shape[0]
     opt = _lib.make_options(precision, refine, max_iter, stop_rule, checkpoint_every, tol,
-                            stall_gate, time_layers)
+                            stall_gate, time_layers, bound_steps, bound_seed)
     if workspace is None:
         workspace = _lib.allocate_workspace(n, opt, H.device)
     P = torch.empty_like(H)

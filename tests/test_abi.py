@@ -38,7 +38,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 def test_struct_layouts_match_header():
     from paper_2107_02737_amd import _lib
-    assert ctypes.sizeof(_lib.sp2_options) == 6 * 4 + 2 * 8
+    assert ctypes.sizeof(_lib.sp2_options) == 8 * 4 + 2 * 8
     assert ctypes.sizeof(_lib.sp2_info) == 4 * 4 + 6 * 8
 
 
@@ -47,6 +47,7 @@ def test_default_options(lib):
     o = _lib.sp2_default_options()
     assert (o.precision, o.refine, o.max_iter, o.stop_rule, o.checkpoint_every) == (2, 1, 100, 1, 0)
     assert o.tol == 1e-5 and o.stall_gate == 1.0
+    assert (o.bound_steps, o.bound_seed, o.flags) == (0, 0, 0)
 
 
 def test_workspace_bytes(lib):
@@ -63,6 +64,14 @@ def test_workspace_bytes(lib):
     assert _lib.sp2_workspace_bytes(0, o) == 0
     o.max_iter = 0
     assert _lib.sp2_workspace_bytes(256, o) == 0
+    o = _lib.sp2_default_options()
+    o.bound_steps = 65
+    assert _lib.sp2_workspace_bytes(256, o) == 0
+    o.bound_steps = 7
+    assert _lib.sp2_workspace_bytes(256, o) == 0
+    for k in (8, 64):
+        o.bound_steps = k
+        assert _lib.sp2_workspace_bytes(256, o) > 0
 
 
 def test_invalid_arguments_rejected_before_device_work(lib):
@@ -103,3 +112,7 @@ def test_invalid_arguments_rejected_before_device_work(lib):
     assert lib.sp2_layer(fake, 8, 8, 2, 0, ctypes.c_void_p(0x2000), ws, 1 << 30, None) == \
         _lib.SP2_ERR_INVALID_ARG
     assert lib.sp2_split(fake, 8, 8, 0, fake, fake, None) == _lib.SP2_ERR_INVALID_ARG
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    for steps in (0, 7, 65):
+        assert lib.sp2_spectral_bounds(fake, 8, 8, steps, 0, ctypes.byref(lo), ctypes.byref(hi),
+                                       ws, 1 << 30, None) == _lib.SP2_ERR_INVALID_ARG

@@ -33,16 +33,22 @@ def setup():
     return pk, gold, torch.from_numpy(h32).to("cuda")
 
 
-@pytest.mark.parametrize("precision", ["bf16x3", "fp16x3", "fp32"])
-def test_water_6144(setup, precision):
+@pytest.mark.parametrize("precision,bound_steps", [("bf16x3", 0), ("fp16x3", 0), ("fp32", 0),
+                                                   ("bf16x3", 32), ("fp32", 32)])
+def test_water_6144(setup, precision, bound_steps):
     import torch
     pk, gold, H = setup
     n, n_occ = int(gold["n"]), int(gold["n_occ"])
-    banner(f"water N={n} {precision} refine=fp32")
-    P, info = pk.density(H, n_occ, precision=precision, refine="fp32", return_info=True)
+    banner(f"water N={n} {precision} refine=fp32 bound_steps={bound_steps}")
+    P, info = pk.density(H, n_occ, precision=precision, refine="fp32", bound_steps=bound_steps,
+                         return_info=True)
     assert info["converged"] == 1
-    assert info["eps_min"] == pytest.approx(float(gold["eps_min"]), rel=1e-12)
-    assert info["eps_max"] == pytest.approx(float(gold["eps_max"]), rel=1e-12)
+    if bound_steps == 0:
+        assert info["eps_min"] == pytest.approx(float(gold["eps_min"]), rel=1e-12)
+        assert info["eps_max"] == pytest.approx(float(gold["eps_max"]), rel=1e-12)
+    else:   # tighter, still enclosing the exact HOMO / LUMO levels
+        assert float(gold["eps_min"]) < info["eps_min"] < float(gold["homo"])
+        assert float(gold["lumo"]) < info["eps_max"] < float(gold["eps_max"])
     pi = torch.from_numpy(np.asarray(gold["pair_i"], dtype=np.int64)).cuda()
     pj = torch.from_numpy(np.asarray(gold["pair_j"], dtype=np.int64)).cuda()
     d = P[pi, pj].double().cpu().numpy() - gold["pair_val"]
