@@ -319,7 +319,7 @@ def main():
         Pl, linfo, lsec = timed_solves(pk, H, n_occ, args.precision, args.refine, 5, 1, True,
                                        args.compare_bound_steps)
         lerr = sampled_error(Pl, gold)
-        out["with_lanczos_bounds" if args.compare_bound_steps else "with_gershgorin_bounds"] = {
+        out["with_bound_steps"] = {
             "bound_steps": args.compare_bound_steps, "solves_per_s": 1.0 / lsec,
             "n_iter": linfo[-1]["n_iter"], "eps": [linfo[-1]["eps_min"], linfo[-1]["eps_max"]],
             "fro_over_sqrt_n_est": lerr["fro_over_sqrt_n_est"]}

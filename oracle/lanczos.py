@@ -5,9 +5,10 @@ The paper maps the spectrum of H onto [0, 1] before the first layer
 (``sp2_oracle.gershgorin_bounds``) are always valid but loose; the tighter
 the interval, the larger the mapped HOMO-LUMO gap and the fewer layers the
 network needs.  This module is the plain FP64 reference of the optional
-tightening step: ``k`` steps of the symmetric Lanczos recurrence (Golub and
-Van Loan, Matrix Computations, Section 10.1) from a pseudo-random start
-vector, the extreme Ritz values of the tridiagonal matrix, each widened by
+tightening step: ``k`` steps of the symmetric Lanczos recurrence with full
+reorthogonalisation (Golub and Van Loan, Matrix Computations, Sections 10.1
+and 10.3) from a pseudo-random start vector, the extreme Ritz values of the
+tridiagonal matrix, each widened by
 its Ritz residual norm ``|beta_k s_k|`` and a relative safety margin, then
 clipped to the Gershgorin interval.
 
@@ -52,12 +53,15 @@ def start_vector(n, seed=0):
 
 
 def lanczos(h, steps, seed=0, return_vectors=False):
-    """``steps`` steps of the Lanczos recurrence on the symmetric ``h`` (FP64,
-    no reorthogonalisation): ``w = H v_j - alpha_j v_j - beta_{j-1} v_{j-1}``,
-    ``alpha_j = v_j . H v_j``, ``beta_j = ||w||``, ``v_{j+1} = w / beta_j``.
-    Stops early when ``beta_j`` vanishes (an invariant subspace was found).
-    Returns ``(alpha, beta)`` (``beta[-1]`` couples to the next, unused
-    vector), plus the Lanczos vectors ``V`` (N x (k+1)) if asked."""
+    """``steps`` steps of the Lanczos recurrence on the symmetric ``h``
+    (FP64): ``w = H v_j - alpha_j v_j - beta_{j-1} v_{j-1}`` with
+    ``alpha_j = v_j . H v_j``, then full reorthogonalisation of ``w``
+    against ``v_0 .. v_j`` by two passes of classical Gram-Schmidt
+    (``w -= V (V^T w)``, Golub and Van Loan Section 10.3), ``beta_j = ||w||``,
+    ``v_{j+1} = w / beta_j``.  Stops early when ``beta_j`` vanishes (an
+    invariant subspace was found).  Returns ``(alpha, beta)`` (``beta[-1]``
+    couples to the next, unused vector), plus the Lanczos vectors ``V``
+    (N x (k+1)) if asked."""
     h = np.asarray(h, dtype=np.float64)
     n = h.shape[0]
     v = start_vector(n, seed)
@@ -68,6 +72,9 @@ def lanczos(h, steps, seed=0, return_vectors=False):
         w = h @ v
         a = float(v @ w)
         w = w - a * v - b_prev * v_prev
+        basis = np.array(vecs).T
+        for _pass in range(2):
+            w = w - basis @ (basis.T @ w)
         b = float(np.linalg.norm(w))
         alpha.append(a)
         beta.append(b)

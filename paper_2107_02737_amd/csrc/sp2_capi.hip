@@ -113,7 +113,9 @@ bool make_layout(int64_t n, const sp2_options& o, Layout& L) {
   L.off_partial = take(kPartialBytes);
   L.lz_blocks = static_cast<int>((n + kLzRowsPerBlock - 1) / kLzRowsPerBlock);
   L.off_lz = take(sizeof(LzState));
-  L.off_lzvec = take(size_t(3) * size_t(n) * 8);
+  // Lanczos vectors v_0 .. v_k and w, sized for the largest k so that the
+  // layout does not depend on the bound option (the tape reader rebuilds it)
+  L.off_lzvec = take(size_t(kLzMaxSteps + 2) * size_t(n) * 8);
   L.off_lzpart = take(size_t(L.lz_blocks) * 8);
   L.slot_bytes = size_t(L.np) * size_t(L.np) * 4;
   L.every = o.checkpoint_every;
@@ -138,7 +140,7 @@ struct WS {
   int* counter;
   float* partial;
   LzState* lz;
-  double* lzv;      // v, v_prev, w: n doubles each
+  double* lzv;      // Lanczos vectors v_0 .. v_k, then w: n doubles each
   double* lzpart;
   float* slotf(int i) const { return reinterpret_cast<float*>(base + L.off_slot0 + L.slot_bytes * size_t(i)); }
   uint16_t* hi(int pair) const { return reinterpret_cast<uint16_t*>(slotf(1 + pair)); }
@@ -169,16 +171,15 @@ void bind(WS& w, void* ws, const Layout& L) {
 // round trip; a NaN H or a degenerate spectrum leaves ctrl as it is).
 sp2_status refine_bounds(const WS& w, const float* H, int64_t n, int64_t ld, int steps,
                          int32_t seed, hipStream_t st) {
-  double* v = w.lzv;
-  double* vp = w.lzv + n;
-  double* wv = w.lzv + 2 * n;
-  k_lz_start<<<1, kLzThreads, 0, st>>>(v, vp, n, static_cast<uint64_t>(static_cast<uint32_t>(seed)),
+  double* V = w.lzv;
+  double* wv = w.lzv + int64_t(steps + 1) * n;
+  k_lz_start<<<1, kLzThreads, 0, st>>>(V, n, static_cast<uint64_t>(static_cast<uint32_t>(seed)),
                                        w.lz);
   LAUNCH_TRY();
   for (int j = 0; j < steps; ++j) {
-    k_lz_matvec<<<w.L.lz_blocks, 256, 0, st>>>(H, n, ld, v, wv, w.lzpart, w.lz);
+    k_lz_matvec<<<w.L.lz_blocks, 256, 0, st>>>(H, n, ld, V + int64_t(j) * n, wv, w.lzpart, w.lz);
     LAUNCH_TRY();
-    k_lz_update<<<1, kLzThreads, 0, st>>>(wv, v, vp, w.lzpart, w.L.lz_blocks, n, w.lz, j);
+    k_lz_update<<<1, kLzThreads, 0, st>>>(wv, V, w.lzpart, w.L.lz_blocks, n, w.lz, j);
     LAUNCH_TRY();
   }
   k_lz_bounds<<<1, 64, 0, st>>>(w.lz, w.ctrl, kLzMargin);
@@ -772,6 +773,7 @@ sp2_status sp2_spectral_bounds(const float* H, int64_t n, int64_t ld, int32_t st
                 SP2_MAX_BOUND_STEPS);
   sp2_options o;
   sp2_default_options(&o);
+  o.bound_steps = steps;
   Layout L;
   if (!make_layout(n, o, L)) return fail(SP2_ERR_INVALID_ARG, "matrix order out of range");
   if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 || ws_bytes < L.off_slot0)

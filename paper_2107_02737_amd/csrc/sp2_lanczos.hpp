@@ -3,9 +3,9 @@
 // The network needs an interval holding the spectrum of H (Section II.D);
 // Gershgorin discs always hold it but are loose, which shrinks the mapped
 // HOMO-LUMO gap and costs layers.  Here k steps of the symmetric Lanczos
-// recurrence (Golub and Van Loan, Matrix Computations, Section 10.1) run on
-// the device in FP64 from a SplitMix64 start vector (Steele, Lea and Flood,
-// OOPSLA 2014); the extreme eigenvalues of the k x k tridiagonal matrix
+// recurrence with full reorthogonalisation (Golub and Van Loan, Matrix
+// Computations, Sections 10.1 and 10.3) run on the device in FP64 from a
+// SplitMix64 start vector (Steele, Lea and Flood, OOPSLA 2014); the extreme eigenvalues of the k x k tridiagonal matrix
 // (Sturm-count bisection), widened by their Ritz residual norms
 // |beta_k s_k| (inverse iteration) and a relative margin, replace the
 // Gershgorin bounds wherever they are tighter.  Nothing returns to the host.
@@ -49,21 +49,20 @@ __device__ __forceinline__ double block_sum1(double a, double* red) {
   return s;
 }
 
-// v = u / |u|, u_i = (z_i >> 11) 2^-53 - 1/2; v_prev = 0; state reset.
-__global__ __launch_bounds__(kLzThreads) void k_lz_start(double* __restrict__ v,
-                                                         double* __restrict__ vp, int64_t n,
+// V_0 = u / |u|, u_i = (z_i >> 11) 2^-53 - 1/2; state reset.  V holds the
+// Lanczos vectors as consecutive rows of n doubles.
+__global__ __launch_bounds__(kLzThreads) void k_lz_start(double* __restrict__ V, int64_t n,
                                                          uint64_t seed, LzState* st) {
   __shared__ double red[kLzThreads / kWave];
   double s = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += kLzThreads) {
     const double u = static_cast<double>(splitmix64(seed, static_cast<uint64_t>(i)) >> 11) *
                          0x1.0p-53 - 0.5;
-    v[i] = u;
-    vp[i] = 0.0;
+    V[i] = u;
     s += u * u;
   }
   const double nrm = sqrt(block_sum1<kLzThreads>(s, red));
-  for (int64_t i = threadIdx.x; i < n; i += kLzThreads) v[i] = v[i] / nrm;
+  for (int64_t i = threadIdx.x; i < n; i += kLzThreads) V[i] = V[i] / nrm;
   if (threadIdx.x == 0) {
     st->steps = 0;
     st->broke = 0;
@@ -134,27 +133,63 @@ __global__ __launch_bounds__(256) void k_lz_matvec(const float* __restrict__ H, 
   }
 }
 
-// One Lanczos step after w = H v_j: alpha_j = sum of the partials;
-// w -= alpha_j v_j + beta_{j-1} v_{j-1}; beta_j = |w|; v_{j-1} <- v_j,
-// v_j <- w / beta_j.
+// One Lanczos step after w = H v_j (j = step): alpha_j = sum of the
+// partials; w -= alpha_j v_j + beta_{j-1} v_{j-1}; then full
+// reorthogonalisation against v_0 .. v_j by two passes of classical
+// Gram-Schmidt (c = V^T w, w -= V c), which keeps the recurrence free of
+// spurious copies of converged Ritz values and reproducible to rounding;
+// beta_j = |w|, v_{j+1} = w / beta_j.
 __global__ __launch_bounds__(kLzThreads) void k_lz_update(double* __restrict__ w,
-                                                          double* __restrict__ v,
-                                                          double* __restrict__ vp,
+                                                          double* __restrict__ V,
                                                           const double* __restrict__ part,
                                                           int nparts, int64_t n, LzState* st,
                                                           int step) {
-  __shared__ double red[kLzThreads / kWave];
+  constexpr int NW = kLzThreads / kWave, G = 8;
+  __shared__ double red[NW * G];
+  __shared__ double coef[kLzMaxSteps + G];
   if (st->broke) return;
   double a = 0.0;
   for (int i = threadIdx.x; i < nparts; i += kLzThreads) a += part[i];
   const double alpha = block_sum1<kLzThreads>(a, red);
   const double bprev = step > 0 ? st->beta[step - 1] : 0.0;
-  double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += kLzThreads) {
-    const double wi = w[i] - alpha * v[i] - bprev * vp[i];
-    w[i] = wi;
-    s += wi * wi;
+  const double* vj = V + int64_t(step) * n;
+  const double* vm = step > 0 ? V + int64_t(step - 1) * n : vj;
+  for (int64_t i = threadIdx.x; i < n; i += kLzThreads) w[i] = w[i] - alpha * vj[i] - bprev * vm[i];
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int g = 0; g <= step; g += G) {
+      double c[G];
+#pragma unroll
+      for (int q = 0; q < G; ++q) c[q] = 0.0;
+      for (int64_t i = threadIdx.x; i < n; i += kLzThreads) {
+        const double wi = w[i];
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+          if (g + q <= step) c[q] = fma(V[int64_t(g + q) * n + i], wi, c[q]);
+      }
+#pragma unroll
+      for (int q = 0; q < G; ++q) c[q] = wave_sum(c[q]);
+      __syncthreads();
+      if ((threadIdx.x & (kWave - 1)) == 0) {
+#pragma unroll
+        for (int q = 0; q < G; ++q) red[(threadIdx.x / kWave) * G + q] = c[q];
+      }
+      __syncthreads();
+      if (threadIdx.x < G) {
+        double s = 0.0;
+        for (int k = 0; k < NW; ++k) s += red[k * G + threadIdx.x];
+        coef[g + threadIdx.x] = s;
+      }
+    }
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < n; i += kLzThreads) {
+      double s = w[i];
+      for (int q = 0; q <= step; ++q) s = fma(-coef[q], V[int64_t(q) * n + i], s);
+      w[i] = s;
+    }
+    __syncthreads();
   }
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += kLzThreads) s += w[i] * w[i];
   const double beta = sqrt(block_sum1<kLzThreads>(s, red));
   if (threadIdx.x == 0) {
     st->alpha[step] = alpha;
@@ -163,10 +198,8 @@ __global__ __launch_bounds__(kLzThreads) void k_lz_update(double* __restrict__ w
     if (!(beta > 1e-300)) st->broke = 1;
   }
   if (!(beta > 1e-300)) return;
-  for (int64_t i = threadIdx.x; i < n; i += kLzThreads) {
-    vp[i] = v[i];
-    v[i] = w[i] / beta;
-  }
+  double* vn = V + int64_t(step + 1) * n;
+  for (int64_t i = threadIdx.x; i < n; i += kLzThreads) vn[i] = w[i] / beta;
 }
 
 // Eigenvalues of the symmetric tridiagonal T (diagonal a, off-diagonal b)
