@@ -53,36 +53,32 @@ def start_vector(n, seed=0):
 
 
 def lanczos(h, steps, seed=0, return_vectors=False):
-    """``steps`` steps of the Lanczos recurrence on the symmetric ``h``
-    (FP64): ``w = H v_j - alpha_j v_j - beta_{j-1} v_{j-1}`` with
-    ``alpha_j = v_j . H v_j``, then full reorthogonalisation of ``w``
-    against ``v_0 .. v_j`` by two passes of classical Gram-Schmidt
-    (``w -= V (V^T w)``, Golub and Van Loan Section 10.3), ``beta_j = ||w||``,
-    ``v_{j+1} = w / beta_j``.  Stops early when ``beta_j`` vanishes (an
-    invariant subspace was found).  Returns ``(alpha, beta)`` (``beta[-1]``
-    couples to the next, unused vector), plus the Lanczos vectors ``V``
-    (N x (k+1)) if asked."""
+    """``steps`` steps of the Lanczos recurrence on the symmetric ``h`` (FP64)
+    with full reorthogonalisation (Golub and Van Loan Section 10.3): for
+    ``w = H v_j``, two passes of classical Gram-Schmidt against
+    ``V = [v_0 .. v_j]`` (``c = V^T w``, ``w -= V c``), the first pass giving
+    ``alpha_j = c_j = v_j . H v_j`` (in exact arithmetic the same numbers as
+    the three-term recurrence); ``beta_j = ||w||``,
+    ``v_{j+1} = w * (1 / beta_j)``.  Stops early when ``beta_j`` vanishes
+    (an invariant subspace was found).  Returns ``(alpha, beta)``
+    (``beta[-1]`` couples to the next, unused vector), plus the Lanczos
+    vectors ``V`` (N x (k+1)) if asked."""
     h = np.asarray(h, dtype=np.float64)
     n = h.shape[0]
-    v = start_vector(n, seed)
-    v_prev = np.zeros(n)
-    b_prev = 0.0
-    alpha, beta, vecs = [], [], [v]
-    for _ in range(steps):
-        w = h @ v
-        a = float(v @ w)
-        w = w - a * v - b_prev * v_prev
+    vecs = [start_vector(n, seed)]
+    alpha, beta = [], []
+    for j in range(min(steps, n)):
+        w = h @ vecs[j]
         basis = np.array(vecs).T
-        for _pass in range(2):
-            w = w - basis @ (basis.T @ w)
+        c = basis.T @ w
+        w = w - basis @ c
+        w = w - basis @ (basis.T @ w)
         b = float(np.linalg.norm(w))
-        alpha.append(a)
+        alpha.append(float(c[j]))
         beta.append(b)
         if not b > 1e-300:
             break
-        v_prev, v = v, w / b
-        b_prev = b
-        vecs.append(v)
+        vecs.append(w * (1.0 / b))
     if return_vectors:
         return np.array(alpha), np.array(beta), np.array(vecs).T
     return np.array(alpha), np.array(beta)

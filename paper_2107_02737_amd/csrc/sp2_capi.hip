@@ -75,8 +75,8 @@ struct Layout {
   int nb_split, ntiles_split, nb_f32, ntiles_f32;
   int init_blocks, gersh_blocks, max_parts;
   size_t off_ctrl, off_hist, off_meta, off_parts0, off_parts1, off_gersh, off_counter, off_partial;
-  size_t off_lz, off_lzvec, off_lzpart;   // Lanczos state, 3 vectors of n doubles, partials
-  int lz_blocks;
+  size_t off_lz, off_lzvec, off_lzpart;   // Lanczos state, vectors, chunk partials
+  int lz_blocks, lz_chunks;
   size_t off_slot0;     // first matrix slot
   size_t slot_bytes;
   int nslots, ntape, every;
@@ -112,11 +112,13 @@ bool make_layout(int64_t n, const sp2_options& o, Layout& L) {
   L.off_counter = take(size_t(kMaxTailTiles) * 4);
   L.off_partial = take(kPartialBytes);
   L.lz_blocks = static_cast<int>((n + kLzRowsPerBlock - 1) / kLzRowsPerBlock);
+  L.lz_chunks = static_cast<int>((n + kLzChunk - 1) / kLzChunk);
   L.off_lz = take(sizeof(LzState));
-  // Lanczos vectors v_0 .. v_k and w, sized for the largest k so that the
-  // layout does not depend on the bound option (the tape reader rebuilds it)
-  L.off_lzvec = take(size_t(kLzMaxSteps + 2) * size_t(n) * 8);
-  L.off_lzpart = take(size_t(L.lz_blocks) * 8);
+  // Lanczos vectors v_0 .. v_kmax and two w buffers, sized for the largest
+  // k so that the layout does not depend on the bound option (the tape
+  // reader rebuilds it)
+  L.off_lzvec = take(size_t(kLzMaxSteps + 3) * size_t(n) * 8);
+  L.off_lzpart = take(size_t(L.lz_chunks) * (2 * kLzCoef + 1) * 8);
   L.slot_bytes = size_t(L.np) * size_t(L.np) * 4;
   L.every = o.checkpoint_every;
   // slots 0-3: S (FP32), two hi/lo plane pairs (or FP32 ping-pong), S^2 for
@@ -140,7 +142,7 @@ struct WS {
   int* counter;
   float* partial;
   LzState* lz;
-  double* lzv;      // Lanczos vectors v_0 .. v_k, then w: n doubles each
+  double* lzv;      // Lanczos vectors v_0 .. v_kmax, then two w buffers: n doubles each
   double* lzpart;
   float* slotf(int i) const { return reinterpret_cast<float*>(base + L.off_slot0 + L.slot_bytes * size_t(i)); }
   uint16_t* hi(int pair) const { return reinterpret_cast<uint16_t*>(slotf(1 + pair)); }
@@ -171,18 +173,28 @@ void bind(WS& w, void* ws, const Layout& L) {
 // round trip; a NaN H or a degenerate spectrum leaves ctrl as it is).
 sp2_status refine_bounds(const WS& w, const float* H, int64_t n, int64_t ld, int steps,
                          int32_t seed, hipStream_t st) {
+  const int nc = w.L.lz_chunks;
   double* V = w.lzv;
-  double* wv = w.lzv + int64_t(steps + 1) * n;
+  double* wb[2] = {w.lzv + int64_t(kLzMaxSteps + 1) * n, w.lzv + int64_t(kLzMaxSteps + 2) * n};
+  double* p1 = w.lzpart;                  // first-pass dot partials
+  double* p2 = p1 + size_t(nc) * kLzCoef;  // second-pass dot partials
+  double* pn = p2 + size_t(nc) * kLzCoef;  // squared-norm partials
+  steps = static_cast<int>(std::min<int64_t>(steps, n));
   k_lz_start<<<1, kLzThreads, 0, st>>>(V, n, static_cast<uint64_t>(static_cast<uint32_t>(seed)),
                                        w.lz);
   LAUNCH_TRY();
   for (int j = 0; j < steps; ++j) {
-    k_lz_matvec<<<w.L.lz_blocks, 256, 0, st>>>(H, n, ld, V + int64_t(j) * n, wv, w.lzpart, w.lz);
+    double* wj = wb[j & 1];
+    k_lz_matvec<<<w.L.lz_blocks, 256, 0, st>>>(H, n, ld, V, wb[(j + 1) & 1], wj, pn, nc, w.lz, j);
     LAUNCH_TRY();
-    k_lz_update<<<1, kLzThreads, 0, st>>>(wv, V, w.lzpart, w.L.lz_blocks, n, w.lz, j);
+    k_lz_dots<<<nc, kLzChunk, 0, st>>>(V, wj, n, j, p1, w.lz);
+    LAUNCH_TRY();
+    k_lz_apply<<<nc, kLzChunk, 0, st>>>(V, wj, n, j, p1, nc, p2, w.lz, 0);
+    LAUNCH_TRY();
+    k_lz_apply<<<nc, kLzChunk, 0, st>>>(V, wj, n, j, p2, nc, pn, w.lz, 1);
     LAUNCH_TRY();
   }
-  k_lz_bounds<<<1, 64, 0, st>>>(w.lz, w.ctrl, kLzMargin);
+  k_lz_bounds<<<1, 64, 0, st>>>(w.lz, w.ctrl, kLzMargin, pn, nc);
   LAUNCH_TRY();
   return SP2_OK;
 }

@@ -16,15 +16,17 @@
 namespace sp2 {
 
 constexpr int kLzMaxSteps = 64;
-constexpr int kLzThreads = 1024;     // one-work-group kernels
+constexpr int kLzThreads = 1024;     // start kernel
 constexpr int kLzRowsPerWave = 4;
 constexpr int kLzRowsPerBlock = 4 * kLzRowsPerWave;
+constexpr int kLzChunk = 256;        // rows per work-group of the vector kernels
+constexpr int kLzCoef = kLzMaxSteps + 1;
 constexpr double kLzMargin = 0.01;   // relative widening of the Ritz interval
 
 struct LzState {
   double alpha[kLzMaxSteps];
   double beta[kLzMaxSteps];
-  int32_t steps;    // recorded (alpha, beta) pairs
+  int32_t steps;    // recorded alpha values
   int32_t broke;    // beta vanished: invariant subspace, later steps skipped
   int32_t pad[2];
 };
@@ -49,6 +51,14 @@ __device__ __forceinline__ double block_sum1(double a, double* red) {
   return s;
 }
 
+// Sum of the per-chunk partials of one quantity, chunks in order (every
+// work-group that needs it computes the same value).
+__device__ __forceinline__ double chunk_sum(const double* part, int nchunks, int stride, int idx) {
+  double s = 0.0;
+  for (int b = 0; b < nchunks; ++b) s += part[b * stride + idx];
+  return s;
+}
+
 // V_0 = u / |u|, u_i = (z_i >> 11) 2^-53 - 1/2; state reset.  V holds the
 // Lanczos vectors as consecutive rows of n doubles.
 __global__ __launch_bounds__(kLzThreads) void k_lz_start(double* __restrict__ V, int64_t n,
@@ -69,15 +79,33 @@ __global__ __launch_bounds__(kLzThreads) void k_lz_start(double* __restrict__ V,
   }
 }
 
-// w = H v (FP32 H, FP64 products and sums); each wave takes 4 consecutive
-// rows so that every v load serves 4 rows.  Block b writes the partial
-// sum over its 16 rows of v_i w_i (rows in order).
+// Step j: wout = H v_j (FP32 H, FP64 products and sums), each wave taking 4
+// consecutive rows so that every v load serves 4 rows.  For j >= 1, v_j is
+// formed on the fly as win * (1 / beta_{j-1}), beta_{j-1} = sqrt of the
+// summed squared-norm partials of step j-1, and stored into V row j by the
+// work-group owning each row; block 0 records beta_{j-1}.
 __global__ __launch_bounds__(256) void k_lz_matvec(const float* __restrict__ H, int64_t n,
-                                                   int64_t ld, const double* __restrict__ v,
-                                                   double* __restrict__ w,
-                                                   double* __restrict__ part, const LzState* st) {
-  __shared__ double red[kLzRowsPerBlock];
+                                                   int64_t ld, double* __restrict__ V,
+                                                   const double* __restrict__ win,
+                                                   double* __restrict__ wout,
+                                                   const double* __restrict__ norm_part,
+                                                   int nchunks, LzState* st, int j) {
   if (st->broke) return;
+  const double* v = V + int64_t(j) * n;
+  double inv = 1.0;
+  if (j > 0) {
+    const double beta = sqrt(chunk_sum(norm_part, nchunks, 1, 0));
+    if (!(beta > 1e-300)) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->beta[j - 1] = beta;
+        st->broke = 1;
+      }
+      return;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->beta[j - 1] = beta;
+    inv = 1.0 / beta;
+    v = win;
+  }
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = threadIdx.x / kWave;
   const int64_t r0 = int64_t(blockIdx.x) * kLzRowsPerBlock + wv * kLzRowsPerWave;
@@ -87,7 +115,7 @@ __global__ __launch_bounds__(256) void k_lz_matvec(const float* __restrict__ H, 
   if (vec) {
     const int64_t n4 = n & ~int64_t(3);
     for (int64_t c = 4 * lane; c < n4; c += 4 * kWave) {
-      const double v0 = v[c], v1 = v[c + 1], v2 = v[c + 2], v3 = v[c + 3];
+      const double v0 = v[c] * inv, v1 = v[c + 1] * inv, v2 = v[c + 2] * inv, v3 = v[c + 3] * inv;
 #pragma unroll
       for (int rr = 0; rr < kLzRowsPerWave; ++rr) {
         const int64_t row = r0 + rr;
@@ -105,7 +133,7 @@ __global__ __launch_bounds__(256) void k_lz_matvec(const float* __restrict__ H, 
     c_done = n4;
   }
   for (int64_t c = c_done + lane; c < n; c += kWave) {
-    const double vc = v[c];
+    const double vc = v[c] * inv;
 #pragma unroll
     for (int rr = 0; rr < kLzRowsPerWave; ++rr) {
       const int64_t row = r0 + rr;
@@ -116,90 +144,73 @@ __global__ __launch_bounds__(256) void k_lz_matvec(const float* __restrict__ H, 
   for (int rr = 0; rr < kLzRowsPerWave; ++rr) {
     const double s = wave_sum(acc[rr]);
     const int64_t row = r0 + rr;
-    if (lane == 0) {
-      double d = 0.0;
-      if (row < n) {
-        w[row] = s;
-        d = v[row] * s;
-      }
-      red[wv * kLzRowsPerWave + rr] = d;
+    if (lane == 0 && row < n) {
+      wout[row] = s;
+      if (j > 0) V[int64_t(j) * n + row] = win[row] * inv;
     }
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int i = 0; i < kLzRowsPerBlock; ++i) s += red[i];
-    part[blockIdx.x] = s;
   }
 }
 
-// One Lanczos step after w = H v_j (j = step): alpha_j = sum of the
-// partials; w -= alpha_j v_j + beta_{j-1} v_{j-1}; then full
-// reorthogonalisation against v_0 .. v_j by two passes of classical
-// Gram-Schmidt (c = V^T w, w -= V c), which keeps the recurrence free of
-// spurious copies of converged Ritz values and reproducible to rounding;
-// beta_j = |w|, v_{j+1} = w / beta_j.
-__global__ __launch_bounds__(kLzThreads) void k_lz_update(double* __restrict__ w,
-                                                          double* __restrict__ V,
-                                                          const double* __restrict__ part,
-                                                          int nparts, int64_t n, LzState* st,
-                                                          int step) {
-  constexpr int NW = kLzThreads / kWave, G = 8;
-  __shared__ double red[NW * G];
-  __shared__ double coef[kLzMaxSteps + G];
+// Partial dot products of w with v_0 .. v_j over one chunk of 256 rows:
+// part[chunk * kLzCoef + i].
+__device__ __forceinline__ void chunk_dots(const double* V, double wr, int64_t row, int64_t n, int j,
+                                           double* part, double* red) {
+  constexpr int NW = kLzChunk / kWave;
+  for (int i = 0; i <= j; ++i) {
+    const double p = row < n ? V[int64_t(i) * n + row] * wr : 0.0;
+    const double s = wave_sum(p);
+    if ((threadIdx.x & (kWave - 1)) == 0) red[(threadIdx.x / kWave) * kLzCoef + i] = s;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i <= j; i += kLzChunk) {
+    double s = 0.0;
+    for (int k = 0; k < NW; ++k) s += red[k * kLzCoef + i];
+    part[blockIdx.x * kLzCoef + i] = s;
+  }
+}
+
+// First Gram-Schmidt pass, dots: part = chunk partials of V^T w.
+__global__ __launch_bounds__(kLzChunk) void k_lz_dots(const double* __restrict__ V,
+                                                      const double* __restrict__ w, int64_t n,
+                                                      int j, double* __restrict__ part,
+                                                      const LzState* st) {
+  __shared__ double red[(kLzChunk / kWave) * kLzCoef];
   if (st->broke) return;
-  double a = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += kLzThreads) a += part[i];
-  const double alpha = block_sum1<kLzThreads>(a, red);
-  const double bprev = step > 0 ? st->beta[step - 1] : 0.0;
-  const double* vj = V + int64_t(step) * n;
-  const double* vm = step > 0 ? V + int64_t(step - 1) * n : vj;
-  for (int64_t i = threadIdx.x; i < n; i += kLzThreads) w[i] = w[i] - alpha * vj[i] - bprev * vm[i];
-  for (int pass = 0; pass < 2; ++pass) {
-    for (int g = 0; g <= step; g += G) {
-      double c[G];
-#pragma unroll
-      for (int q = 0; q < G; ++q) c[q] = 0.0;
-      for (int64_t i = threadIdx.x; i < n; i += kLzThreads) {
-        const double wi = w[i];
-#pragma unroll
-        for (int q = 0; q < G; ++q)
-          if (g + q <= step) c[q] = fma(V[int64_t(g + q) * n + i], wi, c[q]);
-      }
-#pragma unroll
-      for (int q = 0; q < G; ++q) c[q] = wave_sum(c[q]);
-      __syncthreads();
-      if ((threadIdx.x & (kWave - 1)) == 0) {
-#pragma unroll
-        for (int q = 0; q < G; ++q) red[(threadIdx.x / kWave) * G + q] = c[q];
-      }
-      __syncthreads();
-      if (threadIdx.x < G) {
-        double s = 0.0;
-        for (int k = 0; k < NW; ++k) s += red[k * G + threadIdx.x];
-        coef[g + threadIdx.x] = s;
-      }
-    }
-    __syncthreads();
-    for (int64_t i = threadIdx.x; i < n; i += kLzThreads) {
-      double s = w[i];
-      for (int q = 0; q <= step; ++q) s = fma(-coef[q], V[int64_t(q) * n + i], s);
-      w[i] = s;
-    }
-    __syncthreads();
+  const int64_t row = int64_t(blockIdx.x) * kLzChunk + threadIdx.x;
+  chunk_dots(V, row < n ? w[row] : 0.0, row, n, j, part, red);
+}
+
+// A Gram-Schmidt update: c = sum of the chunk partials, w -= V c on this
+// chunk; then either the partial dots of the second pass (last = 0; block 0
+// records alpha_j = c_j of the first pass) or the partial |w|^2 (last = 1).
+__global__ __launch_bounds__(kLzChunk) void k_lz_apply(const double* __restrict__ V,
+                                                       double* __restrict__ w, int64_t n, int j,
+                                                       const double* __restrict__ part_in,
+                                                       int nchunks, double* __restrict__ part_out,
+                                                       LzState* st, int last) {
+  __shared__ double red[(kLzChunk / kWave) * kLzCoef];
+  __shared__ double coef[kLzCoef];
+  if (st->broke) return;
+  for (int i = threadIdx.x; i <= j; i += kLzChunk)
+    coef[i] = chunk_sum(part_in, nchunks, kLzCoef, i);
+  __syncthreads();
+  const int64_t row = int64_t(blockIdx.x) * kLzChunk + threadIdx.x;
+  double wr = 0.0;
+  if (row < n) {
+    wr = w[row];
+    for (int i = 0; i <= j; ++i) wr = fma(-coef[i], V[int64_t(i) * n + row], wr);
+    w[row] = wr;
   }
-  double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += kLzThreads) s += w[i] * w[i];
-  const double beta = sqrt(block_sum1<kLzThreads>(s, red));
-  if (threadIdx.x == 0) {
-    st->alpha[step] = alpha;
-    st->beta[step] = beta;
-    st->steps = step + 1;
-    if (!(beta > 1e-300)) st->broke = 1;
+  if (!last) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st->alpha[j] = coef[j];
+      st->steps = j + 1;
+    }
+    chunk_dots(V, wr, row, n, j, part_out, red);
+  } else {
+    const double s = block_sum1<kLzChunk>(wr * wr, red);
+    if (threadIdx.x == 0) part_out[blockIdx.x] = s;
   }
-  if (!(beta > 1e-300)) return;
-  double* vn = V + int64_t(step + 1) * n;
-  for (int64_t i = threadIdx.x; i < n; i += kLzThreads) vn[i] = w[i] / beta;
 }
 
 // Eigenvalues of the symmetric tridiagonal T (diagonal a, off-diagonal b)
@@ -292,14 +303,19 @@ __device__ inline double tridiag_last_component(const double* a, const double* b
 
 // Replace the Gershgorin bounds in ctrl by the Ritz interval where tighter.
 // One thread does the O(k^2) work.
-__global__ __launch_bounds__(64) void k_lz_bounds(const LzState* st, Ctrl* ctrl, double margin) {
+// The last beta (coupling to the next, unused vector) comes from the norm
+// partials of the last step unless the recurrence broke down.
+__global__ __launch_bounds__(64) void k_lz_bounds(LzState* st, Ctrl* ctrl, double margin,
+                                                  const double* __restrict__ norm_part,
+                                                  int nchunks) {
   __shared__ double x[kLzMaxSteps], dl[kLzMaxSteps], dd[kLzMaxSteps], du[kLzMaxSteps],
       du2[kLzMaxSteps];
   __shared__ int swp[kLzMaxSteps];
   if (threadIdx.x != 0) return;
-  if (ctrl->nonfinite || ctrl->degenerate) return;
   const int k = st->steps;
   if (k <= 0) return;
+  if (!st->broke) st->beta[k - 1] = sqrt(chunk_sum(norm_part, nchunks, 1, 0));
+  if (ctrl->nonfinite || ctrl->degenerate) return;
   const double* a = st->alpha;
   const double* b = st->beta;
   double lo = INFINITY, hi = -INFINITY, scale = 0.0;
