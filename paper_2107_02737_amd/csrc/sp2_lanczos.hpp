@@ -228,16 +228,30 @@ __device__ inline int sturm_count(const double* a, const double* b, int k, doubl
   return cnt;
 }
 
-// The eigenvalue of index `idx` (0-based, ascending) by bisection.
+// The eigenvalue of index `idx` (0-based, ascending) of T in [lo, hi] by
+// multisection across the 64 lanes of one wave: every round each lane counts
+// at one of 64 interior points and the interval shrinks to the first gap
+// whose right end holds more than idx eigenvalues below it.
 __device__ inline double tridiag_eig(const double* a, const double* b, int k, int idx, double lo,
                                      double hi, double pivmin) {
-  for (int it = 0; it < 200; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    if (mid <= lo || mid >= hi) break;
-    if (sturm_count(a, b, k, mid, pivmin) > idx)
-      hi = mid;
-    else
-      lo = mid;
+  const int lane = threadIdx.x & (kWave - 1);
+  for (int round = 0; round < 16; ++round) {
+    const double step = (hi - lo) / (kWave + 1);
+    const double x = lo + (lane + 1) * step;
+    const bool above = sturm_count(a, b, k, x, pivmin) > idx;
+    const unsigned long long m = __ballot(above);
+    double nlo, nhi;
+    if (m == 0ull) {
+      nlo = __shfl(x, kWave - 1, kWave);
+      nhi = hi;
+    } else {
+      const int f = __ffsll(static_cast<long long>(m)) - 1;
+      nhi = __shfl(x, f, kWave);
+      nlo = f == 0 ? lo : __shfl(x, f - 1, kWave);
+    }
+    if (!(nhi - nlo < hi - lo)) break;   // no representable progress left
+    lo = nlo;
+    hi = nhi;
   }
   return 0.5 * (lo + hi);
 }
@@ -311,10 +325,10 @@ __global__ __launch_bounds__(64) void k_lz_bounds(LzState* st, Ctrl* ctrl, doubl
   __shared__ double x[kLzMaxSteps], dl[kLzMaxSteps], dd[kLzMaxSteps], du[kLzMaxSteps],
       du2[kLzMaxSteps];
   __shared__ int swp[kLzMaxSteps];
-  if (threadIdx.x != 0) return;
   const int k = st->steps;
   if (k <= 0) return;
-  if (!st->broke) st->beta[k - 1] = sqrt(chunk_sum(norm_part, nchunks, 1, 0));
+  if (threadIdx.x == 0 && !st->broke) st->beta[k - 1] = sqrt(chunk_sum(norm_part, nchunks, 1, 0));
+  __syncthreads();
   if (ctrl->nonfinite || ctrl->degenerate) return;
   const double* a = st->alpha;
   const double* b = st->beta;
@@ -332,6 +346,7 @@ __global__ __launch_bounds__(64) void k_lz_bounds(LzState* st, Ctrl* ctrl, doubl
   hi += pad;
   const double th_lo = tridiag_eig(a, b, k, 0, lo, hi, pivmin);
   const double th_hi = tridiag_eig(a, b, k, k - 1, lo, hi, pivmin);
+  if (threadIdx.x != 0) return;
   const double tiny = 1e-13 * scale;
   const double r_lo = fabs(b[k - 1]) *
       tridiag_last_component(a, b, k, th_lo - tiny, tiny, x, dl, dd, du, du2, swp);
