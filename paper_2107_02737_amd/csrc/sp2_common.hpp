@@ -168,24 +168,22 @@ __device__ inline void split_fp16s(float x, uint16_t& hi, uint16_t& lo) {
 // ---------------------------------------------------------------------------
 // K-tiled layout of the 16-bit planes.  The plane of an np x np matrix is
 // stored as blocks of 256 rows x 16 columns (8 KB each), block (I, K) at
-// element (I * np/16 + K) * 4096; inside a block, row r is 32 contiguous
-// bytes whose two 16-byte chunks are swapped when plane_swz(r) is 1.  One K
-// step of a 256-row panel is then one contiguous 8 KB block that the product
-// kernel copies verbatim into LDS, where the swap makes the MFMA fragment
-// reads (lanes reading 16 bytes from consecutive rows) bank-conflict free
-// for both 8- and 16-lane service groups.
+// element (I * np/16 + K) * 4096; inside a block, columns 0-7 of all 256
+// rows come first (16 bytes per row), then columns 8-15.  One K step of a
+// 256-row panel is then one contiguous 8 KB block that the product kernel
+// copies verbatim into LDS, where an MFMA fragment read (consecutive lanes
+// reading 16 bytes of consecutive rows) is bank-conflict free, and the
+// epilogue writes a chunk of 64 consecutive rows as one contiguous 1 KB
+// store.
 // ---------------------------------------------------------------------------
 
 constexpr int kPlaneRows = 256;
 constexpr int kPlaneCols = 16;
 
-__device__ __forceinline__ int plane_swz(int r) { return ((r >> 2) ^ (r >> 3)) & 1; }
-
 // Element offset of (i, k) in the tiled plane of an np x np matrix.
 __device__ __forceinline__ int64_t plane_off(int64_t i, int64_t k, int64_t np) {
   const int64_t blk = (i >> 8) * (np >> 4) + (k >> 4);
-  const int r = static_cast<int>(i & 255), c = static_cast<int>(k & 15);
-  return (blk * 256 + r) * 16 + (((c >> 3) ^ plane_swz(r)) << 3) + (c & 7);
+  return blk * 4096 + ((k >> 3) & 1) * 2048 + (i & 255) * 8 + (k & 7);
 }
 
 // ---------------------------------------------------------------------------

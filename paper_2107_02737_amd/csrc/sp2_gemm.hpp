@@ -260,50 +260,40 @@ __device__ __forceinline__ void sym_epilogue(const f32x16 (&acc)[MI][NI], const 
 
 // ---------------------------------------------------------------------------
 // LDS-staged epilogue of the 256 x 256 split tile (4 waves of 128 x 128).
-// Two passes, one per 128-row half: the two waves that own the half write
-// their final values (alpha*acc + beta*C) into a padded [128][257] FP32 LDS
-// image and accumulate the trace partials; then all 256 threads copy the
-// half out in 8-element runs -- rows of the tile (direct) and rows of the
-// mirrored tile (columns of the image) -- as FP32 and, when requested, as
-// the hi/lo pair in the K-tiled plane layout.  On diagonal tiles only
-// elements on or above the diagonal are used, each also mirrored, so the
-// result is exactly symmetric.
+// One round per 128-row half: the two waves that own the half dump their
+// accumulators into a [128][257] FP32 LDS image (odd row stride: a column
+// read by consecutive lanes and a row read by consecutive lanes are both
+// bank-conflict free).  Then four passes over the image, each mapping
+// lanes so that every global access of a wave is contiguous: (A) upper
+// elements, v = alpha acc + beta C, FP32 result and FP64 traces, v written
+// back; (B) upper elements as hi/lo planes, lane = row; (C) the mirrored
+// FP32 result, lane = image row; (D) the mirrored planes, lane = image
+// column.  On diagonal tiles only elements on or above the diagonal are
+// taken, each also mirrored, so the result is exactly symmetric.
 // ---------------------------------------------------------------------------
 
 constexpr int kEpiLd = 257;   // padded LDS row (floats)
 
-__device__ __forceinline__ void store_run8(const Epi& p, int64_t row, int64_t col0, const float (&v)[8],
-                                           int first, int last) {
-  // elements [first, last) of the run (row, col0 .. col0+7)
-  const int64_t np = p.np;
-  if (row >= p.n_valid) return;
-  if (first == 0 && last == 8 && col0 + 8 <= p.n_valid && p.vec_ok) {
-    float* o = p.out + row * p.ld_out + col0;
-    *reinterpret_cast<f32x4*>(o) = f32x4{v[0], v[1], v[2], v[3]};
-    *reinterpret_cast<f32x4*>(o + 4) = f32x4{v[4], v[5], v[6], v[7]};
+// Elements [first, last) of 8 consecutive plane elements starting at
+// offset o (one chunk row) as the hi/lo pair.
+__device__ __forceinline__ void store_planes8(const Epi& p, int64_t o, const float (&v)[8], int first,
+                                              int last) {
+  uint16_t h[8], l[8];
+#pragma clang loop unroll(full)
+  for (int e = 0; e < 8; ++e) split_value(v[e], p.split_out, h[e], l[e]);
+  if (first == 0 && last == 8) {
+    u32x4 hv, lv;
+#pragma clang loop unroll(full)
+    for (int e = 0; e < 4; ++e) {
+      hv[e] = uint32_t(h[2 * e]) | (uint32_t(h[2 * e + 1]) << 16);
+      lv[e] = uint32_t(l[2 * e]) | (uint32_t(l[2 * e + 1]) << 16);
+    }
+    *reinterpret_cast<u32x4*>(p.hi_out + o) = hv;
+    *reinterpret_cast<u32x4*>(p.lo_out + o) = lv;
   } else {
-    for (int e = first; e < last; ++e)
-      if (col0 + e < p.n_valid) p.out[row * p.ld_out + col0 + e] = v[e];
-  }
-  if (p.split_out) {
-    uint16_t h[8], l[8];
-#pragma clang loop unroll(full)
-    for (int e = 0; e < 8; ++e) split_value(v[e], p.split_out, h[e], l[e]);
-    const int64_t o = plane_off(row, col0, np);   // a run of 8 never crosses a chunk
-    if (first == 0 && last == 8) {
-      u32x4 hv, lv;
-#pragma clang loop unroll(full)
-      for (int e = 0; e < 4; ++e) {
-        hv[e] = uint32_t(h[2 * e]) | (uint32_t(h[2 * e + 1]) << 16);
-        lv[e] = uint32_t(l[2 * e]) | (uint32_t(l[2 * e + 1]) << 16);
-      }
-      *reinterpret_cast<u32x4*>(p.hi_out + o) = hv;
-      *reinterpret_cast<u32x4*>(p.lo_out + o) = lv;
-    } else {
-      for (int e = first; e < last; ++e) {
-        p.hi_out[o + e] = h[e];
-        p.lo_out[o + e] = l[e];
-      }
+    for (int e = first; e < last; ++e) {
+      p.hi_out[o + e] = h[e];
+      p.lo_out[o + e] = l[e];
     }
   }
 }
@@ -312,10 +302,13 @@ template <int NT, int MI, int NI>
 __device__ __forceinline__ void sym_epilogue_lds(const f32x16 (&acc)[MI][NI], const Epi& p, float alpha,
                                                  float beta, int ti, int tj, int wm, int wn, int lane,
                                                  double* red, int tile, float* img) {
-  constexpr int BM = 256, TM = 128, TN = 128;
+  static_assert(NT == 256, "four waves");
+  constexpr int BM = 256, TM = 128, TN = 128, S = kEpiLd;
   const int64_t np = p.np;
   const bool diag = ti == tj;
-  const int tid = threadIdx.x;
+  const int w = threadIdx.x / kWave;
+  const int64_t R0 = int64_t(ti) * BM, C0 = int64_t(tj) * BM;   // tile origin
+  const int64_t nv = p.n_valid;
   double t1 = 0.0, t2 = 0.0;
   for (int half = 0; half < 2; ++half) {
     __syncthreads();   // the image (and before it, the operand ring) is free
@@ -329,71 +322,81 @@ __device__ __forceinline__ void sym_epilogue_lds(const f32x16 (&acc)[MI][NI], co
           for (int q = 0; q < 4; ++q)
 #pragma clang loop unroll(full)
             for (int e = 0; e < 4; ++e)
-              img[(mi * 32 + 8 * q + 4 * (lane >> 5) + e) * kEpiLd + cl] = acc[mi][ni][4 * q + e] * p.oscale;
+              img[(mi * 32 + 8 * q + 4 * (lane >> 5) + e) * S + cl] = acc[mi][ni][4 * q + e] * p.oscale;
         }
     }
     __syncthreads();
-    // direct runs: 128 rows x 32 runs of 8 columns; mirrored runs: 256 rows
-    // (tile columns) x 16 runs of 8 rows of the half.  C is symmetric, so the
-    // mirrored run reads it at the mirrored position.
-    for (int task = tid; task < 8192; task += NT) {
-      float v[8], c[8];
-      int64_t row, col0;
-      int first = 0, last = 8;
-      bool direct = task < 4096;
-      if (direct) {
-        const int rh = task >> 5, c0 = (task & 31) * 8;
-        const int rl = half * TM + rh;
+    const int hr = half * TM;   // tile row of image row 0
+    // Pass A, upper elements: v = alpha acc + beta C, FP32 result, traces;
+    // v goes back into the image for the other passes (C is symmetric, so
+    // the mirrored element takes the same v).  Lane = column (4 of them),
+    // wave = every 4th row: every access is 64 consecutive floats.
+    for (int rh = w; rh < TM; rh += 4) {
+      const int rl = hr + rh;
+      const int64_t row = R0 + rl;
 #pragma clang loop unroll(full)
-        for (int e = 0; e < 8; ++e) v[e] = img[rh * kEpiLd + c0 + e];
-        if (diag) first = rl <= c0 ? 0 : (rl >= c0 + 8 ? 8 : rl - c0);   // columns >= row
-        row = int64_t(ti) * BM + rl;
-        col0 = int64_t(tj) * BM + c0;
-      } else {
-        const int t = task - 4096;
-        const int cl = t >> 4, r0 = (t & 15) * 8;   // image column, first image row of the run
-#pragma clang loop unroll(full)
-        for (int e = 0; e < 8; ++e) v[e] = img[(r0 + e) * kEpiLd + cl];
-        const int rl0 = half * TM + r0;
-        if (diag) last = rl0 + 8 <= cl ? 8 : (rl0 >= cl ? 0 : cl - rl0);   // rows < column
-        row = int64_t(tj) * BM + cl;
-        col0 = int64_t(ti) * BM + rl0;
-      }
-      if (first >= last) continue;
-      if (beta != 0.0f) {
-        const float* cp = p.c + row * np + col0;
-        if (first == 0 && last == 8) {
-          const f32x4 a = *reinterpret_cast<const f32x4*>(cp);
-          const f32x4 b = *reinterpret_cast<const f32x4*>(cp + 4);
-#pragma clang loop unroll(full)
-          for (int e = 0; e < 4; ++e) {
-            c[e] = a[e];
-            c[4 + e] = b[e];
-          }
+      for (int j = 0; j < 4; ++j) {
+        const int c = lane + 64 * j;
+        float v = img[rh * S + c];
+        if (diag && c < rl) continue;   // below the diagonal: mirrored from above
+        const int64_t col = C0 + c;
+        v = beta != 0.0f ? alpha * v + beta * p.c[row * np + col] : alpha * v;
+        img[rh * S + c] = v;
+        const double d = static_cast<double>(v);
+        if (diag && c == rl) {
+          t1 += d;
+          t2 += d * d;
         } else {
-#pragma clang loop unroll(full)
-          for (int e = 0; e < 8; ++e) c[e] = (e >= first && e < last) ? cp[e] : 0.0f;
+          t2 += 2.0 * d * d;   // each unordered pair counted once
         }
-#pragma clang loop unroll(full)
-        for (int e = 0; e < 8; ++e) v[e] = alpha * v[e] + beta * c[e];
-      } else {
-#pragma clang loop unroll(full)
-        for (int e = 0; e < 8; ++e) v[e] = alpha * v[e];
+        if (p.out && row < nv && col < nv) p.out[row * p.ld_out + col] = v;
       }
-      if (direct) {   // each unordered pair is counted once, from its upper element
+    }
+    __syncthreads();
+    // Pass B, upper elements as hi/lo planes: lane = row (64 consecutive
+    // rows: one contiguous 1 KB store per chunk of 8 columns).
+    if (p.split_out) {
+      const int rh = (w & 1) * 64 + lane;
+      const int rl = hr + rh;
+      const int64_t row = R0 + rl;
+      for (int k8 = w >> 1; k8 < BM / 8; k8 += 2) {
+        const int c0 = k8 * 8;
+        const int first = !diag ? 0 : (rl <= c0 ? 0 : (rl >= c0 + 8 ? 8 : rl - c0));
+        if (first >= 8) continue;
+        float v[8];
 #pragma clang loop unroll(full)
-        for (int e = 0; e < 8; ++e) {
-          if (e < first) continue;
-          const double d = static_cast<double>(v[e]);
-          if (row == col0 + e) {
-            t1 += d;
-            t2 += d * d;
-          } else {
-            t2 += 2.0 * d * d;
-          }
-        }
+        for (int e = 0; e < 8; ++e) v[e] = img[rh * S + c0 + e];
+        store_planes8(p, plane_off(row, C0 + c0, np), v, first, 8);
       }
-      store_run8(p, row, col0, v, first, last);
+    }
+    // Pass C, mirrored FP32: output row C0 + cl, columns R0 + hr + r; lane =
+    // image row (64 consecutive output columns per store).
+    if (p.out) {
+      const int r = (w & 1) * 64 + lane;
+      const int rl = hr + r;
+      const int64_t col = R0 + rl;
+      const int cb = (w >> 1) * 128;
+      for (int cl = cb; cl < cb + 128; ++cl) {
+        const float v = img[r * S + cl];
+        if (diag && !(rl < cl)) continue;   // strict upper elements only
+        const int64_t row = C0 + cl;
+        if (row < nv && col < nv) p.out[row * p.ld_out + col] = v;
+      }
+    }
+    // Pass D, mirrored planes: lane = output row C0 + cl (64 consecutive
+    // rows per chunk store), chunks of 8 image rows.
+    if (p.split_out) {
+      const int cl = w * 64 + lane;
+      const int64_t row = C0 + cl;
+      for (int k8 = 0; k8 < TM / 8; ++k8) {
+        const int r0 = k8 * 8, rl0 = hr + r0;
+        const int last = !diag ? 8 : (rl0 + 8 <= cl ? 8 : (rl0 >= cl ? 0 : cl - rl0));
+        if (last <= 0) continue;
+        float v[8];
+#pragma clang loop unroll(full)
+        for (int e = 0; e < 8; ++e) v[e] = img[(r0 + e) * S + cl];
+        store_planes8(p, plane_off(row, R0 + rl0, np), v, 0, last);
+      }
     }
   }
   if (p.parts_out) {
@@ -502,12 +505,11 @@ void k_sym_split(SplitArgs p) {
     }                                                                                     \
   }
 
-  // Fragment addresses (bytes within a slot).  Row r of a 32-row block,
-  // h = lane/32 reads logical chunk h, stored at h ^ plane_swz(r)
-  // (plane_swz only sees rows bits 2-3, which a multiple of 32 rows keeps).
-  const int r = lane & 31, h = lane >> 5, sw = plane_swz(r);
-  const int fa = (wm * TM + r) * 32 + ((h ^ sw) << 4);
-  const int fb = (wn * TN + r) * 32 + ((h ^ sw) << 4);
+  // Fragment addresses (bytes within a slot): row r of a 32-row block,
+  // h = lane/32 reads column chunk h (16 bytes per row, chunk h at +4 KB).
+  const int r = lane & 31, h = lane >> 5;
+  const int fa = h * 4096 + (wm * TM + r) * 16;
+  const int fb = h * 4096 + (wn * TN + r) * 16;
   const char* L = reinterpret_cast<const char*>(lds);
 
   f32x16 acc[MI][NI];
@@ -525,14 +527,14 @@ void k_sym_split(SplitArgs p) {
   {                                                                                       \
     const char* S_ = L + (SLOT) * SLOT_B;                                                 \
     _Pragma("clang loop unroll(full)") for (int mi = 0; mi < MI; ++mi)                    \
-      AH[mi] = *reinterpret_cast<const u32x4*>(S_ + 0 * PLANE_B + fa + mi * 1024);        \
+      AH[mi] = *reinterpret_cast<const u32x4*>(S_ + 0 * PLANE_B + fa + mi * 512);         \
     _Pragma("clang loop unroll(full)") for (int ni = 0; ni < NI; ++ni)                    \
-      BH[ni] = *reinterpret_cast<const u32x4*>(S_ + 2 * PLANE_B + fb + ni * 1024);        \
+      BH[ni] = *reinterpret_cast<const u32x4*>(S_ + 2 * PLANE_B + fb + ni * 512);         \
     if constexpr (kLo) {                                                                  \
       _Pragma("clang loop unroll(full)") for (int ni = 0; ni < NI; ++ni)                  \
-        BL[ni] = *reinterpret_cast<const u32x4*>(S_ + 3 * PLANE_B + fb + ni * 1024);      \
+        BL[ni] = *reinterpret_cast<const u32x4*>(S_ + 3 * PLANE_B + fb + ni * 512);       \
       _Pragma("clang loop unroll(full)") for (int mi = 0; mi < MI; ++mi)                  \
-        AL[mi] = *reinterpret_cast<const u32x4*>(S_ + 1 * PLANE_B + fa + mi * 1024);      \
+        AL[mi] = *reinterpret_cast<const u32x4*>(S_ + 1 * PLANE_B + fa + mi * 512);       \
     }                                                                                     \
   }
 
