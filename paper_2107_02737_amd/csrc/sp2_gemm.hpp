@@ -132,19 +132,22 @@ __device__ __forceinline__ bool reduce_tail(f32x16 (&acc)[MI][NI], const Decomp&
       for (int r = 0; r < 16; ++r) acc[mi][ni][r] = 0.0f;
   for (int q = 0; q < dc.nsplit; ++q) {
     const float* src = dc.partial + (int64_t(tail) * dc.nsplit + q) * (NT * ACC);
+    // one 32x32 block (4 loads) per group, all loads of a group in flight
 #pragma clang loop unroll(full)
     for (int mi = 0; mi < MI; ++mi)
 #pragma clang loop unroll(full)
-      for (int ni = 0; ni < NI; ++ni)
+      for (int ni = 0; ni < NI; ++ni) {
+        f32x4 x[4];
 #pragma clang loop unroll(full)
         for (int r4 = 0; r4 < 4; ++r4) {
           const int v = (mi * NI + ni) * 4 + r4;
-          const f32x4 x = *reinterpret_cast<const f32x4*>(src + (int64_t(v) * NT + tid) * 4);
-          acc[mi][ni][4 * r4] += x[0];
-          acc[mi][ni][4 * r4 + 1] += x[1];
-          acc[mi][ni][4 * r4 + 2] += x[2];
-          acc[mi][ni][4 * r4 + 3] += x[3];
+          x[r4] = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(src + (int64_t(v) * NT + tid) * 4));
         }
+#pragma clang loop unroll(full)
+        for (int r4 = 0; r4 < 4; ++r4)
+#pragma clang loop unroll(full)
+          for (int e = 0; e < 4; ++e) acc[mi][ni][4 * r4 + e] += x[r4][e];
+      }
   }
   if (tid == 0) dc.counter[tail] = 0;   // ready for the next launch
   return true;
@@ -291,10 +294,12 @@ __device__ __forceinline__ void store_planes8(const Epi& p, int64_t o, const flo
     *reinterpret_cast<u32x4*>(p.hi_out + o) = hv;
     *reinterpret_cast<u32x4*>(p.lo_out + o) = lv;
   } else {
-    for (int e = first; e < last; ++e) {
-      p.hi_out[o + e] = h[e];
-      p.lo_out[o + e] = l[e];
-    }
+#pragma clang loop unroll(full)
+    for (int e = 0; e < 8; ++e)
+      if (e >= first && e < last) {
+        p.hi_out[o + e] = h[e];
+        p.lo_out[o + e] = l[e];
+      }
   }
 }
 
@@ -322,34 +327,55 @@ __device__ __forceinline__ void sym_epilogue_lds(const f32x16 (&acc)[MI][NI], co
           for (int q = 0; q < 4; ++q)
 #pragma clang loop unroll(full)
             for (int e = 0; e < 4; ++e)
-              img[(mi * 32 + 8 * q + 4 * (lane >> 5) + e) * S + cl] = acc[mi][ni][4 * q + e] * p.oscale;
+              img[(mi * 32 + 8 * q + 4 * (lane >> 5) + e) * S + cl] = acc[mi][ni][4 * q + e];
         }
     }
     __syncthreads();
     const int hr = half * TM;   // tile row of image row 0
+    const float as = alpha * p.oscale;   // exact: oscale is a power of two
     // Pass A, upper elements: v = alpha acc + beta C, FP32 result, traces;
     // v goes back into the image for the other passes (C is symmetric, so
     // the mirrored element takes the same v).  Lane = column (4 of them),
-    // wave = every 4th row: every access is 64 consecutive floats.
-    for (int rh = w; rh < TM; rh += 4) {
-      const int rl = hr + rh;
-      const int64_t row = R0 + rl;
+    // wave = every 4th row, 4 rows per step: every access is 64 consecutive
+    // floats and 16 loads are in flight per lane.
+    for (int rb = 0; rb < TM / 4; rb += 4) {
+      float v[4][4], cv[4][4];
 #pragma clang loop unroll(full)
-      for (int j = 0; j < 4; ++j) {
-        const int c = lane + 64 * j;
-        float v = img[rh * S + c];
-        if (diag && c < rl) continue;   // below the diagonal: mirrored from above
-        const int64_t col = C0 + c;
-        v = beta != 0.0f ? alpha * v + beta * p.c[row * np + col] : alpha * v;
-        img[rh * S + c] = v;
-        const double d = static_cast<double>(v);
-        if (diag && c == rl) {
-          t1 += d;
-          t2 += d * d;
-        } else {
-          t2 += 2.0 * d * d;   // each unordered pair counted once
+      for (int i = 0; i < 4; ++i)
+#pragma clang loop unroll(full)
+        for (int j = 0; j < 4; ++j) v[i][j] = img[(w + 4 * (rb + i)) * S + lane + 64 * j];
+      if (beta != 0.0f) {
+#pragma clang loop unroll(full)
+        for (int i = 0; i < 4; ++i)
+#pragma clang loop unroll(full)
+          for (int j = 0; j < 4; ++j)
+            cv[i][j] = p.c[(R0 + hr + w + 4 * (rb + i)) * np + C0 + lane + 64 * j];
+#pragma clang loop unroll(full)
+        for (int i = 0; i < 4; ++i)
+#pragma clang loop unroll(full)
+          for (int j = 0; j < 4; ++j) v[i][j] = as * v[i][j] + beta * cv[i][j];
+      } else {
+#pragma clang loop unroll(full)
+        for (int i = 0; i < 4; ++i)
+#pragma clang loop unroll(full)
+          for (int j = 0; j < 4; ++j) v[i][j] = as * v[i][j];
+      }
+#pragma clang loop unroll(full)
+      for (int i = 0; i < 4; ++i) {
+        const int rh = w + 4 * (rb + i), rl = hr + rh;
+        const int64_t row = R0 + rl;
+#pragma clang loop unroll(full)
+        for (int j = 0; j < 4; ++j) {
+          const int c = lane + 64 * j;
+          img[rh * S + c] = v[i][j];
+          const bool up = !diag || c >= rl;   // below the diagonal: mirrored from above
+          const bool on = diag && c == rl;
+          const double d = up ? static_cast<double>(v[i][j]) : 0.0;
+          t1 += on ? d : 0.0;
+          t2 += (on ? 1.0 : 2.0) * d * d;     // each unordered pair counted once
+          const int64_t col = C0 + c;
+          if (p.out && up && row < nv && col < nv) p.out[row * p.ld_out + col] = v[i][j];
         }
-        if (p.out && row < nv && col < nv) p.out[row * p.ld_out + col] = v;
       }
     }
     __syncthreads();
@@ -359,28 +385,37 @@ __device__ __forceinline__ void sym_epilogue_lds(const f32x16 (&acc)[MI][NI], co
       const int rh = (w & 1) * 64 + lane;
       const int rl = hr + rh;
       const int64_t row = R0 + rl;
-      for (int k8 = w >> 1; k8 < BM / 8; k8 += 2) {
-        const int c0 = k8 * 8;
-        const int first = !diag ? 0 : (rl <= c0 ? 0 : (rl >= c0 + 8 ? 8 : rl - c0));
-        if (first >= 8) continue;
-        float v[8];
+      for (int k8 = w >> 1; k8 < BM / 8; k8 += 4) {
+        float v[2][8];
 #pragma clang loop unroll(full)
-        for (int e = 0; e < 8; ++e) v[e] = img[rh * S + c0 + e];
-        store_planes8(p, plane_off(row, C0 + c0, np), v, first, 8);
+        for (int u = 0; u < 2; ++u)
+#pragma clang loop unroll(full)
+          for (int e = 0; e < 8; ++e) v[u][e] = img[rh * S + (k8 + 2 * u) * 8 + e];
+#pragma clang loop unroll(full)
+        for (int u = 0; u < 2; ++u) {
+          const int c0 = (k8 + 2 * u) * 8;
+          const int first = !diag ? 0 : (rl <= c0 ? 0 : (rl >= c0 + 8 ? 8 : rl - c0));
+          store_planes8(p, plane_off(row, C0 + c0, np), v[u], first, 8);
+        }
       }
     }
     // Pass C, mirrored FP32: output row C0 + cl, columns R0 + hr + r; lane =
-    // image row (64 consecutive output columns per store).
+    // image row (64 consecutive output columns per store), 8 columns per step.
     if (p.out) {
       const int r = (w & 1) * 64 + lane;
       const int rl = hr + r;
       const int64_t col = R0 + rl;
       const int cb = (w >> 1) * 128;
-      for (int cl = cb; cl < cb + 128; ++cl) {
-        const float v = img[r * S + cl];
-        if (diag && !(rl < cl)) continue;   // strict upper elements only
-        const int64_t row = C0 + cl;
-        if (row < nv && col < nv) p.out[row * p.ld_out + col] = v;
+      for (int cl0 = cb; cl0 < cb + 128; cl0 += 8) {
+        float v[8];
+#pragma clang loop unroll(full)
+        for (int e = 0; e < 8; ++e) v[e] = img[r * S + cl0 + e];
+#pragma clang loop unroll(full)
+        for (int e = 0; e < 8; ++e) {
+          const int cl = cl0 + e;
+          const int64_t row = C0 + cl;
+          if ((!diag || rl < cl) && row < nv && col < nv) p.out[row * p.ld_out + col] = v[e];
+        }
       }
     }
     // Pass D, mirrored planes: lane = output row C0 + cl (64 consecutive
@@ -388,14 +423,18 @@ __device__ __forceinline__ void sym_epilogue_lds(const f32x16 (&acc)[MI][NI], co
     if (p.split_out) {
       const int cl = w * 64 + lane;
       const int64_t row = C0 + cl;
-      for (int k8 = 0; k8 < TM / 8; ++k8) {
-        const int r0 = k8 * 8, rl0 = hr + r0;
-        const int last = !diag ? 8 : (rl0 + 8 <= cl ? 8 : (rl0 >= cl ? 0 : cl - rl0));
-        if (last <= 0) continue;
-        float v[8];
+      for (int k8 = 0; k8 < TM / 8; k8 += 2) {
+        float v[2][8];
 #pragma clang loop unroll(full)
-        for (int e = 0; e < 8; ++e) v[e] = img[(r0 + e) * S + cl];
-        store_planes8(p, plane_off(row, R0 + rl0, np), v, 0, last);
+        for (int u = 0; u < 2; ++u)
+#pragma clang loop unroll(full)
+          for (int e = 0; e < 8; ++e) v[u][e] = img[((k8 + u) * 8 + e) * S + cl];
+#pragma clang loop unroll(full)
+        for (int u = 0; u < 2; ++u) {
+          const int rl0 = hr + (k8 + u) * 8;
+          const int last = !diag ? 8 : (rl0 + 8 <= cl ? 8 : (rl0 >= cl ? 0 : cl - rl0));
+          store_planes8(p, plane_off(row, R0 + rl0, np), v[u], 0, last);
+        }
       }
     }
   }
