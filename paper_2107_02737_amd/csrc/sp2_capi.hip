@@ -96,7 +96,9 @@ bool make_layout(int64_t n, const sp2_options& o, Layout& L) {
   const int64_t quads = L.np * L.np / 4;
   L.init_blocks = static_cast<int>(std::min<int64_t>(kInitBlocksMax, (quads + kEwThreads - 1) / kEwThreads));
   L.gersh_blocks = static_cast<int>((n + kRowsPerBlock - 1) / kRowsPerBlock);
-  L.max_parts = std::max({L.ntiles_split, L.ntiles_f32, L.init_blocks, kInitBlocksMax});
+  // split layers: whole tiles + 8 strips per split-K tail tile
+  L.max_parts = std::max({L.ntiles_split + kTailStrips * std::min(L.ntiles_split, kMaxTailTiles),
+                          L.ntiles_f32, L.init_blocks, kInitBlocksMax});
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o2 = off;
@@ -336,16 +338,38 @@ sp2_status reset_counters(const WS& w, hipStream_t st) {
   return SP2_OK;
 }
 
+// Work decomposition of a split launch (the same on every call for a
+// given layout and device).
+template <int KIND>
+Decomp split_decomp(const WS& w) {
+  constexpr size_t piece = size_t(256) * 4 * 4 * 16 * 4;   // one 256x256 FP32 accumulator
+  const int slots = device_cus() * wgs_per_cu(k_sym_split<KIND>, 256);
+  return plan_decomp(w, static_cast<int>(w.L.np / 256), slots, static_cast<int>(w.L.np / 32), piece);
+}
+
+Decomp split_decomp_of(const WS& w, int precision) {
+  const int kind = split_kind_of(precision);
+  if (kind == kBF16X3) return split_decomp<kBF16X3>(w);
+  if (kind == kBF16X1) return split_decomp<kBF16X1>(w);
+  return split_decomp<kFP16X3>(w);
+}
+
+// Trace partial pairs written by one split launch: one per whole tile, one
+// per strip of every split-K tail tile.
+int split_nparts(const Decomp& d) { return d.nfull + kTailStrips * (d.ntiles - d.nfull); }
+
 template <int KIND>
 sp2_status launch_split_t(const WS& w, SplitArgs a, hipStream_t st) {
-  constexpr int NT = 256;
-  constexpr size_t piece = size_t(NT) * 4 * 4 * 16 * 4;   // one 256x256 FP32 accumulator
-  auto kern = k_sym_split<KIND>;
-  const int slots = device_cus() * wgs_per_cu(kern, NT);
-  a.dc = plan_decomp(w, static_cast<int>(w.L.np / 256), slots, static_cast<int>(w.L.np / 32), piece);
-  const int grid = a.dc.nfull + (a.dc.ntiles - a.dc.nfull) * a.dc.nsplit;
-  kern<<<grid, NT, 0, st>>>(a);
+  a.dc = split_decomp<KIND>(w);
+  const int ntail = a.dc.ntiles - a.dc.nfull;
+  const int grid = a.dc.nfull + ntail * a.dc.nsplit;
+  k_sym_split<KIND><<<grid, 256, 0, st>>>(a);
   LAUNCH_TRY();
+  if (ntail > 0) {
+    a.dec.quiet = 1;   // the product launch already recorded this layer's decision
+    k_split_tail<<<ntail * kTailStrips, 256, 0, st>>>(a);
+    LAUNCH_TRY();
+  }
   return SP2_OK;
 }
 
@@ -391,9 +415,9 @@ sp2_status launch_f32(const WS& w, int nseg, const float* const* A, const float*
   return SP2_OK;
 }
 
-int nparts_of_layer(const Layout& L, int precision, int layer) {
-  if (layer == 0) return L.init_blocks;
-  return precision == SP2_FP32 ? L.ntiles_f32 : L.ntiles_split;
+int nparts_of_layer(const WS& w, int precision, int layer) {
+  if (layer == 0) return w.L.init_blocks;
+  return precision == SP2_FP32 ? w.L.ntiles_f32 : split_nparts(split_decomp_of(w, precision));
 }
 
 // Where S_n lives in the forward network (FP32 value and hi/lo planes).
@@ -409,7 +433,7 @@ sp2_status launch_layer(const WS& w, int precision, int n, int mode, const float
   Decide d = make_decide(w, mode, n);
   if (mode == 1) {
     d.parts_in = w.parts[n & 1];
-    d.nparts_in = nparts_of_layer(w.L, precision, n);
+    d.nparts_in = nparts_of_layer(w, precision, n);
     d.n_occ = static_cast<double>(n_occ);
     d.tol = o->tol;
     d.stall_gate = o->stall_gate;
@@ -673,7 +697,7 @@ sp2_status sp2_density_ex(const float* H, int64_t n, int64_t ld, int64_t n_occ,
   if (hm->ctrl[0].nonfinite) return fail(SP2_ERR_NONFINITE, "H holds NaN or Inf");
   if (!hm->ctrl[0].stopped) {
     k_finish_loop<<<1, 256, 0, st>>>(w.ctrl, w.hist, w.parts[o.max_iter & 1],
-                                     nparts_of_layer(L, prec, o.max_iter), o.max_iter, o.tol,
+                                     nparts_of_layer(w, prec, o.max_iter), o.max_iter, o.tol,
                                      o.stop_rule, o.stall_gate);
     LAUNCH_TRY();
     n_iter = o.max_iter;
@@ -694,7 +718,9 @@ sp2_status sp2_density_ex(const float* H, int64_t n, int64_t ld, int64_t n_occ,
       return s;
     HIP_TRY(timer.mark(2 * refine_ev + 1, st));
     k_sum_parts<<<1, 256, 0, st>>>(w.ctrl, w.parts[0],
-                                   o.refine == SP2_REFINE_FP32 ? L.ntiles_f32 : L.ntiles_split);
+                                   o.refine == SP2_REFINE_FP32
+                                       ? L.ntiles_f32
+                                       : split_nparts(split_decomp_of(w, SP2_FP16X3)));
     LAUNCH_TRY();
   } else {
     k_copy_scaled<<<ew_grid(n * n), kEwThreads, 0, st>>>(S, L.np, P, ld, n, n, 1.0f, 0);

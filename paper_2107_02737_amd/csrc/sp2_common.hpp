@@ -53,6 +53,7 @@ struct Decide {
   int mode;                 // 0: fixed coefficients, 1: decide, 2: replay hist->branch
   double n_occ, tol, stall_gate;
   int stop_rule;
+  int quiet;                // 1: decide without recording (a second kernel of the same layer)
 };
 
 // ---------------------------------------------------------------------------
@@ -130,7 +131,7 @@ __device__ __forceinline__ int decide_layer(const Decide& d, double* red) {
     stop = true;
   // Trace-closest sign: Tr(S^2) = t2 versus Tr(2S - S^2) = 2 t1 - t2; ties take S^2.
   const int sign = (fabs(t2 - d.n_occ) <= fabs(2.0 * t1 - t2 - d.n_occ)) ? 1 : -1;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (!d.quiet && blockIdx.x == 0 && threadIdx.x == 0) {
     d.hist->t1[n] = t1;
     d.hist->t2[n] = t2;
     d.hist->err[n] = e;

@@ -132,22 +132,26 @@ __device__ __forceinline__ bool reduce_tail(f32x16 (&acc)[MI][NI], const Decomp&
       for (int r = 0; r < 16; ++r) acc[mi][ni][r] = 0.0f;
   for (int q = 0; q < dc.nsplit; ++q) {
     const float* src = dc.partial + (int64_t(tail) * dc.nsplit + q) * (NT * ACC);
-    // one 32x32 block (4 loads) per group, all loads of a group in flight
+    // four 32x32 blocks (16 loads of 16 bytes) in flight per group: the
+    // reload is latency-bound with the fragment registers free
 #pragma clang loop unroll(full)
-    for (int mi = 0; mi < MI; ++mi)
+    for (int mi = 0; mi < MI; ++mi) {
+      f32x4 x[NI][4];
 #pragma clang loop unroll(full)
-      for (int ni = 0; ni < NI; ++ni) {
-        f32x4 x[4];
+      for (int ni = 0; ni < NI; ++ni)
 #pragma clang loop unroll(full)
         for (int r4 = 0; r4 < 4; ++r4) {
           const int v = (mi * NI + ni) * 4 + r4;
-          x[r4] = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(src + (int64_t(v) * NT + tid) * 4));
+          x[ni][r4] = *reinterpret_cast<const f32x4*>(src + (int64_t(v) * NT + tid) * 4);
         }
+      __builtin_amdgcn_sched_group_barrier(0x020, NI * 4, 0);   // all 16 loads first
+#pragma clang loop unroll(full)
+      for (int ni = 0; ni < NI; ++ni)
 #pragma clang loop unroll(full)
         for (int r4 = 0; r4 < 4; ++r4)
 #pragma clang loop unroll(full)
-          for (int e = 0; e < 4; ++e) acc[mi][ni][4 * r4 + e] += x[r4][e];
-      }
+          for (int e = 0; e < 4; ++e) acc[mi][ni][4 * r4 + e] += x[ni][r4][e];
+    }
   }
   if (tid == 0) dc.counter[tail] = 0;   // ready for the next launch
   return true;
@@ -303,17 +307,131 @@ __device__ __forceinline__ void store_planes8(const Epi& p, int64_t o, const flo
   }
 }
 
+// The four passes over an image of H rows of one 256 x 256 tile (tile rows
+// hr .. hr+H-1), 256 threads.  as = alpha * output scale.  Adds the trace
+// contributions of the upper elements to (t1, t2).
+template <int H>
+__device__ __forceinline__ void epilogue_passes(const Epi& p, float as, float beta, int ti, int tj,
+                                                int hr, float* img, double& t1, double& t2) {
+  static_assert(H == 32 || H == 128, "image height");
+  constexpr int BM = 256, S = kEpiLd, G = BM / H;
+  const int64_t np = p.np;
+  const bool diag = ti == tj;
+  const int t = threadIdx.x, w = t / kWave, lane = t & (kWave - 1);
+  const int64_t R0 = int64_t(ti) * BM, C0 = int64_t(tj) * BM;   // tile origin
+  const int64_t nv = p.n_valid;
+  // Pass A, upper elements: v = alpha acc + beta C, FP32 result, traces;
+  // v goes back into the image for the other passes (C is symmetric, so
+  // the mirrored element takes the same v).  Lane = column (4 of them),
+  // wave = every 4th row, 4 rows per step: every access is 64 consecutive
+  // floats and 16 loads are in flight per lane.
+  for (int rb = 0; rb < H / 4; rb += 4) {
+    float v[4][4], cv[4][4];
+#pragma clang loop unroll(full)
+    for (int i = 0; i < 4; ++i)
+#pragma clang loop unroll(full)
+      for (int j = 0; j < 4; ++j) v[i][j] = img[(w + 4 * (rb + i)) * S + lane + 64 * j];
+    if (beta != 0.0f) {
+#pragma clang loop unroll(full)
+      for (int i = 0; i < 4; ++i)
+#pragma clang loop unroll(full)
+        for (int j = 0; j < 4; ++j)
+          cv[i][j] = p.c[(R0 + hr + w + 4 * (rb + i)) * np + C0 + lane + 64 * j];
+#pragma clang loop unroll(full)
+      for (int i = 0; i < 4; ++i)
+#pragma clang loop unroll(full)
+        for (int j = 0; j < 4; ++j) v[i][j] = as * v[i][j] + beta * cv[i][j];
+    } else {
+#pragma clang loop unroll(full)
+      for (int i = 0; i < 4; ++i)
+#pragma clang loop unroll(full)
+        for (int j = 0; j < 4; ++j) v[i][j] = as * v[i][j];
+    }
+#pragma clang loop unroll(full)
+    for (int i = 0; i < 4; ++i) {
+      const int rh = w + 4 * (rb + i), rl = hr + rh;
+      const int64_t row = R0 + rl;
+#pragma clang loop unroll(full)
+      for (int j = 0; j < 4; ++j) {
+        const int c = lane + 64 * j;
+        img[rh * S + c] = v[i][j];
+        const bool up = !diag || c >= rl;   // below the diagonal: mirrored from above
+        const bool on = diag && c == rl;
+        const double d = up ? static_cast<double>(v[i][j]) : 0.0;
+        t1 += on ? d : 0.0;
+        t2 += (on ? 1.0 : 2.0) * d * d;     // each unordered pair counted once
+        const int64_t col = C0 + c;
+        if (p.out && up && row < nv && col < nv) p.out[row * p.ld_out + col] = v[i][j];
+      }
+    }
+  }
+  __syncthreads();
+  // Pass B, upper elements as hi/lo planes: thread = row (consecutive rows:
+  // one contiguous store per chunk of 8 columns); the G thread groups take
+  // interleaved chunks.
+  if (p.split_out) {
+    const int rh = t % H, rl = hr + rh;
+    const int64_t row = R0 + rl;
+    for (int k8 = t / H; k8 < BM / 8; k8 += 2 * G) {
+      float v[2][8];
+#pragma clang loop unroll(full)
+      for (int u = 0; u < 2; ++u)
+#pragma clang loop unroll(full)
+        for (int e = 0; e < 8; ++e) v[u][e] = img[rh * S + (k8 + G * u) * 8 + e];
+#pragma clang loop unroll(full)
+      for (int u = 0; u < 2; ++u) {
+        const int c0 = (k8 + G * u) * 8;
+        const int first = !diag ? 0 : (rl <= c0 ? 0 : (rl >= c0 + 8 ? 8 : rl - c0));
+        store_planes8(p, plane_off(row, C0 + c0, np), v[u], first, 8);
+      }
+    }
+  }
+  // Pass C, mirrored FP32: output row C0 + cl, columns R0 + hr + r; thread =
+  // image row (consecutive output columns per store), 8 columns per step.
+  if (p.out) {
+    const int r = t % H, rl = hr + r;
+    const int64_t col = R0 + rl;
+    const int cb = (t / H) * H;
+    for (int cl0 = cb; cl0 < cb + H; cl0 += 8) {
+      float v[8];
+#pragma clang loop unroll(full)
+      for (int e = 0; e < 8; ++e) v[e] = img[r * S + cl0 + e];
+#pragma clang loop unroll(full)
+      for (int e = 0; e < 8; ++e) {
+        const int cl = cl0 + e;
+        const int64_t row = C0 + cl;
+        if ((!diag || rl < cl) && row < nv && col < nv) p.out[row * p.ld_out + col] = v[e];
+      }
+    }
+  }
+  // Pass D, mirrored planes: thread = output row C0 + cl (consecutive rows
+  // per chunk store), chunks of 8 image rows.
+  if (p.split_out) {
+    const int cl = t;
+    const int64_t row = C0 + cl;
+    for (int k8 = 0; k8 < H / 8; k8 += 2) {
+      float v[2][8];
+#pragma clang loop unroll(full)
+      for (int u = 0; u < 2; ++u)
+#pragma clang loop unroll(full)
+        for (int e = 0; e < 8; ++e) v[u][e] = img[((k8 + u) * 8 + e) * S + cl];
+#pragma clang loop unroll(full)
+      for (int u = 0; u < 2; ++u) {
+        const int rl0 = hr + (k8 + u) * 8;
+        const int last = !diag ? 8 : (rl0 + 8 <= cl ? 8 : (rl0 >= cl ? 0 : cl - rl0));
+        store_planes8(p, plane_off(row, R0 + rl0, np), v[u], 0, last);
+      }
+    }
+  }
+}
+
 template <int NT, int MI, int NI>
 __device__ __forceinline__ void sym_epilogue_lds(const f32x16 (&acc)[MI][NI], const Epi& p, float alpha,
                                                  float beta, int ti, int tj, int wm, int wn, int lane,
                                                  double* red, int tile, float* img) {
   static_assert(NT == 256, "four waves");
-  constexpr int BM = 256, TM = 128, TN = 128, S = kEpiLd;
-  const int64_t np = p.np;
-  const bool diag = ti == tj;
-  const int w = threadIdx.x / kWave;
-  const int64_t R0 = int64_t(ti) * BM, C0 = int64_t(tj) * BM;   // tile origin
-  const int64_t nv = p.n_valid;
+  constexpr int TM = 128, TN = 128, S = kEpiLd;
+  const float as = alpha * p.oscale;   // exact: oscale is a power of two
   double t1 = 0.0, t2 = 0.0;
   for (int half = 0; half < 2; ++half) {
     __syncthreads();   // the image (and before it, the operand ring) is free
@@ -331,112 +449,7 @@ __device__ __forceinline__ void sym_epilogue_lds(const f32x16 (&acc)[MI][NI], co
         }
     }
     __syncthreads();
-    const int hr = half * TM;   // tile row of image row 0
-    const float as = alpha * p.oscale;   // exact: oscale is a power of two
-    // Pass A, upper elements: v = alpha acc + beta C, FP32 result, traces;
-    // v goes back into the image for the other passes (C is symmetric, so
-    // the mirrored element takes the same v).  Lane = column (4 of them),
-    // wave = every 4th row, 4 rows per step: every access is 64 consecutive
-    // floats and 16 loads are in flight per lane.
-    for (int rb = 0; rb < TM / 4; rb += 4) {
-      float v[4][4], cv[4][4];
-#pragma clang loop unroll(full)
-      for (int i = 0; i < 4; ++i)
-#pragma clang loop unroll(full)
-        for (int j = 0; j < 4; ++j) v[i][j] = img[(w + 4 * (rb + i)) * S + lane + 64 * j];
-      if (beta != 0.0f) {
-#pragma clang loop unroll(full)
-        for (int i = 0; i < 4; ++i)
-#pragma clang loop unroll(full)
-          for (int j = 0; j < 4; ++j)
-            cv[i][j] = p.c[(R0 + hr + w + 4 * (rb + i)) * np + C0 + lane + 64 * j];
-#pragma clang loop unroll(full)
-        for (int i = 0; i < 4; ++i)
-#pragma clang loop unroll(full)
-          for (int j = 0; j < 4; ++j) v[i][j] = as * v[i][j] + beta * cv[i][j];
-      } else {
-#pragma clang loop unroll(full)
-        for (int i = 0; i < 4; ++i)
-#pragma clang loop unroll(full)
-          for (int j = 0; j < 4; ++j) v[i][j] = as * v[i][j];
-      }
-#pragma clang loop unroll(full)
-      for (int i = 0; i < 4; ++i) {
-        const int rh = w + 4 * (rb + i), rl = hr + rh;
-        const int64_t row = R0 + rl;
-#pragma clang loop unroll(full)
-        for (int j = 0; j < 4; ++j) {
-          const int c = lane + 64 * j;
-          img[rh * S + c] = v[i][j];
-          const bool up = !diag || c >= rl;   // below the diagonal: mirrored from above
-          const bool on = diag && c == rl;
-          const double d = up ? static_cast<double>(v[i][j]) : 0.0;
-          t1 += on ? d : 0.0;
-          t2 += (on ? 1.0 : 2.0) * d * d;     // each unordered pair counted once
-          const int64_t col = C0 + c;
-          if (p.out && up && row < nv && col < nv) p.out[row * p.ld_out + col] = v[i][j];
-        }
-      }
-    }
-    __syncthreads();
-    // Pass B, upper elements as hi/lo planes: lane = row (64 consecutive
-    // rows: one contiguous 1 KB store per chunk of 8 columns).
-    if (p.split_out) {
-      const int rh = (w & 1) * 64 + lane;
-      const int rl = hr + rh;
-      const int64_t row = R0 + rl;
-      for (int k8 = w >> 1; k8 < BM / 8; k8 += 4) {
-        float v[2][8];
-#pragma clang loop unroll(full)
-        for (int u = 0; u < 2; ++u)
-#pragma clang loop unroll(full)
-          for (int e = 0; e < 8; ++e) v[u][e] = img[rh * S + (k8 + 2 * u) * 8 + e];
-#pragma clang loop unroll(full)
-        for (int u = 0; u < 2; ++u) {
-          const int c0 = (k8 + 2 * u) * 8;
-          const int first = !diag ? 0 : (rl <= c0 ? 0 : (rl >= c0 + 8 ? 8 : rl - c0));
-          store_planes8(p, plane_off(row, C0 + c0, np), v[u], first, 8);
-        }
-      }
-    }
-    // Pass C, mirrored FP32: output row C0 + cl, columns R0 + hr + r; lane =
-    // image row (64 consecutive output columns per store), 8 columns per step.
-    if (p.out) {
-      const int r = (w & 1) * 64 + lane;
-      const int rl = hr + r;
-      const int64_t col = R0 + rl;
-      const int cb = (w >> 1) * 128;
-      for (int cl0 = cb; cl0 < cb + 128; cl0 += 8) {
-        float v[8];
-#pragma clang loop unroll(full)
-        for (int e = 0; e < 8; ++e) v[e] = img[r * S + cl0 + e];
-#pragma clang loop unroll(full)
-        for (int e = 0; e < 8; ++e) {
-          const int cl = cl0 + e;
-          const int64_t row = C0 + cl;
-          if ((!diag || rl < cl) && row < nv && col < nv) p.out[row * p.ld_out + col] = v[e];
-        }
-      }
-    }
-    // Pass D, mirrored planes: lane = output row C0 + cl (64 consecutive
-    // rows per chunk store), chunks of 8 image rows.
-    if (p.split_out) {
-      const int cl = w * 64 + lane;
-      const int64_t row = C0 + cl;
-      for (int k8 = 0; k8 < TM / 8; k8 += 2) {
-        float v[2][8];
-#pragma clang loop unroll(full)
-        for (int u = 0; u < 2; ++u)
-#pragma clang loop unroll(full)
-          for (int e = 0; e < 8; ++e) v[u][e] = img[((k8 + u) * 8 + e) * S + cl];
-#pragma clang loop unroll(full)
-        for (int u = 0; u < 2; ++u) {
-          const int rl0 = hr + (k8 + u) * 8;
-          const int last = !diag ? 8 : (rl0 + 8 <= cl ? 8 : (rl0 >= cl ? 0 : cl - rl0));
-          store_planes8(p, plane_off(row, R0 + rl0, np), v[u], 0, last);
-        }
-      }
-    }
+    epilogue_passes<TM>(p, as, beta, ti, tj, half * TM, img, t1, t2);
   }
   if (p.parts_out) {
     block_sum2<NT>(t1, t2, red);
@@ -445,6 +458,25 @@ __device__ __forceinline__ void sym_epilogue_lds(const f32x16 (&acc)[MI][NI], co
       p.parts_out[2 * tile + 1] = t2;
     }
   }
+}
+
+// Split-K tail: a piece stores its raw accumulator (layout: 16 floats per
+// block, 4 at a time, thread-minor) for k_split_tail to sum.
+template <int NT, int MI, int NI>
+__device__ __forceinline__ void store_piece(const f32x16 (&acc)[MI][NI], const Decomp& dc, int tail,
+                                            int piece) {
+  float* mine = dc.partial + (int64_t(tail) * dc.nsplit + piece) * (NT * MI * NI * 16);
+#pragma clang loop unroll(full)
+  for (int mi = 0; mi < MI; ++mi)
+#pragma clang loop unroll(full)
+    for (int ni = 0; ni < NI; ++ni)
+#pragma clang loop unroll(full)
+      for (int r4 = 0; r4 < 4; ++r4) {
+        const int v = (mi * NI + ni) * 4 + r4;
+        *reinterpret_cast<f32x4*>(mine + (int64_t(v) * NT + threadIdx.x) * 4) =
+            f32x4{acc[mi][ni][4 * r4], acc[mi][ni][4 * r4 + 1], acc[mi][ni][4 * r4 + 2],
+                  acc[mi][ni][4 * r4 + 3]};
+      }
 }
 
 // ---------------------------------------------------------------------------
@@ -640,9 +672,79 @@ void k_sym_split(SplitArgs p) {
 #undef SP2_MFMA
 #undef SP2_INTERLEAVE
 #undef SP2_STEP
-  if (tail >= 0 && !reduce_tail<NT, MI, NI>(acc, p.dc, tail, piece)) return;
+  if (tail >= 0) {   // summed and finished by k_split_tail
+    store_piece<NT, MI, NI>(acc, p.dc, tail, piece);
+    return;
+  }
   sym_epilogue_lds<NT, MI, NI>(acc, p.epi, alpha, beta, ti, tj, wm, wn, lane, red, tile,
                                reinterpret_cast<float*>(lds));
+}
+
+// ---------------------------------------------------------------------------
+// Split-K tail of k_sym_split, spread over the machine: work-group
+// (tail tile, strip) sums the nsplit stored pieces of 32 rows of the tile in
+// piece order (so the result does not depend on which piece finished last)
+// and runs the epilogue passes on that strip.  Strip s holds rows
+// 32 s .. 32 s + 31, i.e. accumulator block mi = s % 4 of the two waves with
+// wm = s / 4.  Trace partials go to parts_out[nfull + 8 * tail + s].
+// ---------------------------------------------------------------------------
+constexpr int kTailStrips = 8;
+
+__global__ __launch_bounds__(256) void k_split_tail(SplitArgs p) {
+  constexpr int NT = 256, H = 32, S = kEpiLd, NI = 4;
+  __shared__ float img[H * S];
+  __shared__ double red[2 * (NT / kWave)];
+  const int sign = decide_layer<NT>(p.dec, red);
+  if (sign == 0) return;
+  float alpha = p.epi.alpha, beta = p.epi.beta;
+  if (p.dec.mode != 0) {
+    alpha = sign > 0 ? 1.0f : -1.0f;
+    beta = sign > 0 ? 0.0f : 2.0f;
+  }
+  const Decomp& dc = p.dc;
+  const int tail = blockIdx.x / kTailStrips, s = blockIdx.x % kTailStrips;
+  const int tile = dc.nfull + tail;
+  int ti, tj;
+  tile_of(tile, dc.nb, dc.band, ti, tj);
+  const int wm = s / 4, mi = s % 4, t = threadIdx.x;
+  // item j = t + 256 k (k = 0..7): wave wn = j / 1024, block (ni, r4) =
+  // (j % 1024) / 64, lane j % 64 -- consecutive threads read consecutive
+  // 16-byte pieces of a piece's accumulator.
+  f32x4 sum[8];
+#pragma clang loop unroll(full)
+  for (int k = 0; k < 8; ++k) sum[k] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int q = 0; q < dc.nsplit; ++q) {
+    const float* src = dc.partial + (int64_t(tail) * dc.nsplit + q) * (NT * 4 * NI * 16);
+    f32x4 x[8];
+#pragma clang loop unroll(full)
+    for (int k = 0; k < 8; ++k) {
+      const int j = t + 256 * k, wn = j >> 10, blk = (j & 1023) >> 6, ln = j & 63;
+      const int v = mi * NI * 4 + blk;
+      const int tid = (2 * wm + wn) * kWave + ln;
+      x[k] = *reinterpret_cast<const f32x4*>(src + (int64_t(v) * NT + tid) * 4);
+    }
+#pragma clang loop unroll(full)
+    for (int k = 0; k < 8; ++k) sum[k] += x[k];
+  }
+#pragma clang loop unroll(full)
+  for (int k = 0; k < 8; ++k) {
+    const int j = t + 256 * k, wn = j >> 10, blk = (j & 1023) >> 6, ln = j & 63;
+    const int ni = blk >> 2, r4 = blk & 3;
+    const int col = wn * 128 + ni * 32 + (ln & 31);
+#pragma clang loop unroll(full)
+    for (int e = 0; e < 4; ++e) img[(8 * r4 + 4 * (ln >> 5) + e) * S + col] = sum[k][e];
+  }
+  __syncthreads();
+  double t1 = 0.0, t2 = 0.0;
+  epilogue_passes<H>(p.epi, alpha * p.epi.oscale, beta, ti, tj, 32 * s, img, t1, t2);
+  if (p.epi.parts_out) {
+    block_sum2<NT>(t1, t2, red);
+    if (threadIdx.x == 0) {
+      const int idx = dc.nfull + kTailStrips * tail + s;
+      p.epi.parts_out[2 * idx] = t1;
+      p.epi.parts_out[2 * idx + 1] = t2;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
