@@ -627,30 +627,27 @@ void k_sym_split(SplitArgs p) {
     SP2_MFMA1(AH, BL)                                                                     \
     SP2_MFMA1(AL, BH)                                                                     \
   }
-#define SP2_INTERLEAVE()                                                                  \
-  if constexpr (kLo) {                                                                    \
-    _Pragma("clang loop unroll(full)") for (int g = 0; g < 16; ++g) {                    \
-      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);                                  \
-      __builtin_amdgcn_sched_group_barrier(0x008, 3, 0);                                  \
-    }                                                                                     \
-  } else {                                                                                \
-    _Pragma("clang loop unroll(full)") for (int g = 0; g < 8; ++g) {                     \
-      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);                                  \
-      __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);                                  \
-    }                                                                                     \
-  }
   // One K step: K step K is in registers (CUR); publish K + 1, refill the
   // slot K came from with K + 4, compute K while reading K + 1 into NXT.
-  // After the last step the NXT reads fetch a stale slot that is never used.
+  // The first product's MFMAs go ahead of the DMA issue so that the matrix
+  // pipes restart right after the barrier.  After the last step the NXT
+  // reads fetch a stale slot that is never used.
 #define SP2_STEP(K, CAH, CAL, CBH, CBL, NAH, NAL, NBH, NBL)                               \
   {                                                                                       \
     const int k_ = (K);                                                                   \
     wait_ring<kCopies>(min(k_ + 3, ke - 1) - (k_ + 1));                                   \
     __syncthreads();                                                                      \
+    SP2_MFMA1(CAH, CBH);                                                                  \
     if (k_ + 4 < ke) SP2_DMA_STAGE((k_ - kb) & (NS - 1), k_ + 4);                         \
     SP2_FRAG(NAH, NAL, NBH, NBL, (k_ + 1 - kb) & (NS - 1));                               \
-    SP2_MFMA(CAH, CAL, CBH, CBL);                                                         \
-    SP2_INTERLEAVE();                                                                     \
+    if constexpr (kLo) {                                                                  \
+      SP2_MFMA1(CAH, CBL);                                                                \
+      SP2_MFMA1(CAL, CBH);                                                                \
+      _Pragma("clang loop unroll(full)") for (int g = 0; g < 16; ++g) {                  \
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);                                \
+        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);                                \
+      }                                                                                   \
+    }                                                                                     \
   }
 
   // K ranges are whole pairs of K steps (work_of splits in units of 32).
@@ -670,7 +667,6 @@ void k_sym_split(SplitArgs p) {
 #undef SP2_FRAG
 #undef SP2_MFMA1
 #undef SP2_MFMA
-#undef SP2_INTERLEAVE
 #undef SP2_STEP
   if (tail >= 0) {   // summed and finished by k_split_tail
     store_piece<NT, MI, NI>(acc, p.dc, tail, piece);
