@@ -211,6 +211,35 @@ __global__ __launch_bounds__(kEwThreads) void k_copy_scaled(const float* __restr
   }
 }
 
+// Y = X with the strict lower triangle taken from the upper one
+// (Y_ij = X_ji for i > j), np x np with leading dimension np; Y may be X
+// (then only the lower triangle is written).  64 x 64 blocks, transposed
+// through LDS so that both the reads and the writes are row-contiguous.
+constexpr int kMirrorTile = 64;
+__global__ __launch_bounds__(256) void k_mirror_upper(const float* X,
+                                                      float* Y, int64_t np) {
+  __shared__ float t[kMirrorTile][kMirrorTile + 1];
+  const int nb = static_cast<int>(np / kMirrorTile);
+  const int bi = blockIdx.x / nb, bj = blockIdx.x % nb;   // output block (bi, bj)
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 columns x 4 rows per pass
+  const int64_t r0 = int64_t(bi) * kMirrorTile, c0 = int64_t(bj) * kMirrorTile;
+  if (bi < bj) {   // upper block: plain copy
+    if (X != Y)
+      for (int r = ty; r < kMirrorTile; r += 4) Y[(r0 + r) * np + c0 + tx] = X[(r0 + r) * np + c0 + tx];
+    return;
+  }
+  // source block (bj, bi) of the upper triangle, transposed
+  for (int r = ty; r < kMirrorTile; r += 4) t[r][tx] = X[(c0 + r) * np + r0 + tx];
+  __syncthreads();
+  for (int r = ty; r < kMirrorTile; r += 4) {
+    const int64_t i = r0 + r, j = c0 + tx;
+    if (i > j)
+      Y[i * np + j] = t[tx][r];
+    else if (X != Y)
+      Y[i * np + j] = X[i * np + j];
+  }
+}
+
 // P = 0 (value 0) or P = I (value 1), n x n with leading dimension ld.
 __global__ __launch_bounds__(kEwThreads) void k_fill_diag(float* __restrict__ P, int64_t n,
                                                           int64_t ld, float value) {

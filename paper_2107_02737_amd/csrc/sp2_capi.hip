@@ -303,6 +303,7 @@ Epi make_epi(const Layout& L) {
   e.alpha = 1.0f;
   e.beta = 0.0f;
   e.oscale = 1.0f;
+  e.mirror_out = 1;
   return e;
 }
 
@@ -429,7 +430,7 @@ float* s_f32(const WS& w, int precision, int n) {
 // the recorded branch.  src/dst FP32 buffers may alias (split modes only).
 sp2_status launch_layer(const WS& w, int precision, int n, int mode, const float* src, float* dst,
                         int pair_in, int pair_out, double* parts_out, hipStream_t st,
-                        const sp2_options* o, int64_t n_occ) {
+                        const sp2_options* o, int64_t n_occ, bool full_out = true) {
   Decide d = make_decide(w, mode, n);
   if (mode == 1) {
     d.parts_in = w.parts[n & 1];
@@ -450,8 +451,18 @@ sp2_status launch_layer(const WS& w, int precision, int n, int mode, const float
   e.split_out = split_code_of(precision);
   e.hi_out = w.hi(pair_out);
   e.lo_out = w.lo(pair_out);
+  // The next split layer reads only the planes and the upper triangle of C.
+  e.mirror_out = full_out ? 1 : 0;
   return launch_split(w, precision, w.hi(pair_in), w.lo(pair_in), w.hi(pair_in), w.lo(pair_in), e,
                       d, st);
+}
+
+// Complete an FP32 iterate that split layers left upper-triangle-only.
+sp2_status mirror_upper(const WS& w, const float* X, float* Y, hipStream_t st) {
+  const int nb = static_cast<int>(w.L.np / kMirrorTile);
+  k_mirror_upper<<<nb * nb, 256, 0, st>>>(X, Y, w.L.np);
+  LAUNCH_TRY();
+  return SP2_OK;
 }
 
 sp2_status check_ws(const Layout& L, void* ws, size_t ws_bytes) {
@@ -662,13 +673,17 @@ sp2_status sp2_density_ex(const float* H, int64_t n, int64_t ld, int64_t n_occ,
       if (timer.mark(2 * k, st) != hipSuccess) err = fail(SP2_ERR_DEVICE, "event record failed");
       if (err == SP2_OK)
         err = launch_layer(w, prec, k, 1, src, dst, k & 1, (k + 1) & 1, w.parts[(k + 1) & 1], st, &o,
-                           n_occ);
+                           n_occ, prec == SP2_FP32);
       if (err == SP2_OK && timer.mark(2 * k + 1, st) != hipSuccess)
         err = fail(SP2_ERR_DEVICE, "event record failed");
       if (err == SP2_OK && o.checkpoint_every > 0 && (k + 1) % o.checkpoint_every == 0) {
-        hipError_t e = hipMemcpyAsync(w.tape((k + 1) / o.checkpoint_every), dst, L.slot_bytes,
-                                      hipMemcpyDeviceToDevice, st);
-        if (e != hipSuccess) err = fail(SP2_ERR_DEVICE, "tape copy: %s", hipGetErrorString(e));
+        if (prec == SP2_FP32) {
+          hipError_t e = hipMemcpyAsync(w.tape((k + 1) / o.checkpoint_every), dst, L.slot_bytes,
+                                        hipMemcpyDeviceToDevice, st);
+          if (e != hipSuccess) err = fail(SP2_ERR_DEVICE, "tape copy: %s", hipGetErrorString(e));
+        } else {
+          err = mirror_upper(w, dst, w.tape((k + 1) / o.checkpoint_every), st);
+        }
       }
     }
     launched = end;
@@ -705,6 +720,9 @@ sp2_status sp2_density_ex(const float* H, int64_t n, int64_t ld, int64_t n_occ,
     n_iter = hm->ctrl[0].n_iter;
   }
   const float* S = s_f32(w, prec, n_iter);
+  // split layers wrote the FP32 iterate's upper triangle only
+  if (prec != SP2_FP32 && n_iter > 0)
+    if ((s = mirror_upper(w, S, const_cast<float*>(S), st))) return s;
   if (o.refine == SP2_REFINE_SPLIT && prec == SP2_FP32 && (n_iter & 1)) {
     // S sits in slot 1, which the split refinement uses for hi/lo planes.
     HIP_TRY(hipMemcpyAsync(w.slotf(0), S, L.slot_bytes, hipMemcpyDeviceToDevice, st));

@@ -40,6 +40,7 @@ struct Epi {
   float alpha, beta;     // used when the launch has no branch
   float oscale;          // scale of the raw accumulator (2^-28 for scaled fp16)
   int np;
+  int mirror_out;        // 1: FP32 result in both triangles; 0: upper triangle only
 };
 
 // Work decomposition of one launch.  Work-groups [0, nfull) each compute a
@@ -388,7 +389,7 @@ __device__ __forceinline__ void epilogue_passes(const Epi& p, float as, float be
   }
   // Pass C, mirrored FP32: output row C0 + cl, columns R0 + hr + r; thread =
   // image row (consecutive output columns per store), 8 columns per step.
-  if (p.out) {
+  if (p.out && p.mirror_out) {
     const int r = t % H, rl = hr + r;
     const int64_t col = R0 + rl;
     const int cb = (t / H) * H;
