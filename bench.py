@@ -324,6 +324,15 @@ def main():
             "n_iter": linfo[-1]["n_iter"], "eps": [linfo[-1]["eps_min"], linfo[-1]["eps_max"]],
             "fro_over_sqrt_n_est": lerr["fro_over_sqrt_n_est"]}
         del Pl
+    if args.refine == "fp32":
+        # the same solve with the FP32-equivalent split refinement (FP16x3 products)
+        Ps, sinfo, ssec = timed_solves(pk, H, n_occ, args.precision, "split", 5, 1, True,
+                                       args.bound_steps)
+        serr = sampled_error(Ps, gold)
+        out["with_split_refine"] = {"solves_per_s": 1.0 / ssec,
+                                    "refine_ms": float(np.mean([d["refine_ms"] for d in sinfo])),
+                                    "fro_over_sqrt_n_est": serr["fro_over_sqrt_n_est"]}
+        del Ps
     if not args.no_fp32_compare and args.precision != "fp32":
         _, finfo, fsec = timed_solves(pk, H, n_occ, "fp32", args.refine, 3, 1, True)
         f_layer_ms = float(np.mean([d["layer_ms"] / max(1, d["n_iter"]) for d in finfo]))
