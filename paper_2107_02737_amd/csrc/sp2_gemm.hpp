@@ -488,9 +488,12 @@ __device__ __forceinline__ void store_piece(const f32x16 (&acc)[MI][NI], const D
 // global_load_lds DMA straight from the K-tiled planes, four K steps ahead:
 // while one slot is consumed, up to three (96 KB) are in flight, and each
 // wave waits only for the oldest of its outstanding copies.  Fragments are
-// double buffered in registers: one barrier per K step, between the MFMA
-// clusters, and the LDS reads of the next K step are interleaved 1:3 (1:2
-// for one product) with the MFMAs of the current one.
+// double buffered in registers: one barrier per K step.  A wave issues its
+// copies for K step k + 4 between the MFMAs of the first product of step k
+// (one copy after every second MFMA), and the LDS reads of step k + 1
+// between those of the other two products (one read per two MFMAs), so its
+// instruction stream keeps the matrix pipe fed (with one wave per SIMD,
+// a copy or read issued alone would leave the pipe idle).
 // ---------------------------------------------------------------------------
 
 // One 16-byte chunk per lane from global memory into LDS at m0 + 16 * lane.
@@ -620,42 +623,67 @@ void k_sym_split(SplitArgs p) {
       acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(                              \
           __builtin_bit_cast(bf16x8, X[mi]), __builtin_bit_cast(bf16x8, Y[ni]), acc[mi][ni], 0, 0, 0); \
   }
-  // hi*hi first for every block, then hi*lo, then lo*hi: an accumulator is
-  // revisited only every 16 MFMAs.
-#define SP2_MFMA(AH, AL, BH, BL)                                                          \
-  SP2_MFMA1(AH, BH)                                                                       \
+  // Per K step, hi*hi first for every block, then hi*lo, then lo*hi: an
+  // accumulator is revisited only every 16 MFMAs.
+  // First product of a K step with the refill of slot SLOT (K step KTI)
+  // woven in: one copy after every second MFMA (every fourth for one plane
+  // pair), so that the address arithmetic and copy issue of one wave run
+  // while its matrix pipe is busy.  sched_barrier keeps the order as written.
+#define SP2_MFMA1_DMA(X, Y, SLOT, KTI)                                                    \
+  {                                                                                       \
+    const int64_t kofs_ = int64_t(KTI) * 4096;                                            \
+    const uint32_t m0s_ = lds0 + (SLOT) * SLOT_B + w * 1024;                              \
+    _Pragma("clang loop unroll(full)") for (int mi = 0; mi < MI; ++mi)                    \
+    _Pragma("clang loop unroll(full)") for (int ni = 0; ni < NI; ++ni) {                  \
+      if constexpr (KIND == kFP16X3)                                                      \
+        acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_f16(                             \
+            __builtin_bit_cast(f16x8, X[mi]), __builtin_bit_cast(f16x8, Y[ni]), acc[mi][ni], 0, 0, 0); \
+      else                                                                                \
+        acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(                            \
+            __builtin_bit_cast(bf16x8, X[mi]), __builtin_bit_cast(bf16x8, Y[ni]), acc[mi][ni], 0, 0, 0); \
+      constexpr int kEvery_ = 16 / kCopies;                                               \
+      const int j_ = mi * NI + ni;                                                        \
+      if (j_ % kEvery_ == kEvery_ - 1) {                                                  \
+        const int c_ = j_ / kEvery_, i_ = c_ & 1, pl_ = c_ >> 1;                          \
+        const uint32_t off_ = static_cast<uint32_t>(((i_ * 4 + w) * 64 + lane) * 16);     \
+        const uint16_t* g_ = pl_ == 0 ? ga_hi : pl_ == 1 ? gb_hi : pl_ == 2 ? ga_lo : gb_lo; \
+        const int lp_ = pl_ == 0 ? 0 : pl_ == 1 ? 2 : pl_ == 2 ? 1 : 3;                   \
+        dma_chunk(off_, g_ + kofs_, m0s_ + lp_ * PLANE_B + i_ * 4096);                    \
+      }                                                                                   \
+      __builtin_amdgcn_sched_barrier(0);                                                  \
+    }                                                                                     \
+  }
+  // Second and third products of a K step, with the LDS reads of the next
+  // K step interleaved 1:2.
+#define SP2_MFMA23(CAH, CAL, CBH, CBL)                                                    \
   if constexpr (kLo) {                                                                    \
-    SP2_MFMA1(AH, BL)                                                                     \
-    SP2_MFMA1(AL, BH)                                                                     \
+    SP2_MFMA1(CAH, CBL);                                                                  \
+    SP2_MFMA1(CAL, CBH);                                                                  \
+    _Pragma("clang loop unroll(full)") for (int g = 0; g < 16; ++g) {                    \
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);                                  \
+      __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);                                  \
+    }                                                                                     \
   }
   // One K step: K step K is in registers (CUR); publish K + 1, refill the
   // slot K came from with K + 4, compute K while reading K + 1 into NXT.
-  // The first product's MFMAs go ahead of the DMA issue so that the matrix
-  // pipes restart right after the barrier.  After the last step the NXT
-  // reads fetch a stale slot that is never used.
+  // Copies are issued in every step, so the wait is the same in every step:
+  // in the last four steps of a range they re-copy step ke - 1 into slots
+  // that are never read again (and the NXT reads after the last step fetch
+  // such a slot); the ring drains before the epilogue reuses the LDS.
 #define SP2_STEP(K, CAH, CAL, CBH, CBL, NAH, NAL, NBH, NBL)                               \
   {                                                                                       \
     const int k_ = (K);                                                                   \
-    wait_ring<kCopies>(min(k_ + 3, ke - 1) - (k_ + 1));                                   \
+    wait_ring<kCopies>(2);                                                                \
     __syncthreads();                                                                      \
-    SP2_MFMA1(CAH, CBH);                                                                  \
-    if (k_ + 4 < ke) SP2_DMA_STAGE((k_ - kb) & (NS - 1), k_ + 4);                         \
+    SP2_MFMA1_DMA(CAH, CBH, (k_ - kb) & (NS - 1), min(k_ + 4, ke - 1));                   \
     SP2_FRAG(NAH, NAL, NBH, NBL, (k_ + 1 - kb) & (NS - 1));                               \
-    if constexpr (kLo) {                                                                  \
-      SP2_MFMA1(CAH, CBL);                                                                \
-      SP2_MFMA1(CAL, CBH);                                                                \
-      _Pragma("clang loop unroll(full)") for (int g = 0; g < 16; ++g) {                  \
-        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);                                \
-        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);                                \
-      }                                                                                   \
-    }                                                                                     \
+    SP2_MFMA23(CAH, CAL, CBH, CBL);                                                       \
   }
 
   // K ranges are whole pairs of K steps (work_of splits in units of 32).
 #pragma clang loop unroll(full)
-  for (int s = 0; s < NS; ++s)
-    if (kb + s < ke) SP2_DMA_STAGE(s, kb + s);
-  wait_ring<kCopies>(min(kb + 3, ke - 1) - kb);
+  for (int s = 0; s < NS; ++s) SP2_DMA_STAGE(s, min(kb + s, ke - 1));
+  wait_ring<kCopies>(3);
   __syncthreads();
   SP2_FRAG(Ah0, Al0, Bh0, Bl0, 0);
   for (int kt = kb; kt < ke; kt += 2) {
@@ -667,7 +695,8 @@ void k_sym_split(SplitArgs p) {
 #undef SP2_DMA_STAGE
 #undef SP2_FRAG
 #undef SP2_MFMA1
-#undef SP2_MFMA
+#undef SP2_MFMA1_DMA
+#undef SP2_MFMA23
 #undef SP2_STEP
   if (tail >= 0) {   // summed and finished by k_split_tail
     store_piece<NT, MI, NI>(acc, p.dc, tail, piece);
