@@ -53,9 +53,8 @@ constexpr int64_t kPad = 256;          // matrices are padded to a multiple of t
 constexpr int kBand = 4;               // tile-rows per band of the tile schedule
 constexpr int kChunk = 8;              // layers launched between stop-flag polls
 constexpr int kInitBlocksMax = 1024;   // partial pairs written by the input layer
-constexpr int kF32Tile = 128;
 constexpr size_t kPartialBytes = size_t(64) << 20;   // split-K tail accumulators
-constexpr int kMaxTailTiles = 1024;                   // arrival counters
+constexpr int kMaxTailTiles = 1024;                   // split-K tail tiles per launch
 
 int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
@@ -72,9 +71,9 @@ constexpr int64_t kMetaMagic = 0x5350324d45544131LL;
 // Workspace layout (byte offsets), derived from n and the options only.
 struct Layout {
   int64_t n, np;
-  int nb_split, ntiles_split, nb_f32, ntiles_f32;
+  int nb_split, ntiles_split;
   int init_blocks, gersh_blocks, max_parts;
-  size_t off_ctrl, off_hist, off_meta, off_parts0, off_parts1, off_gersh, off_counter, off_partial;
+  size_t off_ctrl, off_hist, off_meta, off_parts0, off_parts1, off_gersh, off_partial;
   size_t off_lz, off_lzvec, off_lzpart;   // Lanczos state, vectors, chunk partials
   int lz_blocks, lz_chunks;
   size_t off_slot0;     // first matrix slot
@@ -91,14 +90,12 @@ bool make_layout(int64_t n, const sp2_options& o, Layout& L) {
   L.np = round_up(n, kPad);
   L.nb_split = static_cast<int>(L.np / 256);
   L.ntiles_split = ntiles_of(L.nb_split);
-  L.nb_f32 = static_cast<int>(L.np / kF32Tile);
-  L.ntiles_f32 = ntiles_of(L.nb_f32);
   const int64_t quads = L.np * L.np / 4;
   L.init_blocks = static_cast<int>(std::min<int64_t>(kInitBlocksMax, (quads + kEwThreads - 1) / kEwThreads));
   L.gersh_blocks = static_cast<int>((n + kRowsPerBlock - 1) / kRowsPerBlock);
-  // split layers: whole tiles + 8 strips per split-K tail tile
+  // product layers: whole tiles + 8 strips per split-K tail tile
   L.max_parts = std::max({L.ntiles_split + kTailStrips * std::min(L.ntiles_split, kMaxTailTiles),
-                          L.ntiles_f32, L.init_blocks, kInitBlocksMax});
+                          L.init_blocks, kInitBlocksMax});
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o2 = off;
@@ -111,7 +108,6 @@ bool make_layout(int64_t n, const sp2_options& o, Layout& L) {
   L.off_parts0 = take(size_t(L.max_parts) * 16);
   L.off_parts1 = take(size_t(L.max_parts) * 16);
   L.off_gersh = take(size_t(L.gersh_blocks) * 24);
-  L.off_counter = take(size_t(kMaxTailTiles) * 4);
   L.off_partial = take(kPartialBytes);
   L.lz_blocks = static_cast<int>((n + kLzRowsPerBlock - 1) / kLzRowsPerBlock);
   L.lz_chunks = static_cast<int>((n + kLzChunk - 1) / kLzChunk);
@@ -141,7 +137,6 @@ struct WS {
   Meta* meta;
   double* parts[2];
   double* gersh;
-  int* counter;
   float* partial;
   LzState* lz;
   double* lzv;      // Lanczos vectors v_0 .. v_kmax, then two w buffers: n doubles each
@@ -164,7 +159,6 @@ void bind(WS& w, void* ws, const Layout& L) {
   w.parts[0] = reinterpret_cast<double*>(w.base + L.off_parts0);
   w.parts[1] = reinterpret_cast<double*>(w.base + L.off_parts1);
   w.gersh = reinterpret_cast<double*>(w.base + L.off_gersh);
-  w.counter = reinterpret_cast<int*>(w.base + L.off_counter);
   w.partial = reinterpret_cast<float*>(w.base + L.off_partial);
   w.lz = reinterpret_cast<LzState*>(w.base + L.off_lz);
   w.lzv = reinterpret_cast<double*>(w.base + L.off_lzvec);
@@ -227,7 +221,6 @@ Decomp plan_decomp(const WS& w, int nb, int slots, int ksteps, size_t piece_byte
   d.nfull = d.ntiles;
   d.nsplit = 1;
   d.partial = w.partial;
-  d.counter = w.counter;
   if (const char* e = getenv("SP2_NO_SPLITK"))
     if (atoi(e)) return d;
   const int r = slots > 0 ? d.ntiles % slots : 0;
@@ -238,11 +231,6 @@ Decomp plan_decomp(const WS& w, int nb, int slots, int ksteps, size_t piece_byte
   d.nfull = d.ntiles - r;
   d.nsplit = s;
   return d;
-}
-
-__global__ void k_zero_i32(int* p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0;
 }
 
 bool options_ok(const sp2_options& o) {
@@ -333,12 +321,6 @@ int wgs_per_cu(K kernel, int threads) {
   return n;
 }
 
-sp2_status reset_counters(const WS& w, hipStream_t st) {
-  k_zero_i32<<<(kMaxTailTiles + 255) / 256, 256, 0, st>>>(w.counter, kMaxTailTiles);
-  LAUNCH_TRY();
-  return SP2_OK;
-}
-
 // Work decomposition of a split launch (the same on every call for a
 // given layout and device).
 template <int KIND>
@@ -394,7 +376,16 @@ sp2_status launch_split(const WS& w, int precision, const uint16_t* ah, const ui
   return launch_split_t<kFP16X3>(w, a, st);
 }
 
-// Launch an FP32 product sum_s A_s B_s^T (nseg <= 4).
+// Work decomposition of an FP32 product over nseg K segments.
+Decomp f32_decomp(const WS& w, int nseg) {
+  constexpr size_t piece = size_t(256) * 4 * 4 * 16 * 4;   // one 256x256 FP32 accumulator
+  const int slots = device_cus() * wgs_per_cu(k_sym_f32, 256);
+  return plan_decomp(w, static_cast<int>(w.L.np / 256), slots,
+                     static_cast<int>(w.L.np / 32) * nseg, piece);
+}
+
+// Launch an FP32 product sum_s A_s B_s^T (nseg <= 4; row-major operands,
+// leading dimension np), then the strip kernel for its split-K tail tiles.
 sp2_status launch_f32(const WS& w, int nseg, const float* const* A, const float* const* B,
                       const Epi& epi, const Decide& dec, hipStream_t st) {
   F32Args a;
@@ -406,19 +397,26 @@ sp2_status launch_f32(const WS& w, int nseg, const float* const* A, const float*
   a.nseg = nseg;
   a.epi = epi;
   a.dec = dec;
-  auto kern = k_sym_f32<kF32Tile, 2, 2>;
-  constexpr size_t piece = size_t(256) * 2 * 2 * 16 * 4;
-  const int slots = device_cus() * wgs_per_cu(kern, 256);
-  a.dc = plan_decomp(w, w.L.nb_f32, slots, static_cast<int>(w.L.np / 16) * nseg, piece);
-  const int grid = a.dc.nfull + (a.dc.ntiles - a.dc.nfull) * a.dc.nsplit;
-  kern<<<grid, 256, 0, st>>>(a);
+  a.dc = f32_decomp(w, nseg);
+  const int ntail = a.dc.ntiles - a.dc.nfull;
+  k_sym_f32<<<a.dc.nfull + ntail * a.dc.nsplit, 256, 0, st>>>(a);
   LAUNCH_TRY();
+  if (ntail > 0) {
+    SplitArgs t;
+    memset(&t, 0, sizeof(t));
+    t.epi = a.epi;
+    t.dc = a.dc;
+    t.dec = a.dec;
+    t.dec.quiet = 1;   // the product launch already recorded this layer's decision
+    k_split_tail<<<ntail * kTailStrips, 256, 0, st>>>(t);
+    LAUNCH_TRY();
+  }
   return SP2_OK;
 }
 
 int nparts_of_layer(const WS& w, int precision, int layer) {
   if (layer == 0) return w.L.init_blocks;
-  return precision == SP2_FP32 ? w.L.ntiles_f32 : split_nparts(split_decomp_of(w, precision));
+  return split_nparts(precision == SP2_FP32 ? f32_decomp(w, 1) : split_decomp_of(w, precision));
 }
 
 // Where S_n lives in the forward network (FP32 value and hi/lo planes).
@@ -607,7 +605,6 @@ sp2_status sp2_density_ex(const float* H, int64_t n, int64_t ld, int64_t n_occ,
   hipStream_t st = static_cast<hipStream_t>(stream);
   WS w;
   bind(w, workspace, L);
-  if (sp2_status s0 = reset_counters(w, st)) return s0;
   const int prec = o.precision;
   const bool trivial = n_occ == 0 || n_occ == n;
   const bool vec_ok = (ld % 4 == 0) && (reinterpret_cast<uintptr_t>(P) % 16 == 0);
@@ -736,9 +733,9 @@ sp2_status sp2_density_ex(const float* H, int64_t n, int64_t ld, int64_t n_occ,
       return s;
     HIP_TRY(timer.mark(2 * refine_ev + 1, st));
     k_sum_parts<<<1, 256, 0, st>>>(w.ctrl, w.parts[0],
-                                   o.refine == SP2_REFINE_FP32
-                                       ? L.ntiles_f32
-                                       : split_nparts(split_decomp_of(w, SP2_FP16X3)));
+                                   split_nparts(o.refine == SP2_REFINE_FP32
+                                                    ? f32_decomp(w, 1)
+                                                    : split_decomp_of(w, SP2_FP16X3)));
     LAUNCH_TRY();
   } else {
     k_copy_scaled<<<ew_grid(n * n), kEwThreads, 0, st>>>(S, L.np, P, ld, n, n, 1.0f, 0);
@@ -881,7 +878,6 @@ sp2_status sp2_layer(const float* X, int64_t n, int64_t ld, int32_t precision, i
   hipStream_t st = static_cast<hipStream_t>(stream);
   WS w;
   bind(w, workspace, L);
-  if (sp2_status s0 = reset_counters(w, st)) return s0;
   float* Xp = w.slotf(0);
   k_copy_scaled<<<ew_grid(L.np * L.np), kEwThreads, 0, st>>>(X, ld, Xp, L.np, n, L.np, 1.0f, 0);
   LAUNCH_TRY();
@@ -940,7 +936,6 @@ sp2_status open_tape(void* workspace, size_t ws_bytes, hipStream_t st, WS& w, Ho
   if (!make_layout(m.n, o, L)) return fail(SP2_ERR_TAPE, "corrupt tape description");
   if (sp2_status s = check_ws(L, workspace, ws_bytes)) return s;
   bind(w, workspace, L);
-  if (sp2_status s0 = reset_counters(w, st)) return s0;
   return read_back(w, hm, true, st);
 }
 

@@ -23,10 +23,6 @@ namespace sp2 {
 
 enum SplitKind { kBF16X3 = 0, kBF16X1 = 1, kFP16X3 = 2 };
 
-// LDS swizzle of the 16-byte chunk index within a 64-byte row: any 8 or 16
-// consecutive rows read at one logical chunk land in distinct banks.
-__device__ inline int swz(int row) { return ((row >> 1) & 3) ^ ((row >> 3) & 1); }
-
 struct Epi {
   const float* c;        // addend C (ld = np); read only where needed
   float* out;            // result, leading dimension ld_out
@@ -43,19 +39,18 @@ struct Epi {
   int mirror_out;        // 1: FP32 result in both triangles; 0: upper triangle only
 };
 
-// Work decomposition of one launch.  Work-groups [0, nfull) each compute a
-// whole tile (logical tiles 0 .. nfull-1).  The remaining tiles ("tail",
-// the last partial round of the machine) are split along K into nsplit
-// pieces, one per work-group; every piece stores its FP32 partial
-// accumulator, and the last piece to arrive at the tile's counter sums all
-// pieces in a fixed order and runs the epilogue.  No work-group ever waits
-// for another.
+// Work decomposition of one product launch.  Work-groups [0, nfull) each
+// compute a whole tile (logical tiles 0 .. nfull-1).  The remaining tiles
+// ("tail", the last partial round of the machine) are split along K into
+// nsplit pieces, one per work-group; every piece stores its FP32 partial
+// accumulator, and k_split_tail, launched next on the same stream, sums
+// the pieces in a fixed order and runs the epilogue.  No work-group ever
+// waits for another.
 struct Decomp {
   int nb, ntiles, band;
   int nfull;        // whole-tile work-groups
   int nsplit;       // K pieces per tail tile (1: no tail)
   float* partial;   // (ntiles - nfull) * nsplit accumulators of NT * MI*NI*16 floats
-  int* counter;     // one arrival counter per tail tile, zero between launches
 };
 
 struct SplitArgs {
@@ -98,173 +93,12 @@ __device__ __forceinline__ void work_of(const Decomp& dc, int ksteps, int& tile,
   tile_of(tile, dc.nb, dc.band, ti, tj);
 }
 
-// Tail handling after the K loop: store this piece's accumulator; the last
-// piece to arrive reloads all pieces of the tile in piece order, sums them
-// into acc and returns true (it then runs the epilogue).
-template <int NT, int MI, int NI>
-__device__ __forceinline__ bool reduce_tail(f32x16 (&acc)[MI][NI], const Decomp& dc, int tail,
-                                            int piece) {
-  constexpr int ACC = MI * NI * 16;
-  __shared__ int s_last;
-  const int tid = threadIdx.x;
-  float* mine = dc.partial + (int64_t(tail) * dc.nsplit + piece) * (NT * ACC);
-#pragma clang loop unroll(full)
-  for (int mi = 0; mi < MI; ++mi)
-#pragma clang loop unroll(full)
-    for (int ni = 0; ni < NI; ++ni)
-#pragma clang loop unroll(full)
-      for (int r4 = 0; r4 < 4; ++r4) {
-        const int v = (mi * NI + ni) * 4 + r4;
-        *reinterpret_cast<f32x4*>(mine + (int64_t(v) * NT + tid) * 4) =
-            f32x4{acc[mi][ni][4 * r4], acc[mi][ni][4 * r4 + 1], acc[mi][ni][4 * r4 + 2],
-                  acc[mi][ni][4 * r4 + 3]};
-      }
-  __threadfence();   // release the piece device-wide before counting it
-  __syncthreads();
-  if (tid == 0) s_last = atomicAdd(dc.counter + tail, 1) == dc.nsplit - 1;
-  __syncthreads();
-  if (!s_last) return false;
-  __threadfence();   // acquire the other pieces
-#pragma clang loop unroll(full)
-  for (int mi = 0; mi < MI; ++mi)
-#pragma clang loop unroll(full)
-    for (int ni = 0; ni < NI; ++ni)
-#pragma clang loop unroll(full)
-      for (int r = 0; r < 16; ++r) acc[mi][ni][r] = 0.0f;
-  for (int q = 0; q < dc.nsplit; ++q) {
-    const float* src = dc.partial + (int64_t(tail) * dc.nsplit + q) * (NT * ACC);
-    // four 32x32 blocks (16 loads of 16 bytes) in flight per group: the
-    // reload is latency-bound with the fragment registers free
-#pragma clang loop unroll(full)
-    for (int mi = 0; mi < MI; ++mi) {
-      f32x4 x[NI][4];
-#pragma clang loop unroll(full)
-      for (int ni = 0; ni < NI; ++ni)
-#pragma clang loop unroll(full)
-        for (int r4 = 0; r4 < 4; ++r4) {
-          const int v = (mi * NI + ni) * 4 + r4;
-          x[ni][r4] = *reinterpret_cast<const f32x4*>(src + (int64_t(v) * NT + tid) * 4);
-        }
-      __builtin_amdgcn_sched_group_barrier(0x020, NI * 4, 0);   // all 16 loads first
-#pragma clang loop unroll(full)
-      for (int ni = 0; ni < NI; ++ni)
-#pragma clang loop unroll(full)
-        for (int r4 = 0; r4 < 4; ++r4)
-#pragma clang loop unroll(full)
-          for (int e = 0; e < 4; ++e) acc[mi][ni][4 * r4 + e] += x[ni][r4][e];
-    }
-  }
-  if (tid == 0) dc.counter[tail] = 0;   // ready for the next launch
-  return true;
-}
-
 __device__ __forceinline__ void split_value(float v, int kind, uint16_t& h, uint16_t& l) {
   if (kind == 1)
     split_bf16(v, h, l);
   else
     split_fp16s(v, h, l);
 }
-
-// Epilogue over the MI x NI 32x32 accumulator blocks of one wave.  MFMA
-// 32x32 output layout: accumulator element 4q+e of lane l holds row
-// 8q + 4(l/32) + e, column l%32 of the block.
-template <int NT, int BM, int TM, int TN, int MI, int NI>
-__device__ __forceinline__ void sym_epilogue(const f32x16 (&acc)[MI][NI], const Epi& p, float alpha,
-                                    float beta, int ti, int tj, int wm, int wn, int lane,
-                                    double* red, int tile) {
-  const int64_t np = p.np;
-  const bool diag = ti == tj;
-  double t1 = 0.0, t2 = 0.0;
-#pragma clang loop unroll(full)
-  for (int mi = 0; mi < MI; ++mi) {
-#pragma clang loop unroll(full)
-    for (int ni = 0; ni < NI; ++ni) {
-      const int cl = wn * TN + ni * 32 + (lane & 31);
-      const int64_t gj = int64_t(tj) * BM + cl;
-#pragma clang loop unroll(full)
-      for (int q = 0; q < 4; ++q) {
-        const int rl0 = wm * TM + mi * 32 + 8 * q + 4 * (lane >> 5);
-        const int64_t gi0 = int64_t(ti) * BM + rl0;
-        float v[4];
-        bool keep[4];
-#pragma clang loop unroll(full)
-        for (int e = 0; e < 4; ++e) {
-          keep[e] = !diag || (rl0 + e <= cl);
-          float x = acc[mi][ni][4 * q + e] * p.oscale;
-          if (keep[e] && beta != 0.0f) x = alpha * x + beta * p.c[(gi0 + e) * np + gj];
-          else x = alpha * x;
-          v[e] = x;
-        }
-        // traces of the result: off-diagonal entries count for (i,j) and (j,i)
-#pragma clang loop unroll(full)
-        for (int e = 0; e < 4; ++e) {
-          if (!keep[e]) continue;
-          const double d = static_cast<double>(v[e]);
-          if (diag && rl0 + e == cl) {
-            t1 += d;
-            t2 += d * d;
-          } else {
-            t2 += 2.0 * d * d;
-          }
-        }
-        // FP32 result, direct and mirrored
-        const bool full = !diag && gi0 + 3 < p.n_valid && gj < p.n_valid;
-        if (full && p.vec_ok) {
-#pragma clang loop unroll(full)
-          for (int e = 0; e < 4; ++e) p.out[(gi0 + e) * p.ld_out + gj] = v[e];
-          *reinterpret_cast<f32x4*>(p.out + gj * p.ld_out + gi0) = f32x4{v[0], v[1], v[2], v[3]};
-        } else {
-#pragma clang loop unroll(full)
-          for (int e = 0; e < 4; ++e) {
-            const int64_t gi = gi0 + e;
-            if (!keep[e] || gi >= p.n_valid || gj >= p.n_valid) continue;
-            p.out[gi * p.ld_out + gj] = v[e];
-            if (gi != gj) p.out[gj * p.ld_out + gi] = v[e];
-          }
-        }
-        // dual 16-bit representation of the result for the next layer, in
-        // the K-tiled plane layout (the mirrored 4-element run is contiguous)
-        if (p.split_out) {
-          uint16_t h[4], l[4];
-#pragma clang loop unroll(full)
-          for (int e = 0; e < 4; ++e) split_value(v[e], p.split_out, h[e], l[e]);
-          if (!diag) {
-#pragma clang loop unroll(full)
-            for (int e = 0; e < 4; ++e) {
-              const int64_t o = plane_off(gi0 + e, gj, np);
-              p.hi_out[o] = h[e];
-              p.lo_out[o] = l[e];
-            }
-            const int64_t om = plane_off(gj, gi0, np);
-            *reinterpret_cast<u32x2*>(p.hi_out + om) =
-                u32x2{uint32_t(h[0]) | (uint32_t(h[1]) << 16), uint32_t(h[2]) | (uint32_t(h[3]) << 16)};
-            *reinterpret_cast<u32x2*>(p.lo_out + om) =
-                u32x2{uint32_t(l[0]) | (uint32_t(l[1]) << 16), uint32_t(l[2]) | (uint32_t(l[3]) << 16)};
-          } else {
-#pragma clang loop unroll(full)
-            for (int e = 0; e < 4; ++e) {
-              if (!keep[e]) continue;
-              const int64_t gi = gi0 + e;
-              const int64_t o = plane_off(gi, gj, np), om = plane_off(gj, gi, np);
-              p.hi_out[o] = h[e];
-              p.lo_out[o] = l[e];
-              p.hi_out[om] = h[e];
-              p.lo_out[om] = l[e];
-            }
-          }
-        }
-      }
-    }
-  }
-  if (p.parts_out) {
-    block_sum2<NT>(t1, t2, red);
-    if (threadIdx.x == 0) {
-      p.parts_out[2 * tile] = t1;
-      p.parts_out[2 * tile + 1] = t2;
-    }
-  }
-}
-
 
 // ---------------------------------------------------------------------------
 // LDS-staged epilogue of the 256 x 256 split tile (4 waves of 128 x 128).
@@ -426,6 +260,10 @@ __device__ __forceinline__ void epilogue_passes(const Epi& p, float as, float be
   }
 }
 
+// Epilogue of a 256x256 tile through LDS.  MFMA 32x32 output layout:
+// accumulator element 4q+e of lane l holds row 8q + 4(l/32) + e, column
+// l%32 of its block.  The two waves of each 128-row half dump their
+// accumulators into the [128][257] image, then epilogue_passes finish it.
 template <int NT, int MI, int NI>
 __device__ __forceinline__ void sym_epilogue_lds(const f32x16 (&acc)[MI][NI], const Epi& p, float alpha,
                                                  float beta, int ti, int tj, int wm, int wn, int lane,
@@ -774,23 +612,26 @@ __global__ __launch_bounds__(256) void k_split_tail(SplitArgs p) {
 }
 
 // ---------------------------------------------------------------------------
-// FP32 product sum_s A_s B_s^T over up to four K segments.  32x32x2 f32
-// MFMA; each lane feeds 8 consecutive K values of its row per 16-wide K
-// tile (the same K order for A and B, so the sum is unchanged).
+// FP32 product sum_s A_s B_s^T over up to four K segments (row-major
+// operands, leading dimension np).  The same work-group shape, LDS ring,
+// copy weaving, split-K tail and epilogue as k_sym_split, with the
+// 32x32x2 f32 MFMA (eight per 32x32 block and 16-wide K step).  The
+// copies gather each 16-byte piece (four consecutive K values of one row)
+// straight from the row-major operands into a chunk-major slot: piece
+// (row, c) at byte c * 4096 + row * 16, so that a fragment read (32
+// consecutive rows of one chunk) is one contiguous 512-byte run.  Lane
+// (r, h) feeds the eight K values of chunks 2h and 2h + 1 of its row over
+// the eight MFMAs, in the same order for A and B, so the sum is unchanged.
 // ---------------------------------------------------------------------------
 
-template <int BM, int WM, int WN>
-__global__ __launch_bounds__(WM* WN* kWave) void k_sym_f32(F32Args p) {
-  constexpr int NT = WM * WN * kWave;
-  constexpr int BK = 16;
-  constexpr int TM = BM / WM, TN = BM / WN;
-  constexpr int MI = TM / 32, NI = TN / 32;
-  constexpr int ARR = BM * BK;          // floats per staged operand
-  constexpr int CPA = ARR / 4;          // 16-byte chunks per operand
-  constexpr int CPT = CPA / NT;
-  static_assert(CPA % NT == 0, "tile / thread mismatch");
-
-  __shared__ __attribute__((aligned(16))) float lds[2 * 2 * ARR];
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void k_sym_f32(F32Args p) {
+  constexpr int NT = 256, BK = 16, NS = 4, MI = 4, NI = 4, TM = 128, TN = 128;
+  constexpr int PANEL_B = 256 * BK * 4;   // one operand panel per K step (16 KB)
+  constexpr int SLOT_B = 2 * PANEL_B;     // A, B
+  constexpr int kCopies = 8;              // per wave and K step: 4 chunks of A and of B
+  static_assert(NS * SLOT_B <= 128 * kEpiLd * 4, "ring exceeds the LDS image");
+  __shared__ __attribute__((aligned(1024))) float lds[128 * kEpiLd];
   __shared__ double red[2 * (NT / kWave)];
 
   const int sign = decide_layer<NT>(p.dec, red);
@@ -800,96 +641,126 @@ __global__ __launch_bounds__(WM* WN* kWave) void k_sym_f32(F32Args p) {
     alpha = sign > 0 ? 1.0f : -1.0f;
     beta = sign > 0 ? 0.0f : 2.0f;
   }
-
   const int64_t np = p.epi.np;
   const int KT = static_cast<int>(np / BK);
-  const int IT = KT * p.nseg;
-  int tile, ti, tj, ib, ie, tail, piece;
-  work_of(p.dc, IT, tile, ti, tj, ib, ie, tail, piece);
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
-  const int wm = wid / WN, wn = wid % WN;
+  int tile, ti, tj, kb, ke, tail, piece;
+  work_of(p.dc, KT * p.nseg / 2, tile, ti, tj, kb, ke, tail, piece);
+  kb *= 2;
+  ke *= 2;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1);
+  const int w = __builtin_amdgcn_readfirstlane(tid / kWave);
+  const int wm = w >> 1, wn = w & 1;
 
-  int64_t goff[CPT];
-  int loff[CPT];
+  // Copies: this wave moves rows w * 64 + lane of both panels, chunks
+  // c = 0..3 (slot bytes c * 4096 + w * 1024 + lane * 16).
+  uint32_t voff[4];
 #pragma clang loop unroll(full)
-  for (int i = 0; i < CPT; ++i) {
-    const int q = tid + NT * i;
-    const int row = q >> 2, c = q & 3;
-    goff[i] = int64_t(row) * np + c * 4;
-    loff[i] = row * BK + ((c ^ swz(row)) * 4);
+  for (int c = 0; c < 4; ++c) voff[c] = static_cast<uint32_t>((w * 64 + lane) * np * 4 + c * 16);
+  const int64_t offa = int64_t(ti) * 256 * np, offb = int64_t(tj) * 256 * np;
+  const uint32_t lds0 = static_cast<uint32_t>(
+      reinterpret_cast<uintptr_t>((__attribute__((address_space(3))) float*)(lds)));
+  // Panel sources of K step IT_ (segment IT_ / KT).
+#define SP2_F32_SRC(IT_, GA, GB)                                                          \
+  const int it_ = (IT_);                                                                  \
+  const int sg_ = (it_ >= KT) + (it_ >= 2 * KT) + (it_ >= 3 * KT);                        \
+  const int64_t ko_ = int64_t(it_ - sg_ * KT) * BK;                                       \
+  const float* GA = (sg_ == 0 ? p.a[0] : sg_ == 1 ? p.a[1] : sg_ == 2 ? p.a[2] : p.a[3]) + offa + ko_; \
+  const float* GB = (sg_ == 0 ? p.b[0] : sg_ == 1 ? p.b[1] : sg_ == 2 ? p.b[2] : p.b[3]) + offb + ko_;
+#define SP2_F32_STAGE(SLOT, IT_)                                                          \
+  {                                                                                       \
+    SP2_F32_SRC(IT_, ga_, gb_)                                                            \
+    const uint32_t m0s_ = lds0 + (SLOT) * SLOT_B + w * 1024;                              \
+    _Pragma("clang loop unroll(full)") for (int c = 0; c < 4; ++c) {                      \
+      dma_chunk(voff[c], ga_, m0s_ + c * 4096);                                           \
+      dma_chunk(voff[c], gb_, m0s_ + PANEL_B + c * 4096);                                 \
+    }                                                                                     \
   }
-  u32x4 sa[CPT], sb[CPT];
+
+  const int r = lane & 31, h = lane >> 5;
+  const int fa = 2 * h * 4096 + (wm * TM + r) * 16;
+  const int fb = PANEL_B + 2 * h * 4096 + (wn * TN + r) * 16;
+  const char* L = reinterpret_cast<const char*>(lds);
+
   f32x16 acc[MI][NI];
 #pragma clang loop unroll(full)
   for (int mi = 0; mi < MI; ++mi)
 #pragma clang loop unroll(full)
     for (int ni = 0; ni < NI; ++ni)
 #pragma clang loop unroll(full)
-      for (int r = 0; r < 16; ++r) acc[mi][ni][r] = 0.0f;
+      for (int q = 0; q < 16; ++q) acc[mi][ni][q] = 0.0f;
+  f32x4 A0[MI][2], B0[NI][2], A1[MI][2], B1[NI][2];
 
-  const int64_t offa = int64_t(ti) * BM * np, offb = int64_t(tj) * BM * np;
-
-#define SP2_GLOAD32(IT_)                                                                \
-  {                                                                                     \
-    const int s_ = (IT_) / KT, kt_ = (IT_)-s_ * KT;                                     \
-    const float* pa_ = (s_ == 0 ? p.a[0] : s_ == 1 ? p.a[1] : s_ == 2 ? p.a[2] : p.a[3]) + offa + kt_ * BK; \
-    const float* pb_ = (s_ == 0 ? p.b[0] : s_ == 1 ? p.b[1] : s_ == 2 ? p.b[2] : p.b[3]) + offb + kt_ * BK; \
-    _Pragma("unroll") for (int i = 0; i < CPT; ++i) {                                   \
-      sa[i] = *reinterpret_cast<const u32x4*>(pa_ + goff[i]);                           \
-      sb[i] = *reinterpret_cast<const u32x4*>(pb_ + goff[i]);                           \
-    }                                                                                   \
+#define SP2_F32_FRAG(AF, BF, SLOT)                                                        \
+  {                                                                                       \
+    const char* S_ = L + (SLOT) * SLOT_B;                                                 \
+    _Pragma("clang loop unroll(full)") for (int u = 0; u < 2; ++u) {                      \
+      _Pragma("clang loop unroll(full)") for (int mi = 0; mi < MI; ++mi)                  \
+        AF[mi][u] = *reinterpret_cast<const f32x4*>(S_ + fa + u * 4096 + mi * 512);       \
+      _Pragma("clang loop unroll(full)") for (int ni = 0; ni < NI; ++ni)                  \
+        BF[ni][u] = *reinterpret_cast<const f32x4*>(S_ + fb + u * 4096 + ni * 512);       \
+    }                                                                                     \
   }
-#define SP2_LSTORE32(BUF)                                                               \
-  _Pragma("unroll") for (int i = 0; i < CPT; ++i) {                                     \
-    float* d = lds + (BUF) * 2 * ARR + loff[i];                                         \
-    *reinterpret_cast<u32x4*>(d) = sa[i];                                               \
-    *reinterpret_cast<u32x4*>(d + ARR) = sb[i];                                         \
+#define SP2_F32_MFMA(AF, BF, SB)                                                          \
+  _Pragma("clang loop unroll(full)") for (int mi = 0; mi < MI; ++mi)                      \
+  _Pragma("clang loop unroll(full)") for (int ni = 0; ni < NI; ++ni)                      \
+    acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x2f32(AF[mi][(SB) >> 2][(SB) & 3],       \
+                                                       BF[ni][(SB) >> 2][(SB) & 3], acc[mi][ni], 0, 0, 0);
+  // One K step: the first eight-k sub-step's 16 MFMAs carry the copies of
+  // K step k + 4 (one after every second MFMA, clamped to the range as in
+  // k_sym_split); the LDS reads of step k + 1 go between the other 112.
+#define SP2_F32_STEP(K, CA, CB, NA, NB)                                                   \
+  {                                                                                       \
+    const int k_ = (K);                                                                   \
+    wait_ring<kCopies>(2);                                                                \
+    __syncthreads();                                                                      \
+    {                                                                                     \
+      SP2_F32_SRC(min(k_ + 4, ke - 1), ga_, gb_)                                          \
+      const uint32_t m0s_ = lds0 + ((k_ - kb) & (NS - 1)) * SLOT_B + w * 1024;            \
+      _Pragma("clang loop unroll(full)") for (int mi = 0; mi < MI; ++mi)                  \
+      _Pragma("clang loop unroll(full)") for (int ni = 0; ni < NI; ++ni) {                \
+        acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x2f32(CA[mi][0][0], CB[ni][0][0],    \
+                                                           acc[mi][ni], 0, 0, 0);         \
+        const int j_ = mi * NI + ni;                                                      \
+        if (j_ & 1) {                                                                     \
+          const int c_ = j_ >> 2;                                                         \
+          if (j_ & 2) dma_chunk(voff[c_], gb_, m0s_ + PANEL_B + c_ * 4096);               \
+          else dma_chunk(voff[c_], ga_, m0s_ + c_ * 4096);                                \
+        }                                                                                 \
+        __builtin_amdgcn_sched_barrier(0);                                                \
+      }                                                                                   \
+    }                                                                                     \
+    SP2_F32_FRAG(NA, NB, (k_ + 1 - kb) & (NS - 1));                                       \
+    _Pragma("clang loop unroll(full)") for (int sb = 1; sb < 8; ++sb) {                   \
+      SP2_F32_MFMA(CA, CB, sb);                                                           \
+    }                                                                                     \
+    _Pragma("clang loop unroll(full)") for (int g = 0; g < 16; ++g) {                    \
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);                                  \
+      __builtin_amdgcn_sched_group_barrier(0x008, 7, 0);                                  \
+    }                                                                                     \
   }
 
-  SP2_GLOAD32(ib);
-  SP2_LSTORE32(0);
+  // K ranges are whole pairs of K steps; copies run four steps ahead.
+#pragma clang loop unroll(full)
+  for (int s = 0; s < NS; ++s) SP2_F32_STAGE(s, min(kb + s, ke - 1));
+  wait_ring<kCopies>(3);
   __syncthreads();
-  for (int it = ib; it < ie; ++it) {
-    const int buf = (it - ib) & 1;
-    if (it + 1 < ie) {
-      SP2_GLOAD32(it + 1);
-    }
-    const float* LA = lds + (buf * 2) * ARR;
-    const float* LB = LA + ARR;
-    const int h = lane >> 5;
-    f32x4 af[MI][2], bf[NI][2];
-#pragma clang loop unroll(full)
-    for (int mi = 0; mi < MI; ++mi) {
-      const int row = wm * TM + mi * 32 + (lane & 31);
-#pragma clang loop unroll(full)
-      for (int u = 0; u < 2; ++u)
-        af[mi][u] = *reinterpret_cast<const f32x4*>(LA + row * BK + (((2 * h + u) ^ swz(row)) * 4));
-    }
-#pragma clang loop unroll(full)
-    for (int ni = 0; ni < NI; ++ni) {
-      const int row = wn * TN + ni * 32 + (lane & 31);
-#pragma clang loop unroll(full)
-      for (int u = 0; u < 2; ++u)
-        bf[ni][u] = *reinterpret_cast<const f32x4*>(LB + row * BK + (((2 * h + u) ^ swz(row)) * 4));
-    }
-#pragma clang loop unroll(full)
-    for (int k = 0; k < 8; ++k)
-#pragma clang loop unroll(full)
-      for (int mi = 0; mi < MI; ++mi)
-#pragma clang loop unroll(full)
-        for (int ni = 0; ni < NI; ++ni)
-          acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[mi][k >> 2][k & 3],
-                                                             bf[ni][k >> 2][k & 3], acc[mi][ni], 0,
-                                                             0, 0);
-    if (it + 1 < ie) {
-      SP2_LSTORE32(buf ^ 1);
-    }
-    __syncthreads();
+  SP2_F32_FRAG(A0, B0, 0);
+  for (int kt = kb; kt < ke; kt += 2) {
+    SP2_F32_STEP(kt, A0, B0, A1, B1);
+    SP2_F32_STEP(kt + 1, A1, B1, A0, B0);
   }
-#undef SP2_GLOAD32
-#undef SP2_LSTORE32
-  if (tail >= 0 && !reduce_tail<NT, MI, NI>(acc, p.dc, tail, piece)) return;
-  sym_epilogue<NT, BM, TM, TN, MI, NI>(acc, p.epi, alpha, beta, ti, tj, wm, wn, lane, red, tile);
+  wait_vmem_all();
+  __syncthreads();
+#undef SP2_F32_SRC
+#undef SP2_F32_STAGE
+#undef SP2_F32_FRAG
+#undef SP2_F32_MFMA
+#undef SP2_F32_STEP
+  if (tail >= 0) {   // summed and finished by k_split_tail
+    store_piece<NT, MI, NI>(acc, p.dc, tail, piece);
+    return;
+  }
+  sym_epilogue_lds<NT, MI, NI>(acc, p.epi, alpha, beta, ti, tj, wm, wn, lane, red, tile, lds);
 }
 
 }  // namespace sp2
