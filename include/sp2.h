@@ -196,6 +196,66 @@ sp2_status sp2_split(const float* X, int64_t n, int64_t ld, int32_t precision,
 sp2_status sp2_layer(const float* X, int64_t n, int64_t ld, int32_t precision, int32_t sign,
                      float* Y, void* workspace, size_t ws_bytes, void* stream);
 
+/* ---- XL-BOMD kernel building block (Section III, Eq. 27-28) ----------------
+ * Extended-Lagrangian dynamics propagates one net charge n_I per atom and
+ * drives it towards the ground-state charges q0[n] of H(n) through the
+ * kernel K = J^-1, J = dq0/dn - I the Jacobian of the residual
+ * f(n) = q0[n] - n; the paper approximates K f in a preconditioned Krylov
+ * subspace.  The charge model is given by its pieces:
+ *   atom_ptr: DEVICE int64[n_atoms + 1]; atom I owns orbitals
+ *             atom_ptr[I] .. atom_ptr[I+1]-1 (non-decreasing, at most n;
+ *             orbitals past atom_ptr[n_atoms] belong to no atom).  Indices
+ *             are clamped to [0, n], so a malformed array gives meaningless
+ *             charges but no access outside the matrices.
+ *   gamma:    DEVICE double[n_atoms * n_atoms], row-major, symmetric: the
+ *             charge coupling, H(n) = H0 + diag(B gamma n) with B the
+ *             orbital-to-atom incidence (every orbital of atom I shifted by
+ *             (gamma n)_I).
+ * Charge vectors are DEVICE double[n_atoms]. */
+#define SP2_XL_MAX_RANK 32
+
+/* Net Mulliken charges of a density matrix in an orthogonal basis with doubly
+ * occupied states: q_I = z_I - 2 sum_{mu in I} P_mu,mu, minus sub_I when sub
+ * is not NULL (with sub = the dynamical charges n, q is the residual f(n)).
+ * P: n x n, leading dimension ld (only the diagonal is read); z, sub, q:
+ * DEVICE double[n_atoms].  Asynchronous on stream. */
+sp2_status sp2_mulliken(const float* P, int64_t n, int64_t ld, int64_t n_atoms,
+                        const int64_t* atom_ptr, const double* z, const double* sub, double* q,
+                        void* stream);
+
+/* Device scratch (bytes, 256-aligned) of sp2_xl_response / sp2_xl_kernel for
+ * matrices of order n, n_atoms atoms and Krylov rank `rank`. */
+size_t sp2_xl_scratch_bytes(int64_t n, int64_t n_atoms, int32_t rank);
+
+/* Charge-space Jacobian-vector product jv = J v = dq0/dn v - v at the H of
+ * the last sp2_density_ex call on `workspace` (which must hold a derivative
+ * tape: opt->checkpoint_every > 0): dq0/dn v = -2 B^T diag(P1) with P1 the
+ * sp2_jvp response to H1 = diag(B gamma v).  v, jv: DEVICE double[n_atoms].
+ * Blocks until done.  SP2_ERR_TAPE without a tape. */
+sp2_status sp2_xl_response(void* workspace, size_t ws_bytes, int64_t n_atoms,
+                           const int64_t* atom_ptr, const double* gamma, const double* v,
+                           double* jv, void* scratch, size_t scratch_bytes, void* stream);
+
+/* Rank-`rank` (1..SP2_XL_MAX_RANK) Krylov approximation kf ~ K f = J^-1 f at
+ * the H of the last sp2_density_ex call on `workspace` (derivative tape
+ * required).  With the preconditioner K0 (DEVICE double[n_atoms^2],
+ * row-major; NULL means K0 = -I): v_1 = K0 f / |K0 f|; each further basis
+ * vector is K0 J v_k (one sp2_xl_response) orthonormalised against the
+ * previous ones (classical Gram-Schmidt, two passes); kf = V c with c
+ * minimising |K0 J V c - K0 f| (QR of the K0 J v_k, two-pass Gram-Schmidt).
+ * This is the minimal-residual (GMRES) form of the preconditioned Krylov
+ * approximation; at full rank it is exact.  The basis stops early when a new
+ * direction vanishes (invariant subspace: the result is then exact).
+ * Outputs: kf (DEVICE double[n_atoms]); rho (HOST double[rank + 1] or NULL):
+ * rho[0] = |K0 f|, rho[k] the minimal residual with k basis vectors (entries
+ * past the rank used are repeated); rank_used (HOST or NULL).  Blocks until
+ * done.  SP2_ERR_INVALID_ARG for a rank outside the range or too small a
+ * scratch; SP2_ERR_TAPE without a tape. */
+sp2_status sp2_xl_kernel(void* workspace, size_t ws_bytes, int64_t n_atoms,
+                         const int64_t* atom_ptr, const double* gamma, const double* k0,
+                         const double* f, int32_t rank, double* kf, double* rho,
+                         int32_t* rank_used, void* scratch, size_t scratch_bytes, void* stream);
+
 /* Thread-local text describing the last error of this thread ("" if none). */
 const char* sp2_last_error(void);
 

@@ -13,3 +13,4 @@ from .sp2_oracle import *  # noqa: F401,F403
 from . import precision_emulation  # noqa: F401,E402
 from . import lanczos  # noqa: F401,E402
 from .lanczos import lanczos_bounds  # noqa: F401,E402
+from . import xlbomd  # noqa: F401,E402

@@ -40,7 +40,9 @@ SP2_MAX_ITER = 256
 # Every symbol include/sp2.h declares.
 EXPORTED = ["sp2_default_options", "sp2_workspace_bytes", "sp2_density", "sp2_density_ex",
             "sp2_jvp", "sp2_vjp", "sp2_bounds", "sp2_spectral_bounds", "sp2_split", "sp2_layer",
+            "sp2_mulliken", "sp2_xl_scratch_bytes", "sp2_xl_response", "sp2_xl_kernel",
             "sp2_last_error"]
+SP2_XL_MAX_RANK = 32
 
 
 class sp2_options(ctypes.Structure):
@@ -105,6 +107,15 @@ def load_library(path=None):
     lib.sp2_split.restype = c_int32
     lib.sp2_layer.argtypes = [vp, c_int64, c_int64, c_int32, c_int32, vp, vp, c_size_t, vp]
     lib.sp2_layer.restype = c_int32
+    lib.sp2_mulliken.argtypes = [vp, c_int64, c_int64, c_int64, vp, vp, vp, vp, vp]
+    lib.sp2_mulliken.restype = c_int32
+    lib.sp2_xl_scratch_bytes.argtypes = [c_int64, c_int64, c_int32]
+    lib.sp2_xl_scratch_bytes.restype = c_size_t
+    lib.sp2_xl_response.argtypes = [vp, c_size_t, c_int64, vp, vp, vp, vp, vp, c_size_t, vp]
+    lib.sp2_xl_response.restype = c_int32
+    lib.sp2_xl_kernel.argtypes = [vp, c_size_t, c_int64, vp, vp, vp, vp, c_int32, vp,
+                                  ctypes.POINTER(c_double), ctypes.POINTER(c_int32), vp, c_size_t, vp]
+    lib.sp2_xl_kernel.restype = c_int32
     lib.sp2_last_error.argtypes = []
     lib.sp2_last_error.restype = ctypes.c_char_p
     _LIB = lib
@@ -261,3 +272,82 @@ def sp2_layer(X, precision, sign, Y, workspace):
 
 def sp2_last_error():
     return load_library().sp2_last_error().decode(errors="replace")
+
+
+def _dev_vec(t, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype or t.dim() != 1 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous 1-D {dtype} tensor")
+    return c_void_p(t.data_ptr())
+
+
+def _charge_model_args(atom_ptr, gamma):
+    na = atom_ptr.numel() - 1
+    if na < 1:
+        raise ValueError("atom_ptr needs n_atoms + 1 entries")
+    if gamma.shape != (na, na) or gamma.dtype != torch.float64 or not gamma.is_contiguous():
+        raise ValueError("gamma must be a contiguous n_atoms x n_atoms float64 device tensor")
+    return na, _dev_vec(atom_ptr, torch.int64, "atom_ptr"), c_void_p(gamma.data_ptr())
+
+
+def sp2_mulliken(P, atom_ptr, z, sub=None, q=None):
+    """``q_I = z_I - 2 sum_{mu in I} P_mu,mu`` (minus ``sub`` if given)."""
+    lib = load_library()
+    na = atom_ptr.numel() - 1
+    if q is None:
+        q = torch.empty(na, dtype=torch.float64, device=P.device)
+    _check(lib.sp2_mulliken(_dev_ptr(P, name="P"), P.shape[0], P.stride(0), na,
+                            _dev_vec(atom_ptr, torch.int64, "atom_ptr"),
+                            _dev_vec(z, torch.float64, "z"),
+                            _dev_vec(sub, torch.float64, "sub") if sub is not None else None,
+                            _dev_vec(q, torch.float64, "q"), _stream(P.device)))
+    return q
+
+
+def sp2_xl_scratch_bytes(n, n_atoms, rank):
+    return int(load_library().sp2_xl_scratch_bytes(int(n), int(n_atoms), int(rank)))
+
+
+def allocate_xl_scratch(n, n_atoms, rank, device=None):
+    """Caller-owned device scratch of sp2_xl_response / sp2_xl_kernel."""
+    nbytes = sp2_xl_scratch_bytes(n, n_atoms, rank)
+    if nbytes == 0:
+        raise SP2Error(SP2_ERR_INVALID_ARG, "invalid size or rank")
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device or "cuda")
+    off = (-buf.data_ptr()) % 256
+    return buf[off:off + nbytes]
+
+
+def sp2_xl_response(workspace, atom_ptr, gamma, v, scratch, jv=None):
+    """``J v = dq0/dn v - v`` at the taped H."""
+    lib = load_library()
+    na, ptr, g = _charge_model_args(atom_ptr, gamma)
+    if jv is None:
+        jv = torch.empty(na, dtype=torch.float64, device=v.device)
+    _check(lib.sp2_xl_response(c_void_p(workspace.data_ptr()), workspace.numel(), na, ptr, g,
+                               _dev_vec(v, torch.float64, "v"), _dev_vec(jv, torch.float64, "jv"),
+                               c_void_p(scratch.data_ptr()), scratch.numel(), _stream(v.device)))
+    return jv
+
+
+def sp2_xl_kernel(workspace, atom_ptr, gamma, f, rank, scratch, k0=None, kf=None):
+    """Rank-``rank`` Krylov approximation of ``K f = J^-1 f`` at the taped H.
+    Returns ``(kf, rho, rank_used)`` (``rho`` a list of ``rank + 1`` floats)."""
+    lib = load_library()
+    na, ptr, g = _charge_model_args(atom_ptr, gamma)
+    if kf is None:
+        kf = torch.empty(na, dtype=torch.float64, device=f.device)
+    if k0 is not None and (k0.shape != (na, na) or k0.dtype != torch.float64
+                           or not k0.is_contiguous() or not k0.is_cuda):
+        raise ValueError("k0 must be a contiguous n_atoms x n_atoms float64 device tensor")
+    rank = int(rank)
+    rho = (c_double * (max(rank, 0) + 1))()
+    used = c_int32(0)
+    _check(lib.sp2_xl_kernel(c_void_p(workspace.data_ptr()), workspace.numel(), na, ptr, g,
+                             c_void_p(k0.data_ptr()) if k0 is not None else None,
+                             _dev_vec(f, torch.float64, "f"), rank, _dev_vec(kf, torch.float64, "kf"),
+                             rho, ctypes.byref(used), c_void_p(scratch.data_ptr()), scratch.numel(),
+                             _stream(f.device)))
+    return kf, list(rho), used.value
+

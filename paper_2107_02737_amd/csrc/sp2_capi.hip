@@ -18,6 +18,7 @@
 #include "sp2_common.hpp"
 #include "sp2_gemm.hpp"
 #include "sp2_lanczos.hpp"
+#include "sp2_xl.hpp"
 
 using namespace sp2;
 
@@ -268,6 +269,8 @@ struct HostMirror {
   Ctrl ctrl[2];
   Hist hist;
   Meta meta;
+  XlState xl;
+  int xl_stop;
 };
 thread_local HostMirror* g_host = nullptr;
 
@@ -993,22 +996,11 @@ sp2_status load_checkpoint(const WS& w, int prec, int slot, float* dst, hipStrea
   return SP2_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-sp2_status sp2_jvp(void* workspace, size_t ws_bytes, const float* H1, int64_t ld, float* P1,
-                   void* stream) {
-  g_err.clear();
-  if (!H1 || !P1) return fail(SP2_ERR_INVALID_ARG, "NULL argument");
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  WS w;
-  HostMirror* hm;
-  sp2_options o;
-  if (sp2_status s = open_tape(workspace, ws_bytes, st, w, hm, o)) return s;
+// Forward derivative P1 = dP/dH [H1] of the taped network (open tape).
+sp2_status jvp_run(const WS& w, const HostMirror* hm, const sp2_options& o, const float* H1,
+                   int64_t ld, float* P1, hipStream_t st) {
   const Layout& L = w.L;
   const int64_t n = L.n;
-  if (ld < n) return fail(SP2_ERR_INVALID_ARG, "ld < n");
   const bool vec_ok = (ld % 4 == 0) && (reinterpret_cast<uintptr_t>(P1) % 16 == 0);
   if (hm->meta.valid == 2) {   // n_occ in {0, n}: P does not depend on H
     k_fill_diag<<<ew_grid(n * n), kEwThreads, 0, st>>>(P1, n, ld, 0.0f);
@@ -1042,6 +1034,23 @@ sp2_status sp2_jvp(void* workspace, size_t ws_bytes, const float* H1, int64_t ld
   }
   HIP_TRY(hipStreamSynchronize(st));
   return SP2_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sp2_status sp2_jvp(void* workspace, size_t ws_bytes, const float* H1, int64_t ld, float* P1,
+                   void* stream) {
+  g_err.clear();
+  if (!H1 || !P1) return fail(SP2_ERR_INVALID_ARG, "NULL argument");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  WS w;
+  HostMirror* hm;
+  sp2_options o;
+  if (sp2_status s = open_tape(workspace, ws_bytes, st, w, hm, o)) return s;
+  if (ld < w.L.n) return fail(SP2_ERR_INVALID_ARG, "ld < n");
+  return jvp_run(w, hm, o, H1, ld, P1, st);
 }
 
 sp2_status sp2_vjp(void* workspace, size_t ws_bytes, const float* W, int64_t ld, float* G,
@@ -1102,6 +1111,183 @@ sp2_status sp2_vjp(void* workspace, size_t ws_bytes, const float* W, int64_t ld,
   k_copy_scaled<<<ew_grid(n * n), kEwThreads, 0, st>>>(w.work(cur), L.np, G, ld, n, n, -inv, 0);
   LAUNCH_TRY();
   HIP_TRY(hipStreamSynchronize(st));
+  return SP2_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Scratch of the XL-BOMD building block (offsets from a 256-aligned base):
+// H1 and P1 (n x n FP32, leading dimension n), the basis V and the response
+// QR factor Q (rank rows of n_atoms doubles each), five charge vectors and
+// the Krylov state.
+struct XlScratch {
+  float* h1;
+  float* p1;
+  double *V, *Q, *r0, *res, *u, *jv, *fk;
+  XlState* st;
+  size_t total;
+};
+
+size_t xl_layout(int64_t n, int64_t na, int rank, char* base, XlScratch* x) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o2 = off;
+    off = round_up(off + bytes, 256);
+    return base ? base + o2 : nullptr;
+  };
+  const size_t mat = size_t(n) * size_t(n) * 4, vec = size_t(na) * 8;
+  char* h1 = take(mat);
+  char* p1 = take(mat);
+  char* V = take(vec * size_t(rank));
+  char* Q = take(vec * size_t(rank));
+  char* r0 = take(vec);
+  char* res = take(vec);
+  char* u = take(vec);
+  char* jv = take(vec);
+  char* fk = take(vec);
+  char* st = take(sizeof(XlState));
+  if (x) {
+    x->h1 = reinterpret_cast<float*>(h1);
+    x->p1 = reinterpret_cast<float*>(p1);
+    x->V = reinterpret_cast<double*>(V);
+    x->Q = reinterpret_cast<double*>(Q);
+    x->r0 = reinterpret_cast<double*>(r0);
+    x->res = reinterpret_cast<double*>(res);
+    x->u = reinterpret_cast<double*>(u);
+    x->jv = reinterpret_cast<double*>(jv);
+    x->fk = reinterpret_cast<double*>(fk);
+    x->st = reinterpret_cast<XlState*>(st);
+    x->total = off;
+  }
+  return off;
+}
+
+int atom_grid(int64_t na) { return static_cast<int>((na + 255) / 256); }
+
+// Common argument checks and set-up of sp2_xl_response / sp2_xl_kernel:
+// open the tape, bind the scratch and clear H1.
+sp2_status xl_open(void* workspace, size_t ws_bytes, int64_t na, const int64_t* atom_ptr,
+                   const double* gamma, int rank, void* scratch, size_t scratch_bytes,
+                   hipStream_t st, WS& w, HostMirror*& hm, sp2_options& o, XlScratch& x) {
+  if (!atom_ptr || !gamma) return fail(SP2_ERR_INVALID_ARG, "NULL atom_ptr or gamma");
+  if (na <= 0 || na > (int64_t(1) << 24)) return fail(SP2_ERR_INVALID_ARG, "n_atoms out of range");
+  if (!scratch || reinterpret_cast<uintptr_t>(scratch) % 256)
+    return fail(SP2_ERR_INVALID_ARG, "scratch missing or not 256-byte aligned");
+  if (sp2_status s = open_tape(workspace, ws_bytes, st, w, hm, o)) return s;
+  const int64_t n = w.L.n;
+  if (scratch_bytes < xl_layout(n, na, rank, nullptr, nullptr))
+    return fail(SP2_ERR_INVALID_ARG, "scratch smaller than sp2_xl_scratch_bytes");
+  xl_layout(n, na, rank, static_cast<char*>(scratch), &x);
+  k_fill_diag<<<ew_grid(n * n), kEwThreads, 0, st>>>(x.h1, n, n, 0.0f);
+  LAUNCH_TRY();
+  return SP2_OK;
+}
+
+// jv = J v = dq0/dn v - v: u = gamma v, H1 = diag(B u), P1 = JVP(H1),
+// jv_I = -2 sum_{mu in I} P1_mu,mu - v_I.  Blocks (the JVP does).
+sp2_status xl_apply_j(const WS& w, const HostMirror* hm, const sp2_options& o, const XlScratch& x,
+                      int64_t na, const int64_t* atom_ptr, const double* gamma, const double* v,
+                      double* jv, hipStream_t st) {
+  const int64_t n = w.L.n;
+  k_atom_matvec<<<static_cast<int>((na + 3) / 4), 256, 0, st>>>(gamma, v, na, 1.0, x.u);
+  LAUNCH_TRY();
+  k_potential_diag<<<atom_grid(na), 256, 0, st>>>(x.u, atom_ptr, na, n, x.h1, n);
+  LAUNCH_TRY();
+  if (sp2_status s = jvp_run(w, hm, o, x.h1, n, x.p1, st)) return s;
+  k_mulliken<<<atom_grid(na), 256, 0, st>>>(x.p1, n, n, na, atom_ptr, nullptr, v, jv);
+  LAUNCH_TRY();
+  return SP2_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sp2_status sp2_mulliken(const float* P, int64_t n, int64_t ld, int64_t n_atoms,
+                        const int64_t* atom_ptr, const double* z, const double* sub, double* q,
+                        void* stream) {
+  g_err.clear();
+  if (!P || !atom_ptr || !z || !q) return fail(SP2_ERR_INVALID_ARG, "NULL argument");
+  if (n <= 0 || ld < n) return fail(SP2_ERR_INVALID_ARG, "need n > 0 and ld >= n");
+  if (n_atoms <= 0 || n_atoms > (int64_t(1) << 24))
+    return fail(SP2_ERR_INVALID_ARG, "n_atoms out of range");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  k_mulliken<<<atom_grid(n_atoms), 256, 0, st>>>(P, n, ld, n_atoms, atom_ptr, z, sub, q);
+  LAUNCH_TRY();
+  return SP2_OK;
+}
+
+size_t sp2_xl_scratch_bytes(int64_t n, int64_t n_atoms, int32_t rank) {
+  if (n <= 0 || n_atoms <= 0 || rank < 1 || rank > SP2_XL_MAX_RANK) return 0;
+  return xl_layout(n, n_atoms, rank, nullptr, nullptr);
+}
+
+sp2_status sp2_xl_response(void* workspace, size_t ws_bytes, int64_t n_atoms,
+                           const int64_t* atom_ptr, const double* gamma, const double* v,
+                           double* jv, void* scratch, size_t scratch_bytes, void* stream) {
+  g_err.clear();
+  if (!v || !jv) return fail(SP2_ERR_INVALID_ARG, "NULL v or jv");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  WS w;
+  HostMirror* hm;
+  sp2_options o;
+  XlScratch x;
+  if (sp2_status s = xl_open(workspace, ws_bytes, n_atoms, atom_ptr, gamma, 1, scratch,
+                             scratch_bytes, st, w, hm, o, x))
+    return s;
+  if (sp2_status s = xl_apply_j(w, hm, o, x, n_atoms, atom_ptr, gamma, v, jv, st)) return s;
+  HIP_TRY(hipStreamSynchronize(st));
+  return SP2_OK;
+}
+
+sp2_status sp2_xl_kernel(void* workspace, size_t ws_bytes, int64_t n_atoms,
+                         const int64_t* atom_ptr, const double* gamma, const double* k0,
+                         const double* f, int32_t rank, double* kf, double* rho,
+                         int32_t* rank_used, void* scratch, size_t scratch_bytes, void* stream) {
+  g_err.clear();
+  if (!f || !kf) return fail(SP2_ERR_INVALID_ARG, "NULL f or kf");
+  if (rank < 1 || rank > SP2_XL_MAX_RANK) return fail(SP2_ERR_INVALID_ARG, "rank out of range");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  WS w;
+  HostMirror* hm;
+  sp2_options o;
+  XlScratch x;
+  if (sp2_status s = xl_open(workspace, ws_bytes, n_atoms, atom_ptr, gamma, rank, scratch,
+                             scratch_bytes, st, w, hm, o, x))
+    return s;
+  const int64_t na = n_atoms;
+  const int mv_grid = static_cast<int>((na + 3) / 4);
+  // r0 = K0 f
+  if (k0)
+    k_atom_matvec<<<mv_grid, 256, 0, st>>>(k0, f, na, 1.0, x.r0);
+  else
+    k_atom_scale<<<atom_grid(na), 256, 0, st>>>(f, na, -1.0, x.r0);
+  LAUNCH_TRY();
+  k_xl_init<<<1, kXlThreads, 0, st>>>(x.r0, na, x.V, x.res, x.st);
+  LAUNCH_TRY();
+  for (int k = 0; k < rank; ++k) {
+    HIP_TRY(hipMemcpyAsync(&hm->xl_stop, &x.st->stop, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (hm->xl_stop) break;
+    const double* vk = x.V + int64_t(k) * na;
+    if (sp2_status s = xl_apply_j(w, hm, o, x, na, atom_ptr, gamma, vk, x.jv, st)) return s;
+    if (k0)
+      k_atom_matvec<<<mv_grid, 256, 0, st>>>(k0, x.jv, na, 1.0, x.fk);
+    else
+      k_atom_scale<<<atom_grid(na), 256, 0, st>>>(x.jv, na, -1.0, x.fk);
+    LAUNCH_TRY();
+    k_xl_step<<<1, kXlThreads, 0, st>>>(x.fk, k, k + 1 == rank, na, x.V, x.Q, x.res, x.u, x.st);
+    LAUNCH_TRY();
+  }
+  k_xl_finish<<<1, kXlThreads, 0, st>>>(x.V, na, x.st, kf);
+  LAUNCH_TRY();
+  HIP_TRY(hipMemcpyAsync(&hm->xl, x.st, sizeof(XlState), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (rho)
+    for (int k = 0; k <= rank; ++k) rho[k] = hm->xl.rho[k];
+  if (rank_used) *rank_used = hm->xl.used;
   return SP2_OK;
 }
 

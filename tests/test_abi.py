@@ -117,3 +117,34 @@ def test_invalid_arguments_rejected_before_device_work(lib):
     for steps in (0, 7, 65):
         assert lib.sp2_spectral_bounds(fake, 8, 8, steps, 0, ctypes.byref(lo), ctypes.byref(hi),
                                        ws, 1 << 30, None) == _lib.SP2_ERR_INVALID_ARG
+
+
+def test_xl_entry_points_reject_bad_arguments(lib):
+    from paper_2107_02737_amd import _lib
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.sp2_xl_scratch_bytes(0, 10, 4) == 0
+    assert lib.sp2_xl_scratch_bytes(64, 10, 0) == 0
+    assert lib.sp2_xl_scratch_bytes(64, 10, _lib.SP2_XL_MAX_RANK + 1) == 0
+    small = lib.sp2_xl_scratch_bytes(64, 10, 1)
+    # two n x n FP32 matrices, 2 rank + 5 charge vectors and the Krylov state
+    assert small >= 2 * 64 * 64 * 4 + 7 * 10 * 8
+    assert lib.sp2_xl_scratch_bytes(64, 10, 8) > small
+    assert lib.sp2_mulliken(None, 8, 8, 2, fake, fake, None, fake, None) == _lib.SP2_ERR_INVALID_ARG
+    assert lib.sp2_mulliken(fake, 8, 4, 2, fake, fake, None, fake, None) == _lib.SP2_ERR_INVALID_ARG
+    assert lib.sp2_mulliken(fake, 8, 8, 0, fake, fake, None, fake, None) == _lib.SP2_ERR_INVALID_ARG
+    rho = (ctypes.c_double * 40)()
+    used = ctypes.c_int32()
+    for rank in (0, _lib.SP2_XL_MAX_RANK + 1):
+        st = lib.sp2_xl_kernel(fake, 1 << 30, 4, fake, fake, None, fake, rank, fake, rho,
+                               ctypes.byref(used), fake, 1 << 30, None)
+        assert st == _lib.SP2_ERR_INVALID_ARG and "rank" in _lib.sp2_last_error()
+    st = lib.sp2_xl_kernel(fake, 1 << 30, 4, fake, fake, None, None, 2, fake, rho,
+                           ctypes.byref(used), fake, 1 << 30, None)
+    assert st == _lib.SP2_ERR_INVALID_ARG
+    assert lib.sp2_xl_response(fake, 1 << 30, 4, fake, fake, None, fake, fake, 1 << 30, None) == \
+        _lib.SP2_ERR_INVALID_ARG
+    # checks that precede the tape read: missing charge model, misaligned scratch
+    assert lib.sp2_xl_response(fake, 1 << 30, 4, None, fake, fake, fake, fake, 1 << 30, None) == \
+        _lib.SP2_ERR_INVALID_ARG
+    assert lib.sp2_xl_response(fake, 1 << 30, 4, fake, fake, fake, fake,
+                               ctypes.c_void_p(0x1010), 1 << 30, None) == _lib.SP2_ERR_INVALID_ARG

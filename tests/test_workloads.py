@@ -79,3 +79,20 @@ def test_padding_and_operands():
     hp = trajectory_perturbation(64, 3, n_real=60)
     assert np.array_equal(hp, hp.T) and not hp[:, 60:].any()
     assert 0.7 < np.linalg.norm(hp[:60, :60], 2) < 1.3
+
+
+def test_water_charge_model():
+    from workloads import charge_shifted_hamiltonian, random_charges, water_charge_model
+    mod = water_charge_model(5, seed=2)
+    ptr, g = mod["atom_ptr"], mod["gamma"]
+    assert ptr.tolist()[:4] == [0, 4, 5, 6] and ptr[-1] == 30 and ptr.size == 16
+    assert mod["z"].sum() == 2 * mod["n_occ"]            # neutral at n_occ = 4M
+    assert np.array_equal(g, g.T) and np.all(np.diag(g)[:3] == [0.5, 0.4, 0.4])
+    assert np.all(np.linalg.eigvalsh(g) > 0)
+    c = random_charges(15, seed=1)
+    assert abs(c.sum()) < 1e-15
+    h = charge_shifted_hamiltonian(mod["h0"], ptr, g, c)
+    shift = g @ c
+    assert np.allclose(np.diag(h - mod["h0"]), np.repeat(shift, np.diff(ptr)))
+    off = (h - mod["h0"]) - np.diag(np.diag(h - mod["h0"]))
+    assert np.all(off == 0)

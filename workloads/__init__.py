@@ -1,9 +1,9 @@
 """Seeded synthetic inputs for the density-matrix solver.
 
-This package only draws input matrices (Hamiltonians, perturbations and
-weights).  It holds none of the solver's arithmetic, so both the FP64 oracle
-and the GPU path can take their inputs from here without sharing any code
-with each other.
+This package only draws inputs (Hamiltonians, perturbations, weights and
+the synthetic charge model).  It holds none of the solver's arithmetic, so
+both the FP64 oracle and the GPU path can take their inputs from here
+without sharing any code with each other.
 """
 
 from .hamiltonians import (  # noqa: F401
@@ -16,4 +16,10 @@ from .hamiltonians import (  # noqa: F401
     trajectory_hamiltonian,
     pad_matrix,
     WATER_ONSITE,
+)
+from .charges import (  # noqa: F401
+    water_charge_model,
+    random_charges,
+    charge_shifted_hamiltonian,
+    WATER_VALENCE,
 )
