@@ -12,8 +12,10 @@ Prints ONE JSON line.  Also reported: effective TFLOPS (3 products of
 2 N^3 per split layer + 2 N^3 per refinement product), the error against the
 FP64 oracle from stored samples of the exact density matrix, plain FP32 SP2
 on the same GPU, the roofline of the layer kernel (HIP-event durations
-recorded around every layer launch during the timed steps) and the FP64
-oracle timed on the host cores.
+recorded around every layer launch during the timed steps), the FP64
+oracle timed on the host cores and, outside the timed steps, the XL-BOMD
+kernel building block (one charge-space response and a rank-4 Krylov
+approximation of K f on the water box's synthetic charge model).
 """
 
 import argparse
@@ -56,6 +58,9 @@ def parse():
                     help="instead of the benchmark: run STEPS steps of the N=16384 trajectory "
                          "workload H(t) = H0 + 0.01 sin(0.1 t) H_p (adjoint on the last step) "
                          "and print per-step times and the drift of Tr P and idempotency")
+    ap.add_argument("--xl-rank", type=int, default=4,
+                    help="also time the XL-BOMD kernel building block (Krylov approximation of "
+                         "K f of this rank on the water box's charge model; 0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM traffic counters)")
     return ap.parse_args()
@@ -210,6 +215,48 @@ def device_checks(P, n_occ):
     }
 
 
+def xl_kernel(pk, seed, rank, precision, refine):
+    """The XL-BOMD kernel building block at N = 6144: H(n) of the water box's
+    synthetic charge model at seeded charges n, one taped solve, then one
+    charge-space response J v and one rank-``rank`` Krylov approximation of
+    K f (f = q0[n] - n), each timed with HIP events; the minimal residual the
+    Krylov call reports is checked against |f - J kf| from a further response."""
+    import torch
+    from workloads import charge_shifted_hamiltonian, random_charges, water_charge_model
+
+    mod = water_charge_model(1024, seed=seed)
+    na = mod["z"].size
+    charges = random_charges(na, seed=5)
+    h = charge_shifted_hamiltonian(mod["h0"], mod["atom_ptr"], mod["gamma"], charges)
+    H = torch.from_numpy(h.astype(np.float32)).to("cuda")
+    dev = lambda a, dt=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dt)
+    ptr, z, gamma, nvec = dev(mod["atom_ptr"], torch.int64), dev(mod["z"]), dev(mod["gamma"]), dev(charges)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    ev[0].record()
+    P, info = pk.density(H, mod["n_occ"], precision=precision, refine=refine, checkpoint_every=4,
+                         return_info=True)
+    ev[1].record()
+    ws = info["workspace"]
+    f = pk.sp2_mulliken(P, ptr, z, sub=nvec)
+    scratch = pk.allocate_xl_scratch(H.shape[0], na, rank)
+    v = dev(np.random.default_rng(3).standard_normal(na))
+    ev[2].record()
+    pk.sp2_xl_response(ws, ptr, gamma, v, scratch)
+    ev[3].record()
+    kf, rho, used = pk.sp2_xl_kernel(ws, ptr, gamma, f, rank, scratch)
+    ev[4].record()
+    jkf = pk.sp2_xl_response(ws, ptr, gamma, kf, scratch)
+    torch.cuda.synchronize()
+    direct = float(np.linalg.norm(f.cpu().numpy() - jkf.cpu().numpy()))
+    return {"n_atoms": na, "rank": rank, "rank_used": used, "precision": precision,
+            "taped_solve_ms": ev[0].elapsed_time(ev[1]),
+            "response_ms": ev[2].elapsed_time(ev[3]), "krylov_ms": ev[3].elapsed_time(ev[4]),
+            "rho_over_rho0": [r / rho[0] for r in rho],
+            "check_residual_over_rho0": direct / rho[0],
+            "workload": "water box 1024 molecules, synthetic charge model (screened Coulomb "
+                        "gamma), seeded charges"}
+
+
 def cpu_baseline(h32, n_occ, layers, n_iter_ref):
     """The FP64 oracle as it stands on the host cores, on a bounded sample:
     bounds + input layer + ``layers`` SP2 layers at full N, extrapolated to a
@@ -340,6 +387,8 @@ def main():
                            "layer_ms": f_layer_ms,
                            "layer_tflops": float(n) ** 3 / (f_layer_ms * 1e-3) / 1e12,
                            "speedup_of_split": fsec / sec}
+    if args.xl_rank > 0:
+        out["xl_kernel"] = xl_kernel(pk, int(gold["seed"]), args.xl_rank, args.precision, args.refine)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(h32, n_occ, args.cpu_layers, n_iter)
     print(json.dumps(out), flush=True)
