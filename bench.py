@@ -215,7 +215,7 @@ def device_checks(P, n_occ):
     }
 
 
-def xl_kernel(pk, seed, rank, precision, refine):
+def xl_kernel(pk, seed, rank, precision, refine, split_derivatives=False):
     """The XL-BOMD kernel building block at N = 6144: H(n) of the water box's
     synthetic charge model at seeded charges n, one taped solve, then one
     charge-space response J v and one rank-``rank`` Krylov approximation of
@@ -234,7 +234,7 @@ def xl_kernel(pk, seed, rank, precision, refine):
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
     ev[0].record()
     P, info = pk.density(H, mod["n_occ"], precision=precision, refine=refine, checkpoint_every=4,
-                         return_info=True)
+                         return_info=True, split_derivatives=split_derivatives)
     ev[1].record()
     ws = info["workspace"]
     f = pk.sp2_mulliken(P, ptr, z, sub=nvec)
@@ -249,6 +249,7 @@ def xl_kernel(pk, seed, rank, precision, refine):
     torch.cuda.synchronize()
     direct = float(np.linalg.norm(f.cpu().numpy() - jkf.cpu().numpy()))
     return {"n_atoms": na, "rank": rank, "rank_used": used, "precision": precision,
+            "derivative_products": "bf16x3" if split_derivatives and precision == "bf16x3" else "fp32",
             "taped_solve_ms": ev[0].elapsed_time(ev[1]),
             "response_ms": ev[2].elapsed_time(ev[3]), "krylov_ms": ev[3].elapsed_time(ev[4]),
             "rho_over_rho0": [r / rho[0] for r in rho],
@@ -389,6 +390,9 @@ def main():
                            "speedup_of_split": fsec / sec}
     if args.xl_rank > 0:
         out["xl_kernel"] = xl_kernel(pk, int(gold["seed"]), args.xl_rank, args.precision, args.refine)
+        if args.precision == "bf16x3":
+            out["xl_kernel_split_derivatives"] = xl_kernel(pk, int(gold["seed"]), args.xl_rank,
+                                                           args.precision, args.refine, True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(h32, n_occ, args.cpu_layers, n_iter)
     print(json.dumps(out), flush=True)

@@ -66,6 +66,7 @@ typedef enum { SP2_REFINE_NONE = 0, SP2_REFINE_FP32 = 1, SP2_REFINE_SPLIT = 2 } 
 #define SP2_MIN_BOUND_STEPS 8
 #define SP2_MAX_BOUND_STEPS 64
 #define SP2_FLAG_TIME_LAYERS 1
+#define SP2_FLAG_SPLIT_DERIVATIVES 2
 
 typedef struct {
   int32_t precision;        /* sp2_precision (default SP2_BF16X3) */
@@ -76,7 +77,12 @@ typedef struct {
   int32_t checkpoint_every; /* 0 (default): no tape.  k > 0: keep S_0 and every k-th
                                iterate in the workspace for sp2_jvp / sp2_vjp */
   int32_t flags;            /* bit SP2_FLAG_TIME_LAYERS: time every layer launch with HIP
-                               events on `stream` (fills sp2_info.layer_ms/refine_ms) */
+                               events on `stream` (fills sp2_info.layer_ms/refine_ms).
+                               bit SP2_FLAG_SPLIT_DERIVATIVES (precision SP2_BF16X3 with a
+                               tape): sp2_jvp / sp2_vjp run the per-layer derivative
+                               products S dS + dS S in the same BF16X3 split arithmetic as
+                               the layers (one two-segment product [S|dS][dS|S]^T per layer)
+                               instead of FP32; the refinement's derivative stays FP32 */
   int32_t bound_steps;      /* 0 (default): Gershgorin bounds.  k in SP2_MIN_BOUND_STEPS..
                                SP2_MAX_BOUND_STEPS: tighten them with k Lanczos steps (see
                                sp2_spectral_bounds) */

@@ -144,11 +144,12 @@ def _stream(device):
 
 
 SP2_FLAG_TIME_LAYERS = 1
+SP2_FLAG_SPLIT_DERIVATIVES = 2
 
 
 def make_options(precision="bf16x3", refine="fp32", max_iter=100, stop_rule=1,
                  checkpoint_every=0, tol=1e-5, stall_gate=1.0, time_layers=False,
-                 bound_steps=0, bound_seed=0):
+                 bound_steps=0, bound_seed=0, split_derivatives=False):
     lib = load_library()
     o = sp2_options()
     lib.sp2_default_options(ctypes.byref(o))
@@ -159,7 +160,8 @@ def make_options(precision="bf16x3", refine="fp32", max_iter=100, stop_rule=1,
     o.checkpoint_every = int(checkpoint_every)
     o.tol = float(tol)
     o.stall_gate = float(stall_gate)
-    o.flags = SP2_FLAG_TIME_LAYERS if time_layers else 0
+    o.flags = (SP2_FLAG_TIME_LAYERS if time_layers else 0) | \
+        (SP2_FLAG_SPLIT_DERIVATIVES if split_derivatives else 0)
     o.bound_steps = int(bound_steps)
     o.bound_seed = int(bound_seed)
     return o

@@ -65,6 +65,8 @@ struct Meta {
   int32_t precision, refine, every, n_iter;
   int32_t valid;       // 1: tape usable, 2: trivial occupation (P independent of H), 0: none
   int32_t max_iter;
+  int32_t flags;       // options flags of the forward call (SP2_FLAG_SPLIT_DERIVATIVES)
+  int32_t reserved;
   int64_t magic;
 };
 constexpr int64_t kMetaMagic = 0x5350324d45544131LL;
@@ -239,7 +241,7 @@ bool options_ok(const sp2_options& o) {
          o.refine <= SP2_REFINE_SPLIT && o.max_iter >= 1 && o.max_iter <= SP2_MAX_ITER &&
          (o.stop_rule == 0 || o.stop_rule == 1) && o.checkpoint_every >= 0 &&
          o.checkpoint_every <= SP2_MAX_ITER && o.tol >= 0.0 && o.stall_gate >= 0.0 &&
-         (o.flags & ~SP2_FLAG_TIME_LAYERS) == 0 &&
+         (o.flags & ~(SP2_FLAG_TIME_LAYERS | SP2_FLAG_SPLIT_DERIVATIVES)) == 0 &&
          (o.bound_steps == 0 ||
           (o.bound_steps >= SP2_MIN_BOUND_STEPS && o.bound_steps <= SP2_MAX_BOUND_STEPS));
 }
@@ -377,6 +379,39 @@ sp2_status launch_split(const WS& w, int precision, const uint16_t* ah, const ui
   if (kind == kBF16X3) return launch_split_t<kBF16X3>(w, a, st);
   if (kind == kBF16X1) return launch_split_t<kBF16X1>(w, a, st);
   return launch_split_t<kFP16X3>(w, a, st);
+}
+
+// BF16X3 two-segment product out = alpha (X Y + Y X) + beta C of two
+// symmetric matrices given by their K-tiled planes: A = [X|Y], B = [Y|X].
+sp2_status launch_split_pair(const WS& w, const uint16_t* xh, const uint16_t* xl,
+                             const uint16_t* yh, const uint16_t* yl, const Epi& epi,
+                             const Decide& dec, hipStream_t st) {
+  SplitArgs a;
+  memset(&a, 0, sizeof(a));
+  a.a_hi = xh;
+  a.a_lo = xl;
+  a.b_hi = yh;
+  a.b_lo = yl;
+  a.a2_hi = yh;
+  a.a2_lo = yl;
+  a.b2_hi = xh;
+  a.b2_lo = xl;
+  a.epi = epi;
+  a.epi.oscale = 1.0f;
+  a.dec = dec;
+  constexpr size_t piece = size_t(256) * 4 * 4 * 16 * 4;
+  const int slots = device_cus() * wgs_per_cu(k_sym_split<kBF16X3, 2>, 256);
+  a.dc = plan_decomp(w, static_cast<int>(w.L.np / 256), slots, static_cast<int>(w.L.np / 32) * 2,
+                     piece);
+  const int ntail = a.dc.ntiles - a.dc.nfull;
+  k_sym_split<kBF16X3, 2><<<a.dc.nfull + ntail * a.dc.nsplit, 256, 0, st>>>(a);
+  LAUNCH_TRY();
+  if (ntail > 0) {
+    a.dec.quiet = 1;
+    k_split_tail<<<ntail * kTailStrips, 256, 0, st>>>(a);
+    LAUNCH_TRY();
+  }
+  return SP2_OK;
 }
 
 // Work decomposition of an FP32 product over nseg K segments.
@@ -614,7 +649,7 @@ sp2_status sp2_density_ex(const float* H, int64_t n, int64_t ld, int64_t n_occ,
   sp2_status s;
 
   {
-    Meta none{n, L.np, prec, o.refine, 0, 0, 0, o.max_iter, kMetaMagic};
+    Meta none{n, L.np, prec, o.refine, 0, 0, 0, o.max_iter, 0, 0, kMetaMagic};
     k_write_meta<<<1, 1, 0, st>>>(w.meta, none);
     LAUNCH_TRY();
   }
@@ -634,7 +669,7 @@ sp2_status sp2_density_ex(const float* H, int64_t n, int64_t ld, int64_t n_occ,
     if ((s = read_back(w, hm, false, st))) return s;
     if (hm->ctrl[0].nonfinite) return fail(SP2_ERR_NONFINITE, "H holds NaN or Inf");
     if (o.checkpoint_every > 0) {
-      Meta m{n, L.np, prec, o.refine, o.checkpoint_every, 0, 2, o.max_iter, kMetaMagic};
+      Meta m{n, L.np, prec, o.refine, o.checkpoint_every, 0, 2, o.max_iter, o.flags, 0, kMetaMagic};
       k_write_meta<<<1, 1, 0, st>>>(w.meta, m);
       LAUNCH_TRY();
     }
@@ -746,7 +781,7 @@ sp2_status sp2_density_ex(const float* H, int64_t n, int64_t ld, int64_t n_occ,
   }
   if (o.checkpoint_every > 0) {
     Meta m{n, L.np, prec, o.refine, o.checkpoint_every, n_iter, hm->ctrl[0].degenerate ? 0 : 1,
-           o.max_iter, kMetaMagic};
+           o.max_iter, o.flags, 0, kMetaMagic};
     k_write_meta<<<1, 1, 0, st>>>(w.meta, m);
     LAUNCH_TRY();
   }
@@ -935,6 +970,7 @@ sp2_status open_tape(void* workspace, size_t ws_bytes, hipStream_t st, WS& w, Ho
   o.refine = m.refine;
   o.checkpoint_every = m.every;
   o.max_iter = m.max_iter;
+  o.flags = m.flags;
   Layout L;
   if (!make_layout(m.n, o, L)) return fail(SP2_ERR_TAPE, "corrupt tape description");
   if (sp2_status s = check_ws(L, workspace, ws_bytes)) return s;
@@ -954,6 +990,38 @@ sp2_status sym_pair(const WS& w, const float* X, const float* Y, const float* C,
   e.alpha = alpha;
   e.beta = beta;
   return launch_f32(w, 2, A, B, e, make_decide(w, mode, layer), st);
+}
+
+// Split derivatives (SP2_FLAG_SPLIT_DERIVATIVES with BF16X3 layers): the
+// BF16X3 planes of a derivative iterate live in work slot 2 + i (hi, then lo).
+bool split_derivatives(const sp2_options& o) {
+  return (o.flags & SP2_FLAG_SPLIT_DERIVATIVES) && o.precision == SP2_BF16X3;
+}
+uint16_t* dhi(const WS& w, int i) { return reinterpret_cast<uint16_t*>(w.work(2 + i)); }
+uint16_t* dlo(const WS& w, int i) { return dhi(w, i) + w.L.np * w.L.np; }
+
+// Split form of sym_pair: out = alpha (X Y + Y X) + beta C from the planes
+// of X and Y (branch coefficients of layer `layer` in mode 2), with the
+// planes of out written to pair `op` of the derivative planes.
+sp2_status sym_pair_split(const WS& w, const uint16_t* xh, const uint16_t* xl, int yp,
+                          const float* C, float* out, int op, int mode, int layer,
+                          hipStream_t st) {
+  Epi e = make_epi(w.L);
+  e.c = C;
+  e.out = out;
+  e.split_out = split_code_of(SP2_BF16X3);
+  e.hi_out = dhi(w, op);
+  e.lo_out = dlo(w, op);
+  return launch_split_pair(w, xh, xl, dhi(w, yp), dlo(w, yp), e, make_decide(w, mode, layer), st);
+}
+
+// BF16X3 planes of an FP32 derivative iterate (np x np) into pair `op`.
+sp2_status split_derivative(const WS& w, const float* X, int op, hipStream_t st) {
+  k_split<<<ew_grid(w.L.np * w.L.np), kEwThreads, 0, st>>>(X, w.L.np, w.L.np, w.L.np, w.L.np,
+                                                            dhi(w, op), dlo(w, op),
+                                                            split_code_of(SP2_BF16X3), 1);
+  LAUNCH_TRY();
+  return SP2_OK;
 }
 
 // Derivative of the McWeeny step at S in direction D (JVP) or its adjoint
@@ -1015,11 +1083,17 @@ sp2_status jvp_run(const WS& w, const HostMirror* hm, const sp2_options& o, cons
   k_copy_scaled<<<ew_grid(L.np * L.np), kEwThreads, 0, st>>>(H1, ld, w.work(0), L.np, n, L.np, -inv, 1);
   LAUNCH_TRY();
   sp2_status s;
+  const bool sd = split_derivatives(o);
+  if (sd && (s = split_derivative(w, w.work(0), 0, st))) return s;
   if ((s = load_checkpoint(w, prec, 0, s_f32(w, prec, 0), st))) return s;
   for (int k = 0; k < nl; ++k) {
     const float* S = s_f32(w, prec, k);
-    if ((s = sym_pair(w, S, w.work(k & 1), w.work(k & 1), w.work((k + 1) & 1), 1.0f, 0.0f, 2, k, st)))
-      return s;
+    if (sd)
+      s = sym_pair_split(w, w.hi(k & 1), w.lo(k & 1), k & 1, w.work(k & 1), w.work((k + 1) & 1),
+                         (k + 1) & 1, 2, k, st);
+    else
+      s = sym_pair(w, S, w.work(k & 1), w.work(k & 1), w.work((k + 1) & 1), 1.0f, 0.0f, 2, k, st);
+    if (s) return s;
     if (k + 1 < nl || o.refine != SP2_REFINE_NONE)
       if ((s = launch_layer(w, prec, k, 2, S, s_f32(w, prec, k + 1), k & 1, (k + 1) & 1, nullptr, st,
                             &o, 0)))
@@ -1092,6 +1166,8 @@ sp2_status sp2_vjp(void* workspace, size_t ws_bytes, const float* W, int64_t ld,
       return s;
     cur = 1;
   }
+  const bool sd = split_derivatives(o);
+  if (sd && (s = split_derivative(w, w.work(cur), cur, st))) return s;
   const int nseg = (nl + k - 1) / k;
   for (int j = nseg - 1; j >= 0; --j) {
     const int c = j * k, e = std::min(c + k, nl);
@@ -1101,9 +1177,19 @@ sp2_status sp2_vjp(void* workspace, size_t ws_bytes, const float* W, int64_t ld,
                             st, &o, 0)))
         return s;
     for (int nn = e - 1; nn >= c; --nn) {
-      if ((s = sym_pair(w, w.seg(nn - c), w.work(cur), w.work(cur), w.work(1 - cur), 1.0f, 0.0f, 2, nn,
-                        st)))
-        return s;
+      if (sd) {
+        // planes of S_nn into pair 0 (the recomputation has moved on)
+        k_split<<<ew_grid(L.np * L.np), kEwThreads, 0, st>>>(w.seg(nn - c), L.np, L.np, L.np, L.np,
+                                                             w.hi(0), w.lo(0),
+                                                             split_code_of(SP2_BF16X3), 1);
+        LAUNCH_TRY();
+        s = sym_pair_split(w, w.hi(0), w.lo(0), cur, w.work(cur), w.work(1 - cur), 1 - cur, 2, nn,
+                           st);
+      } else {
+        s = sym_pair(w, w.seg(nn - c), w.work(cur), w.work(cur), w.work(1 - cur), 1.0f, 0.0f, 2, nn,
+                     st);
+      }
+      if (s) return s;
       cur = 1 - cur;
     }
   }

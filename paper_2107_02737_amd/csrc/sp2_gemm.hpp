@@ -58,6 +58,11 @@ struct SplitArgs {
   const uint16_t* a_lo;
   const uint16_t* b_hi;
   const uint16_t* b_lo;
+  // second K segment (two-segment launches: A = [A1|A2], B = [B1|B2])
+  const uint16_t* a2_hi;
+  const uint16_t* a2_lo;
+  const uint16_t* b2_hi;
+  const uint16_t* b2_lo;
   Epi epi;
   Decomp dc;
   Decide dec;
@@ -364,9 +369,10 @@ __device__ __forceinline__ void wait_ring(int later) {
   }
 }
 
-template <int KIND>
+template <int KIND, int NSEG = 1>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void k_sym_split(SplitArgs p) {
+  static_assert(NSEG == 1 || NSEG == 2, "one or two K segments");
   constexpr int BM = 256, NT = 256, BK = 16, NS = 4, MI = 4, NI = 4, TM = 128, TN = 128;
   constexpr bool kLo = KIND != kBF16X1;
   constexpr int PLANE_B = BM * BK * 2;   // bytes of one plane per K step (8 KB)
@@ -386,7 +392,7 @@ void k_sym_split(SplitArgs p) {
   const int64_t np = p.epi.np;
   const int KT = static_cast<int>(np / BK);
   int tile, ti, tj, kb, ke, tail, piece;
-  work_of(p.dc, KT / 2, tile, ti, tj, kb, ke, tail, piece);
+  work_of(p.dc, NSEG * KT / 2, tile, ti, tj, kb, ke, tail, piece);
   kb *= 2;
   ke *= 2;
   const int tid = threadIdx.x, lane = tid & (kWave - 1);
@@ -395,25 +401,39 @@ void k_sym_split(SplitArgs p) {
 
   // DMA: plane block (panel P, K step kt) starts at element (P*KT + kt)*4096;
   // this wave copies the 1 KB pieces (i*4 + w), i = 0..1, of each plane.
-  const uint16_t* ga_hi = p.a_hi + int64_t(ti) * KT * 4096;
-  const uint16_t* ga_lo = kLo ? p.a_lo + int64_t(ti) * KT * 4096 : nullptr;
-  const uint16_t* gb_hi = p.b_hi + int64_t(tj) * KT * 4096;
-  const uint16_t* gb_lo = kLo ? p.b_lo + int64_t(tj) * KT * 4096 : nullptr;
+  // K steps KT..2KT-1 of a two-segment launch read the second planes.
+  const int64_t pa = int64_t(ti) * KT * 4096, pb = int64_t(tj) * KT * 4096;
+  const uint16_t* ga_hi = p.a_hi + pa;
+  const uint16_t* ga_lo = kLo ? p.a_lo + pa : nullptr;
+  const uint16_t* gb_hi = p.b_hi + pb;
+  const uint16_t* gb_lo = kLo ? p.b_lo + pb : nullptr;
+  const uint16_t* ga2_hi = NSEG == 2 ? p.a2_hi + pa : nullptr;
+  const uint16_t* ga2_lo = NSEG == 2 && kLo ? p.a2_lo + pa : nullptr;
+  const uint16_t* gb2_hi = NSEG == 2 ? p.b2_hi + pb : nullptr;
+  const uint16_t* gb2_lo = NSEG == 2 && kLo ? p.b2_lo + pb : nullptr;
+  // Plane sources of K step KTI: gah_, gal_, gbh_, gbl_ at that K step.
+#define SP2_SRC(KTI)                                                                      \
+  const int sg_ = (NSEG == 2 && (KTI) >= KT) ? 1 : 0;                                     \
+  const int64_t kofs_ = int64_t((KTI) - sg_ * KT) * 4096;                                 \
+  const uint16_t* gah_ = (sg_ ? ga2_hi : ga_hi) + kofs_;                                  \
+  const uint16_t* gal_ = kLo ? (sg_ ? ga2_lo : ga_lo) + kofs_ : nullptr;                  \
+  const uint16_t* gbh_ = (sg_ ? gb2_hi : gb_hi) + kofs_;                                  \
+  const uint16_t* gbl_ = kLo ? (sg_ ? gb2_lo : gb_lo) + kofs_ : nullptr;
   const uint32_t lds0 = static_cast<uint32_t>(
       reinterpret_cast<uintptr_t>((__attribute__((address_space(3))) uint16_t*)(lds)));
   // Per K step every wave issues kCopies copies (2 per plane).
   constexpr int kCopies = kLo ? 8 : 4;
 #define SP2_DMA_STAGE(SLOT, KTI)                                                          \
   {                                                                                       \
-    const int64_t kofs_ = int64_t(KTI) * 4096;                                            \
+    SP2_SRC(KTI)                                                                          \
     const uint32_t m0s_ = lds0 + (SLOT) * SLOT_B + w * 1024;                              \
     _Pragma("clang loop unroll(full)") for (int i = 0; i < 2; ++i) {                      \
       const uint32_t off_ = static_cast<uint32_t>(((i * 4 + w) * 64 + lane) * 16);        \
-      dma_chunk(off_, ga_hi + kofs_, m0s_ + 0 * PLANE_B + i * 4096);                      \
-      dma_chunk(off_, gb_hi + kofs_, m0s_ + 2 * PLANE_B + i * 4096);                      \
+      dma_chunk(off_, gah_, m0s_ + 0 * PLANE_B + i * 4096);                               \
+      dma_chunk(off_, gbh_, m0s_ + 2 * PLANE_B + i * 4096);                               \
       if constexpr (kLo) {                                                                \
-        dma_chunk(off_, ga_lo + kofs_, m0s_ + 1 * PLANE_B + i * 4096);                    \
-        dma_chunk(off_, gb_lo + kofs_, m0s_ + 3 * PLANE_B + i * 4096);                    \
+        dma_chunk(off_, gal_, m0s_ + 1 * PLANE_B + i * 4096);                             \
+        dma_chunk(off_, gbl_, m0s_ + 3 * PLANE_B + i * 4096);                             \
       }                                                                                   \
     }                                                                                     \
   }
@@ -469,7 +489,7 @@ void k_sym_split(SplitArgs p) {
   // while its matrix pipe is busy.  sched_barrier keeps the order as written.
 #define SP2_MFMA1_DMA(X, Y, SLOT, KTI)                                                    \
   {                                                                                       \
-    const int64_t kofs_ = int64_t(KTI) * 4096;                                            \
+    SP2_SRC(KTI)                                                                          \
     const uint32_t m0s_ = lds0 + (SLOT) * SLOT_B + w * 1024;                              \
     _Pragma("clang loop unroll(full)") for (int mi = 0; mi < MI; ++mi)                    \
     _Pragma("clang loop unroll(full)") for (int ni = 0; ni < NI; ++ni) {                  \
@@ -484,9 +504,9 @@ void k_sym_split(SplitArgs p) {
       if (j_ % kEvery_ == kEvery_ - 1) {                                                  \
         const int c_ = j_ / kEvery_, i_ = c_ & 1, pl_ = c_ >> 1;                          \
         const uint32_t off_ = static_cast<uint32_t>(((i_ * 4 + w) * 64 + lane) * 16);     \
-        const uint16_t* g_ = pl_ == 0 ? ga_hi : pl_ == 1 ? gb_hi : pl_ == 2 ? ga_lo : gb_lo; \
+        const uint16_t* g_ = pl_ == 0 ? gah_ : pl_ == 1 ? gbh_ : pl_ == 2 ? gal_ : gbl_;  \
         const int lp_ = pl_ == 0 ? 0 : pl_ == 1 ? 2 : pl_ == 2 ? 1 : 3;                   \
-        dma_chunk(off_, g_ + kofs_, m0s_ + lp_ * PLANE_B + i_ * 4096);                    \
+        dma_chunk(off_, g_, m0s_ + lp_ * PLANE_B + i_ * 4096);                            \
       }                                                                                   \
       __builtin_amdgcn_sched_barrier(0);                                                  \
     }                                                                                     \
@@ -530,6 +550,7 @@ void k_sym_split(SplitArgs p) {
   }
   wait_vmem_all();
   __syncthreads();
+#undef SP2_SRC
 #undef SP2_DMA_STAGE
 #undef SP2_FRAG
 #undef SP2_MFMA1

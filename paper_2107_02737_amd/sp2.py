@@ -28,17 +28,20 @@ def _as_matrix(H, symmetrize):
 
 def density(H, n_occ, tol=1e-5, precision="bf16x3", refine="fp32", max_iter=100, stop_rule=1,
             stall_gate=1.0, checkpoint_every=0, symmetrize=False, return_info=False,
-            workspace=None, time_layers=False, bound_steps=0, bound_seed=0):
+            workspace=None, time_layers=False, bound_steps=0, bound_seed=0,
+            split_derivatives=False):
     """Density matrix of the symmetric ``H`` with ``n_occ`` occupied states.
 
     Returns ``P`` (FP32, same device), or ``(P, info)`` with ``info`` holding
     ``n_iter``, ``converged``, ``eps_min``, ``eps_max``, ``trace``,
     ``idem_err``, ``status`` and the ``branches`` string (1 = S^2).
+    ``split_derivatives`` (BF16X3 with a tape) runs the JVP/VJP layer
+    products in BF16X3 instead of FP32.
     """
     H = _as_matrix(H, symmetrize)
     n = H.shape[0]
     opt = _lib.make_options(precision, refine, max_iter, stop_rule, checkpoint_every, tol,
-                            stall_gate, time_layers, bound_steps, bound_seed)
+                            stall_gate, time_layers, bound_steps, bound_seed, split_derivatives)
     if workspace is None:
         workspace = _lib.allocate_workspace(n, opt, H.device)
     P = torch.empty_like(H)

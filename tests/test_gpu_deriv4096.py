@@ -64,14 +64,14 @@ def _sampled(t, g, prefix):
     return float(np.linalg.norm(d) / np.linalg.norm(ref)), math.sqrt(n * float(np.mean(pd * pd)))
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
-def test_deriv_4096(setup, precision):
+@pytest.mark.parametrize("precision,split", [("fp32", False), ("bf16x3", False), ("bf16x3", True)])
+def test_deriv_4096(setup, precision, split):
     import torch
     pk, g, dev = setup
     n, n_occ = int(g["n"]), int(g["n_occ"])
-    banner(f"water N={n} derivatives {precision} refine=fp32 checkpoint 4")
+    banner(f"water N={n} derivatives {precision} refine=fp32 checkpoint 4 split_derivatives={split}")
     P, info = pk.density(dev["H"], n_occ, precision=precision, refine="fp32", checkpoint_every=4,
-                         return_info=True)
+                         return_info=True, split_derivatives=split)
     assert info["converged"] == 1
     assert info["eps_min"] == pytest.approx(float(g["eps_min"]), rel=1e-12)
     assert info["eps_max"] == pytest.approx(float(g["eps_max"]), rel=1e-12)

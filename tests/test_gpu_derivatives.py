@@ -15,9 +15,12 @@ compared with the FP64 derivative of that same network.
 
 Tolerances: relative Frobenius error <= 1e-4 (FP32 forward) and <= 1e-3
 (16-bit split forward, whose iterates themselves differ from FP64 by
-~1e-5) against the FP64 derivative of the same network; the same bounds
-against perturbation theory (the 1e-5 stop leaves the network ~1e-6 from
-the step function; the rounding of the iterates adds the rest)."""
+~1e-5, with FP32 or with BF16X3 derivative products) against the FP64
+derivative of the same network.  Against perturbation theory the same bounds
+(the 1e-5 stop leaves the network ~1e-6 from the step function; the rounding
+of the iterates adds the rest), or, where larger, the oracle network's own
+distance from it plus the tolerance (an unrefined split network stops at its
+rounding floor, ~1e-3 from the step function's response)."""
 
 import numpy as np
 import pytest
@@ -78,17 +81,18 @@ def _hamiltonian(name):
 
 
 @pytest.mark.parametrize("name,n,n_occ", CASES)
-@pytest.mark.parametrize("precision,refine,tol",
-                         [("fp32", "none", 1e-4), ("fp32", "fp32", 1e-4),
-                          ("bf16x3", "fp32", 1e-3), ("fp16x3", "none", 1e-3)])
-def test_jvp_and_vjp_match_oracle(pk, name, n, n_occ, precision, refine, tol):
-    banner(f"jvp/vjp {name} N={n} {precision} refine={refine}")
+@pytest.mark.parametrize("precision,refine,tol,split",
+                         [("fp32", "none", 1e-4, False), ("fp32", "fp32", 1e-4, False),
+                          ("bf16x3", "fp32", 1e-3, False), ("fp16x3", "none", 1e-3, False),
+                          ("bf16x3", "fp32", 1e-3, True), ("bf16x3", "none", 1e-3, True)])
+def test_jvp_and_vjp_match_oracle(pk, name, n, n_occ, precision, refine, tol, split):
+    banner(f"jvp/vjp {name} N={n} {precision} refine={refine} split_derivatives={split}")
     h32 = _hamiltonian(name)
     h1 = symmetric_normal(n, 2, std=1e-3).astype(np.float32)
     w = symmetric_normal(n, 1).astype(np.float32)
     H = to_dev(h32)
     P, info = pk.density(H, n_occ, precision=precision, refine=refine, checkpoint_every=3,
-                         return_info=True)
+                         return_info=True, split_derivatives=split)
     h64 = h32.astype(np.float64)
     rec, flips = validated_record(h64, n_occ, info, precision, refine)
     P1 = to_dev(np.zeros((n, n)))
@@ -100,7 +104,12 @@ def test_jvp_and_vjp_match_oracle(pk, name, n, n_occ, precision, refine, tol):
     j_dm = oracle.dmpt_response(h64, n_occ, h1.astype(np.float64))
     g_dm = oracle.dmpt_response(h64, n_occ, w.astype(np.float64))
     j, g = to_host(P1), to_host(G)
+    # against perturbation theory: the network itself (its FP64 derivative,
+    # j_ref / g_ref) is this far from the step function's response -- near
+    # 1e-3 for a split network stopped at its rounding floor without
+    # refinement -- and the GPU may add its own rounding on top
     dm_tol = 1e-4 if precision == "fp32" else 1e-3
+    dm_tol = max(dm_tol, max(_rel(j_ref, j_dm), _rel(g_ref, g_dm)) + tol)
     print(f"  n_iter={info['n_iter']} flips={flips} jvp rel={_rel(j, j_ref):.2e} "
           f"vjp rel={_rel(g, g_ref):.2e} vs DMPT: jvp {_rel(j, j_dm):.2e} vjp {_rel(g, g_dm):.2e}",
           flush=True)

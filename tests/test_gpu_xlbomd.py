@@ -34,14 +34,15 @@ def _dvec(a, dtype=None):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=dtype or np.float64)).to("cuda")
 
 
-def _setup(pk, m, precision, refine="fp32", n_pad=None, seed=0, n_occ=None, validate=True):
+def _setup(pk, m, precision, refine="fp32", n_pad=None, seed=0, n_occ=None, validate=True,
+           split=False):
     mod = water_charge_model(m, seed=seed, n_pad=n_pad)
     charges = random_charges(3 * m, seed=5)
     h = charge_shifted_hamiltonian(mod["h0"], mod["atom_ptr"], mod["gamma"], charges)
     h32 = h.astype(np.float32)
     n_occ = mod["n_occ"] if n_occ is None else n_occ
     P, info = pk.density(to_dev(h32), n_occ, precision=precision, refine=refine,
-                         checkpoint_every=4, return_info=True)
+                         checkpoint_every=4, return_info=True, split_derivatives=split)
     h64 = h32.astype(np.float64)
     rec = None
     if validate and 0 < n_occ < h.shape[0]:
@@ -78,10 +79,11 @@ def test_mulliken_residual_matches_oracle(pk, n_pad):
     assert np.abs(to_host(q) - q_exact).max() <= 1e-4
 
 
-@pytest.mark.parametrize("precision,tol", [("fp32", 1e-4), ("bf16x3", 1e-3)])
-def test_response_matches_oracle(pk, precision, tol):
-    banner(f"xl response M=50 {precision}")
-    mod, charges, h64, n_occ, P, info, rec, dev = _setup(pk, 50, precision)
+@pytest.mark.parametrize("precision,tol,split", [("fp32", 1e-4, False), ("bf16x3", 1e-3, False),
+                                                 ("bf16x3", 1e-3, True)])
+def test_response_matches_oracle(pk, precision, tol, split):
+    banner(f"xl response M=50 {precision} split_derivatives={split}")
+    mod, charges, h64, n_occ, P, info, rec, dev = _setup(pk, 50, precision, split=split)
     na = charges.size
     v = np.random.default_rng(11).standard_normal(na)
     scratch = pk.allocate_xl_scratch(h64.shape[0], na, 1)
@@ -156,9 +158,9 @@ def test_degenerate_cases(pk):
 
 def test_residual_property_at_4096(pk):
     # water, 682 molecules + 4 padding orbitals (N = 4096, 2046 atoms)
-    banner("xl kernel N=4096 bf16x3 rank=4 + independent J kf")
+    banner("xl kernel N=4096 bf16x3 (split derivatives) rank=4 + independent J kf")
     mod, charges, h64, n_occ, P, info, rec, dev = _setup(pk, 682, "bf16x3", n_pad=4096,
-                                                          validate=False)
+                                                          validate=False, split=True)
     na = charges.size
     f = pk.sp2_mulliken(P, dev["ptr"], dev["z"], sub=dev["charges"])
     scratch = pk.allocate_xl_scratch(4096, na, 4)
