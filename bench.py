@@ -104,7 +104,8 @@ def trajectory(steps, precision, refine):
     N = 16384, n_occ = 10920; H(t) = H0 + fl32(a_t H_p), a_t = 0.01 sin(0.1 t),
     formed on the device; every step an independent split-precision solve,
     the last one with the tape (checkpoint every 4th iterate) and the adjoint
-    d Tr(W P)/dH.  Solve times from HIP events on the solve's stream."""
+    d Tr(W P)/dH, with FP32 and (BF16X3 layers) with split derivative
+    products.  Solve times from HIP events on the solve's stream."""
     import torch
 
     import paper_2107_02737_amd as pk
@@ -122,7 +123,7 @@ def trajectory(steps, precision, refine):
     P = torch.empty_like(H0)
     times, drift_tr, drift_idem, layers = [], [], [], []
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    adj_ms = None
+    adj_ms = adj_split_ms = adj_split_rel = None
     for t in range(steps):
         H = torch.add(H0, torch.mul(Hp, float(np.float32(0.01 * math.sin(0.1 * t)))))
         last = t == steps - 1
@@ -142,6 +143,19 @@ def trajectory(steps, precision, refine):
             ev1.record()
             torch.cuda.synchronize()
             adj_ms = ev0.elapsed_time(ev1)
+            if precision == "bf16x3":
+                # the same adjoint with the layer maps in BF16X3 (taped again with the option)
+                pk.sp2_density_ex(H, n_occ, pk.make_options(precision, refine, checkpoint_every=4,
+                                                            split_derivatives=True), P, ws)
+                G2 = torch.empty_like(P)
+                ev0.record()
+                pk.sp2_vjp(ws, W, G2)
+                ev1.record()
+                torch.cuda.synchronize()
+                adj_split_ms = ev0.elapsed_time(ev1)
+                adj_split_rel = float(torch.linalg.norm((G2 - G).double()).item()
+                                      / torch.linalg.norm(G.double()).item())
+                del G2
         if t % 10 == 0 or last:
             print(f"# t={t} status={st} n_iter={info.n_iter} {times[-1]:.1f} ms "
                   f"TrP-n={drift_tr[-1]:.2e} idem={drift_idem[-1]:.2e}", file=sys.stderr, flush=True)
@@ -155,6 +169,8 @@ def trajectory(steps, precision, refine):
         "trace_drift": [float(min(drift_tr)), float(max(drift_tr))],
         "idempotency": [float(min(drift_idem)), float(max(drift_idem))],
         "adjoint_ms_last_step": adj_ms,
+        "adjoint_ms_last_step_split_derivatives": adj_split_ms,
+        "adjoint_split_vs_fp32_rel": adj_split_rel,
         "solve_ms_last_step_with_tape": float(tt[-1])}), flush=True)
 
 
