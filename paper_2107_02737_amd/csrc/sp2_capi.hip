@@ -119,7 +119,9 @@ bool make_layout(int64_t n, const sp2_options& o, Layout& L) {
   // k so that the layout does not depend on the bound option (the tape
   // reader rebuilds it)
   L.off_lzvec = take(size_t(kLzMaxSteps + 3) * size_t(n) * 8);
-  L.off_lzpart = take(size_t(L.lz_chunks) * (2 * kLzCoef + 1) * 8);
+  // first-pass dot partials per matvec work-group, second-pass partials and
+  // squared-norm partials per 256-row chunk
+  L.off_lzpart = take((size_t(L.lz_blocks + L.lz_chunks) * kLzCoef + size_t(L.lz_chunks)) * 8);
   L.slot_bytes = size_t(L.np) * size_t(L.np) * 4;
   L.every = o.checkpoint_every;
   // slots 0-3: S (FP32), two hi/lo plane pairs (or FP32 ping-pong), S^2 for
@@ -175,8 +177,9 @@ sp2_status refine_bounds(const WS& w, const float* H, int64_t n, int64_t ld, int
   const int nc = w.L.lz_chunks;
   double* V = w.lzv;
   double* wb[2] = {w.lzv + int64_t(kLzMaxSteps + 1) * n, w.lzv + int64_t(kLzMaxSteps + 2) * n};
-  double* p1 = w.lzpart;                  // first-pass dot partials
-  double* p2 = p1 + size_t(nc) * kLzCoef;  // second-pass dot partials
+  const int nb = w.L.lz_blocks;
+  double* p1 = w.lzpart;                  // first-pass dot partials (per matvec work-group)
+  double* p2 = p1 + size_t(nb) * kLzCoef;  // second-pass dot partials
   double* pn = p2 + size_t(nc) * kLzCoef;  // squared-norm partials
   steps = static_cast<int>(std::min<int64_t>(steps, n));
   k_lz_start<<<1, kLzThreads, 0, st>>>(V, n, static_cast<uint64_t>(static_cast<uint32_t>(seed)),
@@ -184,11 +187,9 @@ sp2_status refine_bounds(const WS& w, const float* H, int64_t n, int64_t ld, int
   LAUNCH_TRY();
   for (int j = 0; j < steps; ++j) {
     double* wj = wb[j & 1];
-    k_lz_matvec<<<w.L.lz_blocks, 256, 0, st>>>(H, n, ld, V, wb[(j + 1) & 1], wj, pn, nc, w.lz, j);
+    k_lz_matvec<<<nb, 256, 0, st>>>(H, n, ld, V, wb[(j + 1) & 1], wj, pn, nc, p1, w.lz, j);
     LAUNCH_TRY();
-    k_lz_dots<<<nc, kLzChunk, 0, st>>>(V, wj, n, j, p1, w.lz);
-    LAUNCH_TRY();
-    k_lz_apply<<<nc, kLzChunk, 0, st>>>(V, wj, n, j, p1, nc, p2, w.lz, 0);
+    k_lz_apply<<<nc, kLzChunk, 0, st>>>(V, wj, n, j, p1, nb, p2, w.lz, 0);
     LAUNCH_TRY();
     k_lz_apply<<<nc, kLzChunk, 0, st>>>(V, wj, n, j, p2, nc, pn, w.lz, 1);
     LAUNCH_TRY();

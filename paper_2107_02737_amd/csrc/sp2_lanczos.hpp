@@ -51,12 +51,47 @@ __device__ __forceinline__ double block_sum1(double a, double* red) {
   return s;
 }
 
-// Sum of the per-chunk partials of one quantity, chunks in order (every
-// work-group that needs it computes the same value).
-__device__ __forceinline__ double chunk_sum(const double* part, int nchunks, int stride, int idx) {
+// Sums of the per-chunk partials part[b * stride + i] over the chunks b for
+// i < count (count * 4 <= blockDim.x), into out[i] (LDS), in a fixed order:
+// thread (i, g) adds chunks g, g + 4, g + 8, ... in turn, then the four
+// results are added in order g = 0..3.  Every work-group that needs a sum
+// computes it identically.  The partials reach the LDS buffer (cap doubles)
+// a batch of chunks at a time, each thread keeping eight loads in flight.
+__device__ __forceinline__ void ordered_sums(const double* __restrict__ part, int nchunks,
+                                             int stride, int count, double* buf, int cap,
+                                             double* out) {
+  constexpr int G = 4, U = 8;
+  const int batch = (cap / count) / G * G;
+  const int i = threadIdx.x / G, g = threadIdx.x % G;
   double s = 0.0;
-  for (int b = 0; b < nchunks; ++b) s += part[b * stride + idx];
-  return s;
+  for (int b0 = 0; b0 < nchunks; b0 += batch) {
+    const int nb = min(batch, nchunks - b0), total = nb * count;
+    for (int q0 = threadIdx.x; q0 < total; q0 += U * blockDim.x) {
+      double v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int q = q0 + u * blockDim.x;
+        v[u] = q < total ? part[int64_t(b0 + q / count) * stride + q % count] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int q = q0 + u * blockDim.x;
+        if (q < total) buf[(q % count) * batch + q / count] = v[u];
+      }
+    }
+    __syncthreads();
+    if (i < count)
+      for (int b = g; b < nb; b += G) s += buf[i * batch + b];
+    __syncthreads();
+  }
+  // the four interleaved partial sums of coefficient i, in order
+  if (i < count) buf[i * G + g] = s;
+  __syncthreads();
+  if (threadIdx.x < count) {
+    const double* r = buf + threadIdx.x * G;
+    out[threadIdx.x] = ((r[0] + r[1]) + r[2]) + r[3];
+  }
+  __syncthreads();
 }
 
 // V_0 = u / |u|, u_i = (z_i >> 11) 2^-53 - 1/2; state reset.  V holds the
@@ -83,18 +118,24 @@ __global__ __launch_bounds__(kLzThreads) void k_lz_start(double* __restrict__ V,
 // consecutive rows so that every v load serves 4 rows.  For j >= 1, v_j is
 // formed on the fly as win * (1 / beta_{j-1}), beta_{j-1} = sqrt of the
 // summed squared-norm partials of step j-1, and stored into V row j by the
-// work-group owning each row; block 0 records beta_{j-1}.
+// work-group owning each row; block 0 records beta_{j-1}.  Each work-group
+// also writes the partial dot products of its rows of wout with
+// v_0 .. v_j (the first Gram-Schmidt pass): dot_part[block * kLzCoef + i].
 __global__ __launch_bounds__(256) void k_lz_matvec(const float* __restrict__ H, int64_t n,
                                                    int64_t ld, double* __restrict__ V,
                                                    const double* __restrict__ win,
                                                    double* __restrict__ wout,
                                                    const double* __restrict__ norm_part,
-                                                   int nchunks, LzState* st, int j) {
+                                                   int nchunks, double* __restrict__ dot_part,
+                                                   LzState* st, int j) {
+  __shared__ double sbuf[256];
+  __shared__ double snorm;
   if (st->broke) return;
   const double* v = V + int64_t(j) * n;
   double inv = 1.0;
   if (j > 0) {
-    const double beta = sqrt(chunk_sum(norm_part, nchunks, 1, 0));
+    ordered_sums(norm_part, nchunks, 1, 1, sbuf, 256, &snorm);
+    const double beta = sqrt(snorm);
     if (!(beta > 1e-300)) {
       if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->beta[j - 1] = beta;
@@ -114,6 +155,7 @@ __global__ __launch_bounds__(256) void k_lz_matvec(const float* __restrict__ H, 
   int64_t c_done = 0;
   if (vec) {
     const int64_t n4 = n & ~int64_t(3);
+#pragma unroll 2
     for (int64_t c = 4 * lane; c < n4; c += 4 * kWave) {
       const double v0 = v[c] * inv, v1 = v[c + 1] * inv, v2 = v[c + 2] * inv, v3 = v[c + 3] * inv;
 #pragma unroll
@@ -140,14 +182,37 @@ __global__ __launch_bounds__(256) void k_lz_matvec(const float* __restrict__ H, 
       if (row < n) acc[rr] = fma(static_cast<double>(H[row * ld + c]), vc, acc[rr]);
     }
   }
+  double ws[kLzRowsPerWave];
 #pragma unroll
   for (int rr = 0; rr < kLzRowsPerWave; ++rr) {
     const double s = wave_sum(acc[rr]);
     const int64_t row = r0 + rr;
+    ws[rr] = row < n ? s : 0.0;
     if (lane == 0 && row < n) {
       wout[row] = s;
       if (j > 0) V[int64_t(j) * n + row] = win[row] * inv;
     }
+  }
+  // lane i: this wave's part of v_i . wout (i <= j < 64), then the waves in order
+  __shared__ double dred[256 / kWave][kWave];
+  double d = 0.0;
+  if (lane <= j) {
+#pragma unroll
+    for (int rr = 0; rr < kLzRowsPerWave; ++rr) {
+      const int64_t row = r0 + rr;
+      if (row < n) {
+        const double vi = lane < j ? V[int64_t(lane) * n + row] : (j > 0 ? win[row] * inv : V[row]);
+        d = fma(vi, ws[rr], d);
+      }
+    }
+  }
+  dred[wv][lane] = d;
+  __syncthreads();
+  if (threadIdx.x <= j) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < 256 / kWave; ++q) t += dred[q][threadIdx.x];
+    dot_part[int64_t(blockIdx.x) * kLzCoef + threadIdx.x] = t;
   }
 }
 
@@ -169,17 +234,6 @@ __device__ __forceinline__ void chunk_dots(const double* V, double wr, int64_t r
   }
 }
 
-// First Gram-Schmidt pass, dots: part = chunk partials of V^T w.
-__global__ __launch_bounds__(kLzChunk) void k_lz_dots(const double* __restrict__ V,
-                                                      const double* __restrict__ w, int64_t n,
-                                                      int j, double* __restrict__ part,
-                                                      const LzState* st) {
-  __shared__ double red[(kLzChunk / kWave) * kLzCoef];
-  if (st->broke) return;
-  const int64_t row = int64_t(blockIdx.x) * kLzChunk + threadIdx.x;
-  chunk_dots(V, row < n ? w[row] : 0.0, row, n, j, part, red);
-}
-
 // A Gram-Schmidt update: c = sum of the chunk partials, w -= V c on this
 // chunk; then either the partial dots of the second pass (last = 0; block 0
 // records alpha_j = c_j of the first pass) or the partial |w|^2 (last = 1).
@@ -188,12 +242,12 @@ __global__ __launch_bounds__(kLzChunk) void k_lz_apply(const double* __restrict_
                                                        const double* __restrict__ part_in,
                                                        int nchunks, double* __restrict__ part_out,
                                                        LzState* st, int last) {
+  constexpr int kBuf = 64 * kLzCoef;
   __shared__ double red[(kLzChunk / kWave) * kLzCoef];
   __shared__ double coef[kLzCoef];
+  __shared__ double buf[kBuf];
   if (st->broke) return;
-  for (int i = threadIdx.x; i <= j; i += kLzChunk)
-    coef[i] = chunk_sum(part_in, nchunks, kLzCoef, i);
-  __syncthreads();
+  ordered_sums(part_in, nchunks, kLzCoef, j + 1, buf, kBuf, coef);
   const int64_t row = int64_t(blockIdx.x) * kLzChunk + threadIdx.x;
   double wr = 0.0;
   if (row < n) {
@@ -325,13 +379,23 @@ __global__ __launch_bounds__(64) void k_lz_bounds(LzState* st, Ctrl* ctrl, doubl
   __shared__ double x[kLzMaxSteps], dl[kLzMaxSteps], dd[kLzMaxSteps], du[kLzMaxSteps],
       du2[kLzMaxSteps];
   __shared__ int swp[kLzMaxSteps];
+  __shared__ double sa[kLzMaxSteps], sb[kLzMaxSteps], sbuf[256], snorm;
   const int k = st->steps;
   if (k <= 0) return;
-  if (threadIdx.x == 0 && !st->broke) st->beta[k - 1] = sqrt(chunk_sum(norm_part, nchunks, 1, 0));
+  if (!st->broke) {
+    ordered_sums(norm_part, nchunks, 1, 1, sbuf, 256, &snorm);
+    if (threadIdx.x == 0) st->beta[k - 1] = sqrt(snorm);
+  }
   __syncthreads();
   if (ctrl->nonfinite || ctrl->degenerate) return;
-  const double* a = st->alpha;
-  const double* b = st->beta;
+  // T in LDS: the bisection reads it many times
+  for (int i = threadIdx.x; i < k; i += blockDim.x) {
+    sa[i] = st->alpha[i];
+    sb[i] = st->beta[i];
+  }
+  __syncthreads();
+  const double* a = sa;
+  const double* b = sb;
   double lo = INFINITY, hi = -INFINITY, scale = 0.0;
   for (int i = 0; i < k; ++i) {
     const double off = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i + 1 < k ? fabs(b[i]) : 0.0);
