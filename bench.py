@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--no-fp32-compare", action="store_true")
     ap.add_argument("--bound-steps", type=int, default=0,
                     help="Lanczos steps tightening the Gershgorin bounds (0: Gershgorin only)")
-    ap.add_argument("--compare-bound-steps", type=int, default=32,
+    ap.add_argument("--compare-bound-steps", type=int, default=24,
                     help="also time solves with this many Lanczos bound steps (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-layers", type=int, default=4,
