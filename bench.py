@@ -398,6 +398,15 @@ def main():
             "n_iter": linfo[-1]["n_iter"], "eps": [linfo[-1]["eps_min"], linfo[-1]["eps_max"]],
             "fro_over_sqrt_n_est": lerr["fro_over_sqrt_n_est"]}
         del Pl
+    if args.refine == "fp32" and not args.no_fp32_compare:
+        # the FP32-equivalent mode: FP16x3 layers, FP32 refinement, 32 Lanczos bound steps
+        Pe, einfo, esec = timed_solves(pk, H, n_occ, "fp16x3", "fp32", 5, 1, True, 32)
+        eerr = sampled_error(Pe, gold)
+        out["fp32_equivalent"] = {"precision": "fp16x3", "refine": "fp32", "bound_steps": 32,
+                                  "solves_per_s": 1.0 / esec, "n_iter": einfo[-1]["n_iter"],
+                                  "fro_over_sqrt_n_est": eerr["fro_over_sqrt_n_est"],
+                                  "tolerance": 1e-6}
+        del Pe
     if args.refine == "fp32":
         # the same solve with the FP32-equivalent split refinement (FP16x3 products)
         Ps, sinfo, ssec = timed_solves(pk, H, n_occ, args.precision, "split", 5, 1, True,

@@ -18,6 +18,11 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "wat
 # 3x the FP32-storage emulation of a 256-molecule box of the same model
 # (the error is set by the mapped gap, which the larger box shares).
 TOL = {"bf16x3": 5e-5, "fp16x3": 3e-6, "fp32": 3e-6}
+# The stated bound for the FP32-equivalent mode (split hi/lo layers with the
+# FP32 refinement): ||P - P_ref||_F / sqrt(N) <= 1e-6.  FP16x3 layers reach it
+# once the Lanczos bounds widen the mapped gap (32 steps: 8.7e-7).
+FP32_EQUIVALENT = ("fp16x3", 32)
+FP32_EQUIVALENT_TOL = 1e-6
 
 
 @pytest.fixture(scope="module")
@@ -34,7 +39,7 @@ def setup():
 
 
 @pytest.mark.parametrize("precision,bound_steps", [("bf16x3", 0), ("fp16x3", 0), ("fp32", 0),
-                                                   ("bf16x3", 32), ("fp32", 32)])
+                                                   ("bf16x3", 32), ("fp32", 32), FP32_EQUIVALENT])
 def test_water_6144(setup, precision, bound_steps):
     import torch
     pk, gold, H = setup
@@ -60,6 +65,7 @@ def test_water_6144(setup, precision, bound_steps):
           f"diag rms={np.sqrt(np.mean(diag ** 2)):.2e} idem={idem:.2e} "
           f"trace_err={abs(info['trace'] - n_occ):.2e}", flush=True)
     assert torch.equal(P, P.T)
-    assert est <= TOL[precision]
+    assert est <= (FP32_EQUIVALENT_TOL if (precision, bound_steps) == FP32_EQUIVALENT
+                   else TOL[precision])
     assert abs(info["trace"] - n_occ) < 0.05
     assert idem < 1e-4
