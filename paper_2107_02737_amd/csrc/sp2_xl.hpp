@@ -172,7 +172,7 @@ __global__ __launch_bounds__(kXlThreads) void k_xl_init(const double* __restrict
 // Step k with the response fk = K0 J v_k: extend the QR of the responses
 // (q_k, column k of R), take the component t_k of the residual along q_k,
 // and unless `last`, the next basis vector v_{k+1} = fk orthonormalised
-// against v_1..v_k (stop when it vanishes).  w1, w2: scratch vectors.
+// against v_1..v_k (stop when it vanishes).  w1: scratch vector.
 __global__ __launch_bounds__(kXlThreads) void k_xl_step(const double* __restrict__ fk, int k,
                                                         int last, int64_t na,
                                                         double* __restrict__ V,
