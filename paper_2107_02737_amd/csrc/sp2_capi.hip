@@ -187,14 +187,14 @@ sp2_status refine_bounds(const WS& w, const float* H, int64_t n, int64_t ld, int
   LAUNCH_TRY();
   for (int j = 0; j < steps; ++j) {
     double* wj = wb[j & 1];
-    k_lz_matvec<<<nb, 256, 0, st>>>(H, n, ld, V, wb[(j + 1) & 1], wj, pn, nc, p1, w.lz, j);
+    k_lz_matvec<<<nb, kLzMvThreads, 0, st>>>(H, n, ld, V, wb[(j + 1) & 1], wj, pn, nc, p1, w.lz, j);
     LAUNCH_TRY();
     k_lz_apply<<<nc, kLzChunk, 0, st>>>(V, wj, n, j, p1, nb, p2, w.lz, 0);
     LAUNCH_TRY();
     k_lz_apply<<<nc, kLzChunk, 0, st>>>(V, wj, n, j, p2, nc, pn, w.lz, 1);
     LAUNCH_TRY();
   }
-  k_lz_bounds<<<1, 64, 0, st>>>(w.lz, w.ctrl, kLzMargin, pn, nc);
+  k_lz_bounds<<<1, 2 * kWave, 0, st>>>(w.lz, w.ctrl, kLzMargin, pn, nc);
   LAUNCH_TRY();
   return SP2_OK;
 }

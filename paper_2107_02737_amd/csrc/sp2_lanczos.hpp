@@ -17,8 +17,9 @@ namespace sp2 {
 
 constexpr int kLzMaxSteps = 64;
 constexpr int kLzThreads = 1024;     // start kernel
-constexpr int kLzRowsPerWave = 4;
-constexpr int kLzRowsPerBlock = 4 * kLzRowsPerWave;
+constexpr int kLzMvThreads = 512;    // matrix-vector work-group: 8 waves
+constexpr int kLzRowsPerWave = 2;
+constexpr int kLzRowsPerBlock = (kLzMvThreads / 64) * kLzRowsPerWave;
 constexpr int kLzChunk = 256;        // rows per work-group of the vector kernels
 constexpr int kLzCoef = kLzMaxSteps + 1;
 constexpr double kLzMargin = 0.01;   // relative widening of the Ritz interval
@@ -114,14 +115,15 @@ __global__ __launch_bounds__(kLzThreads) void k_lz_start(double* __restrict__ V,
   }
 }
 
-// Step j: wout = H v_j (FP32 H, FP64 products and sums), each wave taking 4
-// consecutive rows so that every v load serves 4 rows.  For j >= 1, v_j is
+// Step j: wout = H v_j (FP32 H, FP64 products and sums), each wave taking 2
+// consecutive rows (every v load serves both; many waves keep the H stream
+// at full bandwidth), 8 waves per work-group.  For j >= 1, v_j is
 // formed on the fly as win * (1 / beta_{j-1}), beta_{j-1} = sqrt of the
 // summed squared-norm partials of step j-1, and stored into V row j by the
 // work-group owning each row; block 0 records beta_{j-1}.  Each work-group
 // also writes the partial dot products of its rows of wout with
 // v_0 .. v_j (the first Gram-Schmidt pass): dot_part[block * kLzCoef + i].
-__global__ __launch_bounds__(256) void k_lz_matvec(const float* __restrict__ H, int64_t n,
+__global__ __launch_bounds__(kLzMvThreads) void k_lz_matvec(const float* __restrict__ H, int64_t n,
                                                    int64_t ld, double* __restrict__ V,
                                                    const double* __restrict__ win,
                                                    double* __restrict__ wout,
@@ -150,7 +152,9 @@ __global__ __launch_bounds__(256) void k_lz_matvec(const float* __restrict__ H, 
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = threadIdx.x / kWave;
   const int64_t r0 = int64_t(blockIdx.x) * kLzRowsPerBlock + wv * kLzRowsPerWave;
-  double acc[kLzRowsPerWave] = {0.0, 0.0, 0.0, 0.0};
+  double acc[kLzRowsPerWave];
+#pragma unroll
+  for (int rr = 0; rr < kLzRowsPerWave; ++rr) acc[rr] = 0.0;
   const bool vec = (ld % 4 == 0) && ((reinterpret_cast<uintptr_t>(H) & 15) == 0);
   int64_t c_done = 0;
   if (vec) {
@@ -194,7 +198,7 @@ __global__ __launch_bounds__(256) void k_lz_matvec(const float* __restrict__ H, 
     }
   }
   // lane i: this wave's part of v_i . wout (i <= j < 64), then the waves in order
-  __shared__ double dred[256 / kWave][kWave];
+  __shared__ double dred[kLzMvThreads / kWave][kWave];
   double d = 0.0;
   if (lane <= j) {
 #pragma unroll
@@ -211,7 +215,7 @@ __global__ __launch_bounds__(256) void k_lz_matvec(const float* __restrict__ H, 
   if (threadIdx.x <= j) {
     double t = 0.0;
 #pragma unroll
-    for (int q = 0; q < 256 / kWave; ++q) t += dred[q][threadIdx.x];
+    for (int q = 0; q < kLzMvThreads / kWave; ++q) t += dred[q][threadIdx.x];
     dot_part[int64_t(blockIdx.x) * kLzCoef + threadIdx.x] = t;
   }
 }
@@ -373,13 +377,15 @@ __device__ inline double tridiag_last_component(const double* a, const double* b
 // One thread does the O(k^2) work.
 // The last beta (coupling to the next, unused vector) comes from the norm
 // partials of the last step unless the recurrence broke down.
-__global__ __launch_bounds__(64) void k_lz_bounds(LzState* st, Ctrl* ctrl, double margin,
-                                                  const double* __restrict__ norm_part,
-                                                  int nchunks) {
-  __shared__ double x[kLzMaxSteps], dl[kLzMaxSteps], dd[kLzMaxSteps], du[kLzMaxSteps],
-      du2[kLzMaxSteps];
-  __shared__ int swp[kLzMaxSteps];
-  __shared__ double sa[kLzMaxSteps], sb[kLzMaxSteps], sbuf[256], snorm;
+// Two waves: wave 0 finds the smallest Ritz value and its residual, wave 1
+// the largest, at the same time; thread 0 then widens and clips.
+__global__ __launch_bounds__(2 * kWave) void k_lz_bounds(LzState* st, Ctrl* ctrl, double margin,
+                                                         const double* __restrict__ norm_part,
+                                                         int nchunks) {
+  __shared__ double x[2][kLzMaxSteps], dl[2][kLzMaxSteps], dd[2][kLzMaxSteps],
+      du[2][kLzMaxSteps], du2[2][kLzMaxSteps];
+  __shared__ int swp[2][kLzMaxSteps];
+  __shared__ double sa[kLzMaxSteps], sb[kLzMaxSteps], sbuf[256], snorm, sth[2], sr[2];
   const int k = st->steps;
   if (k <= 0) return;
   if (!st->broke) {
@@ -408,14 +414,18 @@ __global__ __launch_bounds__(64) void k_lz_bounds(LzState* st, Ctrl* ctrl, doubl
   const double pad = 1e-14 * (hi - lo) + 1e-14 * scale;
   lo -= pad;
   hi += pad;
-  const double th_lo = tridiag_eig(a, b, k, 0, lo, hi, pivmin);
-  const double th_hi = tridiag_eig(a, b, k, k - 1, lo, hi, pivmin);
-  if (threadIdx.x != 0) return;
+  const int wv = threadIdx.x / kWave;   // 0: lowest, 1: highest
+  const double th = tridiag_eig(a, b, k, wv == 0 ? 0 : k - 1, lo, hi, pivmin);
   const double tiny = 1e-13 * scale;
-  const double r_lo = fabs(b[k - 1]) *
-      tridiag_last_component(a, b, k, th_lo - tiny, tiny, x, dl, dd, du, du2, swp);
-  const double r_hi = fabs(b[k - 1]) *
-      tridiag_last_component(a, b, k, th_hi + tiny, tiny, x, dl, dd, du, du2, swp);
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    sth[wv] = th;
+    sr[wv] = fabs(b[k - 1]) * tridiag_last_component(a, b, k, wv == 0 ? th - tiny : th + tiny, tiny,
+                                                     x[wv], dl[wv], dd[wv], du[wv], du2[wv],
+                                                     swp[wv]);
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const double th_lo = sth[0], th_hi = sth[1], r_lo = sr[0], r_hi = sr[1];
   const double m = margin * (th_hi - th_lo);
   const double e_lo = fmax(ctrl->eps_min, th_lo - r_lo - m);
   const double e_hi = fmin(ctrl->eps_max, th_hi + r_hi + m);
