@@ -120,8 +120,8 @@ bool make_layout(int64_t n, const sp2_options& o, Layout& L) {
   // reader rebuilds it)
   L.off_lzvec = take(size_t(kLzMaxSteps + 3) * size_t(n) * 8);
   // first-pass dot partials per matvec work-group, second-pass partials and
-  // squared-norm partials per 256-row chunk
-  L.off_lzpart = take((size_t(L.lz_blocks + L.lz_chunks) * kLzCoef + size_t(L.lz_chunks)) * 8);
+  // squared-norm partials per 256-row chunk, first-pass coefficients
+  L.off_lzpart = take((size_t(L.lz_blocks + L.lz_chunks) * kLzCoef + size_t(L.lz_chunks) + kLzCoef) * 8);
   L.slot_bytes = size_t(L.np) * size_t(L.np) * 4;
   L.every = o.checkpoint_every;
   // slots 0-3: S (FP32), two hi/lo plane pairs (or FP32 ping-pong), S^2 for
@@ -181,6 +181,7 @@ sp2_status refine_bounds(const WS& w, const float* H, int64_t n, int64_t ld, int
   double* p1 = w.lzpart;                  // first-pass dot partials (per matvec work-group)
   double* p2 = p1 + size_t(nb) * kLzCoef;  // second-pass dot partials
   double* pn = p2 + size_t(nc) * kLzCoef;  // squared-norm partials
+  double* pc = pn + nc;                    // first-pass coefficients
   steps = static_cast<int>(std::min<int64_t>(steps, n));
   k_lz_start<<<1, kLzThreads, 0, st>>>(V, n, static_cast<uint64_t>(static_cast<uint32_t>(seed)),
                                        w.lz);
@@ -189,9 +190,11 @@ sp2_status refine_bounds(const WS& w, const float* H, int64_t n, int64_t ld, int
     double* wj = wb[j & 1];
     k_lz_matvec<<<nb, kLzMvThreads, 0, st>>>(H, n, ld, V, wb[(j + 1) & 1], wj, pn, nc, p1, w.lz, j);
     LAUNCH_TRY();
-    k_lz_apply<<<nc, kLzChunk, 0, st>>>(V, wj, n, j, p1, nb, p2, w.lz, 0);
+    k_lz_coef<<<j + 1, kLzChunk, 0, st>>>(p1, nb, pc, w.lz);
     LAUNCH_TRY();
-    k_lz_apply<<<nc, kLzChunk, 0, st>>>(V, wj, n, j, p2, nc, pn, w.lz, 1);
+    k_lz_apply<<<nc, kLzChunk, 0, st>>>(V, wj, n, j, pc, nullptr, 0, p2, w.lz, 0);
+    LAUNCH_TRY();
+    k_lz_apply<<<nc, kLzChunk, 0, st>>>(V, wj, n, j, nullptr, p2, nc, pn, w.lz, 1);
     LAUNCH_TRY();
   }
   k_lz_bounds<<<1, 2 * kWave, 0, st>>>(w.lz, w.ctrl, kLzMargin, pn, nc);

@@ -238,11 +238,29 @@ __device__ __forceinline__ void chunk_dots(const double* V, double wr, int64_t r
   }
 }
 
-// A Gram-Schmidt update: c = sum of the chunk partials, w -= V c on this
-// chunk; then either the partial dots of the second pass (last = 0; block 0
-// records alpha_j = c_j of the first pass) or the partial |w|^2 (last = 1).
+// Coefficient i = blockIdx.x of a Gram-Schmidt pass from many partials
+// (one per matrix-vector work-group): thread t adds partials t, t + 256, ...
+// in turn, then a fixed-order tree over the work-group.
+__global__ __launch_bounds__(kLzChunk) void k_lz_coef(const double* __restrict__ part, int nparts,
+                                                      double* __restrict__ coef,
+                                                      const LzState* st) {
+  __shared__ double red[kLzChunk / kWave];
+  if (st->broke) return;
+  const int i = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += kLzChunk) s += part[int64_t(b) * kLzCoef + i];
+  s = block_sum1<kLzChunk>(s, red);
+  if (threadIdx.x == 0) coef[i] = s;
+}
+
+// A Gram-Schmidt update: c from coef_in (the first pass, reduced by
+// k_lz_coef) or summed here from the chunk partials part_in (the second
+// pass), w -= V c on this chunk; then either the partial dots of the second
+// pass (last = 0; block 0 records alpha_j = c_j of the first pass) or the
+// partial |w|^2 (last = 1).
 __global__ __launch_bounds__(kLzChunk) void k_lz_apply(const double* __restrict__ V,
                                                        double* __restrict__ w, int64_t n, int j,
+                                                       const double* __restrict__ coef_in,
                                                        const double* __restrict__ part_in,
                                                        int nchunks, double* __restrict__ part_out,
                                                        LzState* st, int last) {
@@ -251,7 +269,12 @@ __global__ __launch_bounds__(kLzChunk) void k_lz_apply(const double* __restrict_
   __shared__ double coef[kLzCoef];
   __shared__ double buf[kBuf];
   if (st->broke) return;
-  ordered_sums(part_in, nchunks, kLzCoef, j + 1, buf, kBuf, coef);
+  if (coef_in) {
+    if (threadIdx.x <= j) coef[threadIdx.x] = coef_in[threadIdx.x];
+    __syncthreads();
+  } else {
+    ordered_sums(part_in, nchunks, kLzCoef, j + 1, buf, kBuf, coef);
+  }
   const int64_t row = int64_t(blockIdx.x) * kLzChunk + threadIdx.x;
   double wr = 0.0;
   if (row < n) {
