@@ -175,6 +175,35 @@ def test_autograd_function(pk):
     assert _rel(to_host(H.grad), oracle.dmpt_response(h64, 128, w.astype(np.float64))) < 1e-3
 
 
+def test_autograd_split_derivatives(pk):
+    """The autograd function with BF16X3 layers and split derivative products:
+    backward (VJP) and forward-mode (JVP through torch.autograd.forward_ad)
+    against the FP64 derivatives of the same validated network."""
+    import torch
+    import torch.autograd.forward_ad as fwAD
+    banner("autograd SP2Density bf16x3 split derivatives")
+    h32 = _hamiltonian("water")
+    n, n_occ = 300, 200
+    w = symmetric_normal(n, 1).astype(np.float32)
+    h1 = symmetric_normal(n, 2, std=1e-3).astype(np.float32)
+    opts = {"precision": "bf16x3", "refine": "fp32", "split_derivatives": True}
+    H = to_dev(h32).requires_grad_(True)
+    P = pk.SP2Density.apply(H, n_occ, opts)
+    (P * to_dev(w)).sum().backward()
+    with fwAD.dual_level():
+        dual = fwAD.make_dual(to_dev(h32), to_dev(h1))
+        P1 = fwAD.unpack_dual(pk.SP2Density.apply(dual, n_occ, opts)).tangent
+    _, info = pk.density(to_dev(h32), n_occ, checkpoint_every=4, return_info=True, **opts)
+    h64 = h32.astype(np.float64)
+    rec, _ = validated_record(h64, n_occ, info, "bf16x3", "fp32")
+    g_ref = oracle.sp2_vjp(h64, w.astype(np.float64), rec)
+    j_ref = oracle.sp2_jvp(h64, h1.astype(np.float64), rec)
+    print(f"  vjp rel {_rel(to_host(H.grad), g_ref):.2e}  jvp rel {_rel(to_host(P1), j_ref):.2e}",
+          flush=True)
+    assert _rel(to_host(H.grad), g_ref) < 1e-3
+    assert _rel(to_host(P1), j_ref) < 1e-3
+
+
 def test_tape_required(pk):
     banner("no tape")
     h32 = _hamiltonian("c1")
