@@ -111,21 +111,19 @@ def _layer_reference(x32, precision, sign):
     return r, bound
 
 
-# (n, ld, split tile, split-K tail): at these sizes the tiles do not fill the
-# machine, so by default every tile is split along K and reduced by its last
-# piece; "nosplit" forces whole-tile work-groups only.
-CASES = [(256, 256, None, True), (300, 300, None, True), (1000, 1003, None, True),
-         (520, 520, "256", True), (1000, 1000, None, False), (768, 768, "256", False)]
+# (n, ld, split-K): at these sizes the 256x256 tiles do not fill the machine,
+# so by default every tile is split along K into pieces that the strip tail
+# kernel sums; split-K off (SP2_NO_SPLITK) forces whole-tile work-groups only.
+CASES = [(256, 256, True), (300, 300, True), (1000, 1003, True), (520, 520, True),
+         (1000, 1000, False), (768, 768, False)]
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16x1", "bf16x3", "fp16x3"])
-@pytest.mark.parametrize("n,ld,tile,splitk", CASES)
+@pytest.mark.parametrize("n,ld,splitk", CASES)
 @pytest.mark.parametrize("sign", [1, -1])
-def test_layer_matches_oracle_product(pk, precision, n, ld, tile, splitk, sign, monkeypatch):
+def test_layer_matches_oracle_product(pk, precision, n, ld, splitk, sign, monkeypatch):
     import torch
-    banner(f"layer {precision} n={n} ld={ld} tile={tile} splitk={splitk} sign={sign}")
-    if tile:
-        monkeypatch.setenv("SP2_SPLIT_TILE", tile)
+    banner(f"layer {precision} n={n} ld={ld} splitk={splitk} sign={sign}")
     if not splitk:
         monkeypatch.setenv("SP2_NO_SPLITK", "1")
     rng = np.random.default_rng(n + 3)
