@@ -22,14 +22,29 @@ __global__ __launch_bounds__(kRowThreads) void k_gershgorin_rows(const float* __
   double lo = INFINITY, hi = -INFINITY, bad = 0.0;
   if (row < n) {
     const float* r = H + row * ld;
-    double s = 0.0;
+    double s = 0.0, s1 = 0.0;   // two chains: loads stay in flight
     bool finite = true;
-    for (int64_t j = lane; j < n; j += kWave) {
+    int64_t j0 = 0;
+    if ((ld % 4 == 0) && ((reinterpret_cast<uintptr_t>(H) & 15) == 0)) {
+      const int64_t n4 = n & ~int64_t(3);
+#pragma unroll 2
+      for (int64_t c = 4 * lane; c < n4; c += 4 * kWave) {
+        const f32x4 v = *reinterpret_cast<const f32x4*>(r + c);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          finite = finite && isfinite(v[e]);
+          const double a = c + e != row ? fabs(static_cast<double>(v[e])) : 0.0;
+          if (e & 1) s1 += a; else s += a;
+        }
+      }
+      j0 = n4;
+    }
+    for (int64_t j = j0 + lane; j < n; j += kWave) {
       const float v = r[j];
       finite = finite && isfinite(v);
       if (j != row) s += fabs(static_cast<double>(v));
     }
-    s = wave_sum(s);
+    s = wave_sum(s + s1);
     const double fin = wave_min(finite ? 1.0 : 0.0);
     const double d = static_cast<double>(r[row]);
     lo = d - s;
