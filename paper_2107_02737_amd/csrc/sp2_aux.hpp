@@ -116,11 +116,16 @@ __global__ __launch_bounds__(256) void k_bounds_final(const double* __restrict__
 
 constexpr int kEwThreads = 256;
 
-// Input layer S_0 = (eps_max I - H) / (eps_max - eps_min) (Section II.D),
-// scalars in FP64, stored FP32 into the padded np x np buffer S (zero
-// padding), with optional dual 16-bit split (split: 0 none, 1 bf16, 2 fp16
-// scaled) and one (Tr, ||.||_F^2) partial pair per block.  A degenerate
-// spectrum gives S_0 = I/2.  Each thread handles 4 consecutive columns.
+// Input layer (Section II.D): S_0 = (eps_max I - H) / (eps_max - eps_min),
+// computed in FP64 per entry and rounded once to FP32, zero on the padding;
+// also its hi/lo planes (split: 1 bf16, 2 fp16 scaled) and FP64 partials of
+// Tr S_0 and ||S_0||_F^2 per work-group.  Work-groups stride over tiles of
+// 32 rows x 256 columns: the tile is read and S_0 written a row at a time
+// (1 KB per wave access), then the tile, staged in LDS, is written as planes
+// a thread per row, so that every 16-byte chunk store of 32 consecutive rows
+// forms one 512-byte run of the K-tiled layout.  A degenerate spectrum
+// (eps_max = eps_min) gives S_0 = I/2.
+constexpr int kInRows = 32, kInCols = 256, kInLd = 260;   // odd LDS row stride in 16-byte units
 __global__ __launch_bounds__(kEwThreads) void k_input_layer(const float* __restrict__ H, int64_t n,
                                                             int64_t ld, int64_t np,
                                                             const Ctrl* __restrict__ ctrl,
@@ -128,49 +133,82 @@ __global__ __launch_bounds__(kEwThreads) void k_input_layer(const float* __restr
                                                             uint16_t* __restrict__ hi,
                                                             uint16_t* __restrict__ lo, int split,
                                                             double* __restrict__ parts) {
+  static_assert(kEwThreads == 256, "tile mapping");
+  __shared__ __attribute__((aligned(16))) float tile[kInRows * kInLd];
   __shared__ double red[2 * (kEwThreads / kWave)];
   const double emax = ctrl->eps_max;
   const double inv = ctrl->inv_range;
   const bool degenerate = ctrl->degenerate != 0;
-  const int64_t quads = np * np / 4;
+  const bool vec = (ld % 4 == 0) && ((reinterpret_cast<uintptr_t>(H) & 15) == 0);
+  const int64_t tiles_c = np / kInCols, ntiles = (np / kInRows) * tiles_c;
+  const int t = threadIdx.x, q = t & (kWave - 1), rsub = t / kWave;
   double t1 = 0.0, t2 = 0.0;
-  for (int64_t q = int64_t(blockIdx.x) * kEwThreads + threadIdx.x; q < quads;
-       q += int64_t(gridDim.x) * kEwThreads) {
-    const int64_t i = (4 * q) / np;
-    const int64_t j0 = (4 * q) % np;
-    float v[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int64_t j = j0 + c;
-      float x = 0.0f;
-      if (i < n && j < n) {
-        if (degenerate) {
-          x = (i == j) ? 0.5f : 0.0f;
+  for (int64_t tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
+    const int64_t R0 = (tl / tiles_c) * kInRows, C0 = (tl % tiles_c) * kInCols;
+    const int64_t j0 = C0 + 4 * q;
+#pragma unroll 2
+    for (int k = 0; k < kInRows / 4; ++k) {
+      const int r = rsub + 4 * k;
+      const int64_t i = R0 + r;
+      float h4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+      if (i < n) {
+        if (vec && j0 + 3 < n) {
+          const f32x4 h = *reinterpret_cast<const f32x4*>(H + i * ld + j0);
+          h4[0] = h[0]; h4[1] = h[1]; h4[2] = h[2]; h4[3] = h[3];
         } else {
-          const double h = static_cast<double>(H[i * ld + j]);
-          x = static_cast<float>(((i == j ? emax : 0.0) - h) * inv);
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            if (j0 + c < n) h4[c] = H[i * ld + j0 + c];
         }
       }
-      v[c] = x;
-      const double xd = static_cast<double>(x);
-      t2 += xd * xd;
-      if (i == j) t1 += xd;
-    }
-    *reinterpret_cast<f32x4*>(S + i * np + j0) = f32x4{v[0], v[1], v[2], v[3]};
-    if (split) {
-      uint16_t h4[4], l4[4];
+      float v[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        if (split == 1)
-          split_bf16(v[c], h4[c], l4[c]);
-        else
-          split_fp16s(v[c], h4[c], l4[c]);
+        const int64_t j = j0 + c;
+        float x = 0.0f;
+        if (i < n && j < n) {
+          if (degenerate)
+            x = (i == j) ? 0.5f : 0.0f;
+          else
+            x = static_cast<float>(((i == j ? emax : 0.0) - static_cast<double>(h4[c])) * inv);
+        }
+        v[c] = x;
+        const double xd = static_cast<double>(x);
+        t2 += xd * xd;
+        if (i == j) t1 += xd;
       }
-      const int64_t o = plane_off(i, j0, np);   // 4 consecutive columns stay contiguous
-      *reinterpret_cast<u32x2*>(hi + o) =
-          u32x2{uint32_t(h4[0]) | (uint32_t(h4[1]) << 16), uint32_t(h4[2]) | (uint32_t(h4[3]) << 16)};
-      *reinterpret_cast<u32x2*>(lo + o) =
-          u32x2{uint32_t(l4[0]) | (uint32_t(l4[1]) << 16), uint32_t(l4[2]) | (uint32_t(l4[3]) << 16)};
+      *reinterpret_cast<f32x4*>(S + i * np + j0) = f32x4{v[0], v[1], v[2], v[3]};
+      *reinterpret_cast<f32x4*>(tile + r * kInLd + 4 * q) = f32x4{v[0], v[1], v[2], v[3]};
+    }
+    if (split) {
+      __syncthreads();
+      const int r = t % kInRows;
+      const int64_t row = R0 + r;
+#pragma unroll
+      for (int m = 0; m < kInCols / 8 / (kEwThreads / kInRows); ++m) {
+        const int ch = t / kInRows + (kEwThreads / kInRows) * m;
+        const f32x4 a = *reinterpret_cast<const f32x4*>(tile + r * kInLd + ch * 8);
+        const f32x4 b = *reinterpret_cast<const f32x4*>(tile + r * kInLd + ch * 8 + 4);
+        const float x8[8] = {a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
+        uint16_t h8[8], l8[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          if (split == 1)
+            split_bf16(x8[e], h8[e], l8[e]);
+          else
+            split_fp16s(x8[e], h8[e], l8[e]);
+        }
+        const int64_t o = plane_off(row, C0 + ch * 8, np);   // 8 columns = one 16-byte chunk
+        u32x4 hv, lv;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          hv[e] = uint32_t(h8[2 * e]) | (uint32_t(h8[2 * e + 1]) << 16);
+          lv[e] = uint32_t(l8[2 * e]) | (uint32_t(l8[2 * e + 1]) << 16);
+        }
+        *reinterpret_cast<u32x4*>(hi + o) = hv;
+        *reinterpret_cast<u32x4*>(lo + o) = lv;
+      }
+      __syncthreads();   // the next tile reuses the LDS
     }
   }
   block_sum2<kEwThreads>(t1, t2, red);

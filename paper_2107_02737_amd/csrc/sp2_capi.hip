@@ -93,8 +93,8 @@ bool make_layout(int64_t n, const sp2_options& o, Layout& L) {
   L.np = round_up(n, kPad);
   L.nb_split = static_cast<int>(L.np / 256);
   L.ntiles_split = ntiles_of(L.nb_split);
-  const int64_t quads = L.np * L.np / 4;
-  L.init_blocks = static_cast<int>(std::min<int64_t>(kInitBlocksMax, (quads + kEwThreads - 1) / kEwThreads));
+  // input layer: work-groups striding over its 32 x 256 tiles
+  L.init_blocks = static_cast<int>(std::min<int64_t>(kInitBlocksMax, (L.np / kInRows) * (L.np / kInCols)));
   L.gersh_blocks = static_cast<int>((n + kRowsPerBlock - 1) / kRowsPerBlock);
   // product layers: whole tiles + 8 strips per split-K tail tile
   L.max_parts = std::max({L.ntiles_split + kTailStrips * std::min(L.ntiles_split, kMaxTailTiles),
