@@ -126,6 +126,42 @@ constexpr int kEwThreads = 256;
 // forms one 512-byte run of the K-tiled layout.  A degenerate spectrum
 // (eps_max = eps_min) gives S_0 = I/2.
 constexpr int kInRows = 32, kInCols = 256, kInLd = 260;   // odd LDS row stride in 16-byte units
+
+// Hi/lo planes of one 32 x 256 tile staged in LDS (row stride kInLd) at
+// rows R0.., columns C0.. of an np x np matrix in the K-tiled layout: a
+// thread per row, 8 columns (one 16-byte chunk) per store, so that the
+// stores of 32 consecutive rows form one 512-byte run.
+__device__ __forceinline__ void tile_planes(const float* tile, int64_t R0, int64_t C0, int64_t np,
+                                            int split, uint16_t* __restrict__ hi,
+                                            uint16_t* __restrict__ lo) {
+  const int t = threadIdx.x, r = t % kInRows;
+  const int64_t row = R0 + r;
+#pragma unroll
+  for (int m = 0; m < kInCols / 8 / (kEwThreads / kInRows); ++m) {
+    const int ch = t / kInRows + (kEwThreads / kInRows) * m;
+    const f32x4 a = *reinterpret_cast<const f32x4*>(tile + r * kInLd + ch * 8);
+    const f32x4 b = *reinterpret_cast<const f32x4*>(tile + r * kInLd + ch * 8 + 4);
+    const float x8[8] = {a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
+    uint16_t h8[8], l8[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      if (split == 1)
+        split_bf16(x8[e], h8[e], l8[e]);
+      else
+        split_fp16s(x8[e], h8[e], l8[e]);
+    }
+    const int64_t o = plane_off(row, C0 + ch * 8, np);   // 8 columns = one 16-byte chunk
+    u32x4 hv, lv;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      hv[e] = uint32_t(h8[2 * e]) | (uint32_t(h8[2 * e + 1]) << 16);
+      lv[e] = uint32_t(l8[2 * e]) | (uint32_t(l8[2 * e + 1]) << 16);
+    }
+    *reinterpret_cast<u32x4*>(hi + o) = hv;
+    *reinterpret_cast<u32x4*>(lo + o) = lv;
+  }
+}
+
 __global__ __launch_bounds__(kEwThreads) void k_input_layer(const float* __restrict__ H, int64_t n,
                                                             int64_t ld, int64_t np,
                                                             const Ctrl* __restrict__ ctrl,
@@ -182,32 +218,7 @@ __global__ __launch_bounds__(kEwThreads) void k_input_layer(const float* __restr
     }
     if (split) {
       __syncthreads();
-      const int r = t % kInRows;
-      const int64_t row = R0 + r;
-#pragma unroll
-      for (int m = 0; m < kInCols / 8 / (kEwThreads / kInRows); ++m) {
-        const int ch = t / kInRows + (kEwThreads / kInRows) * m;
-        const f32x4 a = *reinterpret_cast<const f32x4*>(tile + r * kInLd + ch * 8);
-        const f32x4 b = *reinterpret_cast<const f32x4*>(tile + r * kInLd + ch * 8 + 4);
-        const float x8[8] = {a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
-        uint16_t h8[8], l8[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          if (split == 1)
-            split_bf16(x8[e], h8[e], l8[e]);
-          else
-            split_fp16s(x8[e], h8[e], l8[e]);
-        }
-        const int64_t o = plane_off(row, C0 + ch * 8, np);   // 8 columns = one 16-byte chunk
-        u32x4 hv, lv;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          hv[e] = uint32_t(h8[2 * e]) | (uint32_t(h8[2 * e + 1]) << 16);
-          lv[e] = uint32_t(l8[2 * e]) | (uint32_t(l8[2 * e + 1]) << 16);
-        }
-        *reinterpret_cast<u32x4*>(hi + o) = hv;
-        *reinterpret_cast<u32x4*>(lo + o) = lv;
-      }
+      tile_planes(tile, R0, C0, np, split, hi, lo);
       __syncthreads();   // the next tile reuses the LDS
     }
   }
@@ -219,14 +230,13 @@ __global__ __launch_bounds__(kEwThreads) void k_input_layer(const float* __restr
 }
 
 // Dual representation of an n x n FP32 matrix (leading dimension ld) into
-// hi/lo planes; rows/cols in [n, np) are zero.  split: 1 bf16, 2 fp16
-// scaled.  tiled: planes in the K-tiled layout of an np x np matrix (np a
-// multiple of 256); otherwise row-major with leading dimension ldo.
+// row-major hi/lo planes (leading dimension ldo); rows/cols in [n, np) are
+// zero.  split: 1 bf16, 2 fp16 scaled.  (The K-tiled planes of the solver
+// come from k_split_tiled.)
 __global__ __launch_bounds__(kEwThreads) void k_split(const float* __restrict__ X, int64_t n,
                                                       int64_t ld, int64_t np, int64_t ldo,
                                                       uint16_t* __restrict__ hi,
-                                                      uint16_t* __restrict__ lo, int split,
-                                                      int tiled) {
+                                                      uint16_t* __restrict__ lo, int split) {
   const int64_t total = np * np;
   for (int64_t q = int64_t(blockIdx.x) * kEwThreads + threadIdx.x; q < total;
        q += int64_t(gridDim.x) * kEwThreads) {
@@ -237,9 +247,46 @@ __global__ __launch_bounds__(kEwThreads) void k_split(const float* __restrict__ 
       split_bf16(x, h, l);
     else
       split_fp16s(x, h, l);
-    const int64_t o = tiled ? plane_off(i, j, np) : i * ldo + j;
+    const int64_t o = i * ldo + j;
     hi[o] = h;
     lo[o] = l;
+  }
+}
+
+// Dual representation of an n x n FP32 matrix (leading dimension ld) into
+// the K-tiled hi/lo planes of an np x np matrix (np a multiple of 256; rows
+// and columns in [n, np) are zero): work-groups stride over 32 x 256 tiles,
+// read a row at a time and written as planes from LDS (tile_planes).
+__global__ __launch_bounds__(kEwThreads) void k_split_tiled(const float* __restrict__ X, int64_t n,
+                                                            int64_t ld, int64_t np,
+                                                            uint16_t* __restrict__ hi,
+                                                            uint16_t* __restrict__ lo, int split) {
+  __shared__ __attribute__((aligned(16))) float tile[kInRows * kInLd];
+  const bool vec = (ld % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
+  const int64_t tiles_c = np / kInCols, ntiles = (np / kInRows) * tiles_c;
+  const int t = threadIdx.x, q = t & (kWave - 1), rsub = t / kWave;
+  for (int64_t tl = blockIdx.x; tl < ntiles; tl += gridDim.x) {
+    const int64_t R0 = (tl / tiles_c) * kInRows, C0 = (tl % tiles_c) * kInCols;
+    const int64_t j0 = C0 + 4 * q;
+#pragma unroll 2
+    for (int k = 0; k < kInRows / 4; ++k) {
+      const int r = rsub + 4 * k;
+      const int64_t i = R0 + r;
+      f32x4 v = {0.0f, 0.0f, 0.0f, 0.0f};
+      if (i < n) {
+        if (vec && j0 + 3 < n) {
+          v = *reinterpret_cast<const f32x4*>(X + i * ld + j0);
+        } else {
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            if (j0 + c < n) v[c] = X[i * ld + j0 + c];
+        }
+      }
+      *reinterpret_cast<f32x4*>(tile + r * kInLd + 4 * q) = v;
+    }
+    __syncthreads();
+    tile_planes(tile, R0, C0, np, split, hi, lo);
+    __syncthreads();   // the next tile reuses the LDS
   }
 }
 

@@ -577,7 +577,7 @@ sp2_status refine(const WS& w, int precision, int refine_mode, int n_iter, const
   // FP16X3 split refinement: planes of S (pair p) and of S^2 (pair 1-p).
   const int p = precision == SP2_FP32 ? 0 : (n_iter & 1);
   if (precision != SP2_FP16X3) {
-    k_split<<<ew_grid(L.np * L.np), kEwThreads, 0, st>>>(S, L.np, L.np, L.np, L.np, w.hi(p), w.lo(p), 2, 1);
+    k_split_tiled<<<L.init_blocks, kEwThreads, 0, st>>>(S, L.np, L.np, L.np, w.hi(p), w.lo(p), 2);
     LAUNCH_TRY();
   }
   e1.split_out = 2;
@@ -898,7 +898,7 @@ sp2_status sp2_split(const float* X, int64_t n, int64_t ld, int32_t precision, u
   const int code = split_code_of(precision);
   if (!code) return fail(SP2_ERR_INVALID_ARG, "precision has no 16-bit split");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  k_split<<<ew_grid(n * n), kEwThreads, 0, st>>>(X, n, ld, n, n, hi, lo, code, 0);
+  k_split<<<ew_grid(n * n), kEwThreads, 0, st>>>(X, n, ld, n, n, hi, lo, code);
   LAUNCH_TRY();
   return SP2_OK;
 }
@@ -937,8 +937,8 @@ sp2_status sp2_layer(const float* X, int64_t n, int64_t ld, int32_t precision, i
     const float* A[1] = {Xp};
     s = launch_f32(w, 1, A, A, e, d0, st);
   } else {
-    k_split<<<ew_grid(L.np * L.np), kEwThreads, 0, st>>>(Xp, L.np, L.np, L.np, L.np, w.hi(0), w.lo(0),
-                                                         split_code_of(precision), 1);
+    k_split_tiled<<<L.init_blocks, kEwThreads, 0, st>>>(Xp, L.np, L.np, L.np, w.hi(0), w.lo(0),
+                                                        split_code_of(precision));
     LAUNCH_TRY();
     s = launch_split(w, precision, w.hi(0), w.lo(0), w.hi(0), w.lo(0), e, d0, st);
   }
@@ -1021,9 +1021,8 @@ sp2_status sym_pair_split(const WS& w, const uint16_t* xh, const uint16_t* xl, i
 
 // BF16X3 planes of an FP32 derivative iterate (np x np) into pair `op`.
 sp2_status split_derivative(const WS& w, const float* X, int op, hipStream_t st) {
-  k_split<<<ew_grid(w.L.np * w.L.np), kEwThreads, 0, st>>>(X, w.L.np, w.L.np, w.L.np, w.L.np,
-                                                            dhi(w, op), dlo(w, op),
-                                                            split_code_of(SP2_BF16X3), 1);
+  k_split_tiled<<<w.L.init_blocks, kEwThreads, 0, st>>>(X, w.L.np, w.L.np, w.L.np, dhi(w, op),
+                                                        dlo(w, op), split_code_of(SP2_BF16X3));
   LAUNCH_TRY();
   return SP2_OK;
 }
@@ -1061,8 +1060,8 @@ sp2_status refine_derivative(const WS& w, const float* S, const float* D, float*
 sp2_status load_checkpoint(const WS& w, int prec, int slot, float* dst, hipStream_t st) {
   HIP_TRY(hipMemcpyAsync(dst, w.tape(slot), w.L.slot_bytes, hipMemcpyDeviceToDevice, st));
   if (prec != SP2_FP32) {
-    k_split<<<ew_grid(w.L.np * w.L.np), kEwThreads, 0, st>>>(dst, w.L.np, w.L.np, w.L.np, w.L.np,
-                                                              w.hi(0), w.lo(0), split_code_of(prec), 1);
+    k_split_tiled<<<w.L.init_blocks, kEwThreads, 0, st>>>(dst, w.L.np, w.L.np, w.L.np, w.hi(0),
+                                                          w.lo(0), split_code_of(prec));
     LAUNCH_TRY();
   }
   return SP2_OK;
@@ -1183,9 +1182,8 @@ sp2_status sp2_vjp(void* workspace, size_t ws_bytes, const float* W, int64_t ld,
     for (int nn = e - 1; nn >= c; --nn) {
       if (sd) {
         // planes of S_nn into pair 0 (the recomputation has moved on)
-        k_split<<<ew_grid(L.np * L.np), kEwThreads, 0, st>>>(w.seg(nn - c), L.np, L.np, L.np, L.np,
-                                                             w.hi(0), w.lo(0),
-                                                             split_code_of(SP2_BF16X3), 1);
+        k_split_tiled<<<L.init_blocks, kEwThreads, 0, st>>>(w.seg(nn - c), L.np, L.np, L.np, w.hi(0),
+                                                            w.lo(0), split_code_of(SP2_BF16X3));
         LAUNCH_TRY();
         s = sym_pair_split(w, w.hi(0), w.lo(0), cur, w.work(cur), w.work(1 - cur), 1 - cur, 2, nn,
                            st);
