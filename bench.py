@@ -429,7 +429,10 @@ def main():
             out["xl_kernel_split_derivatives"] = xl_kernel(pk, int(gold["seed"]), args.xl_rank,
                                                            args.precision, args.refine, True)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(h32, n_occ, args.cpu_layers, n_iter)
+        cb = cpu_baseline(h32, n_occ, args.cpu_layers, n_iter)
+        cb["gpu_speedup_vs_oracle_sp2"] = out["value"] / cb["value"]
+        cb["gpu_speedup_vs_oracle_eigh"] = cb["eigh_seconds"] * out["value"]
+        out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
 

@@ -27,11 +27,14 @@ def _case(name):
         return water_box_hamiltonian(50, seed=3).astype(np.float32), 200, 305
     if name == "water":
         return water_box_hamiltonian(100, seed=5).astype(np.float32), 400, None
+    if name == "random4099":   # ragged, many matrix-vector work-groups and chunks
+        a = np.random.default_rng(4).standard_normal((4099, 4099))
+        return ((a + a.T) / 120.0).astype(np.float32), 2000, 4100
     a = np.random.default_rng(9).standard_normal((777, 777))
     return ((a + a.T) / 40.0).astype(np.float32), 300, None
 
 
-@pytest.mark.parametrize("name", ["c1", "water-ragged", "water", "random777"])
+@pytest.mark.parametrize("name", ["c1", "water-ragged", "water", "random777", "random4099"])
 @pytest.mark.parametrize("steps", [8, 16, 32, 64])
 def test_bounds_match_oracle(pk, name, steps):
     h32, _, ld = _case(name)
