@@ -202,9 +202,10 @@ sp2_status refine_bounds(const WS& w, const float* H, int64_t n, int64_t ld, int
   return SP2_OK;
 }
 
-// Compute units of the current device (cached per device).
+// Compute units of the current device (cached per device and thread, so
+// that concurrent callers never share a write).
 int device_cus() {
-  static int cache[64] = {0};
+  thread_local int cache[64] = {0};
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
   if (!cache[dev]) {
@@ -314,12 +315,12 @@ Decide make_decide(const WS& w, int mode, int layer) {
   return d;
 }
 
-// Resident work-groups per CU of a kernel (cached per kernel).
+// Resident work-groups per CU of a kernel (cached per kernel and thread).
 template <class K>
 int wgs_per_cu(K kernel, int threads) {
   struct Entry { const void* k; int n; };
-  static Entry cache[32];
-  static int used = 0;
+  thread_local Entry cache[32];
+  thread_local int used = 0;
   const void* key = reinterpret_cast<const void*>(kernel);
   for (int i = 0; i < used; ++i)
     if (cache[i].k == key) return cache[i].n;
