@@ -72,14 +72,14 @@ _LIB = None
 
 
 def load_library(path=None):
-    """Load ``libsp2.so`` (built in-tree by ``__graft_entry__.build()``).
+    """Load ``libsp2.so`` (built in-tree by ``paper_2107_02737_amd.build.build()``).
     Fails loudly when it is missing: there is no fallback path."""
     global _LIB
     if _LIB is not None:
         return _LIB
     path = path or LIB_PATH
     if not os.path.exists(path):
-        raise RuntimeError(f"{path} is not built; run __graft_entry__.build() first")
+        raise RuntimeError(f"{path} is not built; run paper_2107_02737_amd.build.build() first")
     lib = ctypes.CDLL(path)
     vp = c_void_p
     lib.sp2_default_options.argtypes = [ctypes.POINTER(sp2_options)]

@@ -22,7 +22,7 @@ def _declared_functions():
 def lib():
     from paper_2107_02737_amd import _lib
     if not os.path.exists(_lib.LIB_PATH):
-        pytest.fail("libsp2.so is not built; run __graft_entry__.build()")
+        pytest.fail("libsp2.so is not built; run paper_2107_02737_amd.build.build()")
     return _lib.load_library()
 
 
