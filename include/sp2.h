@@ -73,7 +73,8 @@ typedef struct {
   int32_t refine;           /* sp2_refine (default SP2_REFINE_FP32) */
   int32_t max_iter;         /* layer cap, 1..SP2_MAX_ITER (default 100) */
   int32_t stop_rule;        /* 0: stop when e_n < tol; 1 (default): also stop when
-                               e_n < stall_gate and e_n >= e_{n-2} (rounding floor) */
+                               e_n < stall_gate and e_n >= e_{n-2} (rounding floor).
+                               Either rule stops only while |Tr S_n - n_occ| < 1/2 */
   int32_t checkpoint_every; /* 0 (default): no tape.  k > 0: keep S_0 and every k-th
                                iterate in the workspace for sp2_jvp / sp2_vjp */
   int32_t flags;            /* bit SP2_FLAG_TIME_LAYERS: time every layer launch with HIP
@@ -88,7 +89,12 @@ typedef struct {
                                sp2_spectral_bounds) */
   int32_t bound_seed;       /* SplitMix64 state of the Lanczos start vector (default 0) */
   double tol;               /* stop when e_n = |Tr S_n - ||S_n||_F^2| < tol (default 1e-5) */
-  double stall_gate;        /* default 1.0 */
+  double stall_gate;        /* gate of the stagnation test; < 0 (default -1): automatic,
+                               max(3/16, n u / 16) with u the unit roundoff of the layer
+                               operands (2^-8 BF16X1, 2^-16 BF16X3, 2^-22 FP16X3, 2^-24
+                               FP32).  Below 3/16 every eigenvalue of S_n is within 1/4 of
+                               0 or 1; n u / 16 stays above the rounding floor of e_n.
+                               NaN is rejected */
 } sp2_options;
 
 typedef struct {

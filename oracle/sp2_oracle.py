@@ -45,6 +45,7 @@ __all__ = [
     "input_layer",
     "choose_branch",
     "should_stop",
+    "STALL_GATE",
     "sp2",
     "sp2_scalar",
     "mcweeny",
@@ -115,18 +116,30 @@ def choose_branch(t1, t2, n_occ):
     return 1 if abs(t2 - n_occ) <= abs(2.0 * t1 - t2 - n_occ) else -1
 
 
-def should_stop(k, errs, tol, stop_rule, stall_gate):
+def should_stop(k, errs, trace_gap, tol, stop_rule, stall_gate):
     """Convergence test on the idempotency estimate ``e_k = |Tr S_k - Tr S_k^2|``
-    (Section II.E: idempotency estimated from traces).  Rule 0: ``e_k < tol``.
-    Rule 1 adds a stagnation test for finite precision: stop once
-    ``e_k < stall_gate`` and ``e_k >= e_{k-2}`` (two more layers did not reduce
-    the error, so rounding dominates)."""
+    (Section II.E: idempotency estimated from traces).
+
+    No stop while ``trace_gap = |Tr S_k - n_occ| >= 1/2``: the approximation
+    does not yet hold ``n_occ`` eigenvalues near 1 (an occupied eigenvalue can
+    be driven close to 0 on the way, which makes ``e_k`` small long before
+    convergence).  Otherwise rule 0 stops when ``e_k < tol``; rule 1 also
+    stops on stagnation, ``e_k >= e_{k-2}`` (two more layers did not reduce
+    the error, so rounding dominates), once ``e_k < stall_gate``.  With every
+    eigenvalue in [0, 1], ``e_k < 3/16`` puts each within 1/4 of 0 or 1, where
+    every layer pair contracts in exact arithmetic; together with the trace
+    gap this also fixes which eigenvalues sit near 1."""
+    if not trace_gap < 0.5:
+        return False
     e = errs[k]
     if e < tol:
         return True
     if stop_rule == 1 and k >= 2 and e < stall_gate and e >= errs[k - 2]:
         return True
     return False
+
+
+STALL_GATE = 3.0 / 16.0
 
 
 @dataclass
@@ -155,7 +168,7 @@ class SP2Record:
         return np.array([1 if s > 0 else 0 for s in self.branches], dtype=np.uint8)
 
 
-def sp2(h, n_occ, tol=1e-10, max_iter=100, stop_rule=0, stall_gate=1.0,
+def sp2(h, n_occ, tol=1e-10, max_iter=100, stop_rule=0, stall_gate=STALL_GATE,
         bounds=None, refine=False, return_iterates=False):
     """DNN-SP2 in FP64 (Eq. 19 and Fig. 1 of Section II.D).
 
@@ -191,7 +204,7 @@ def sp2(h, n_occ, tol=1e-10, max_iter=100, stop_rule=0, stall_gate=1.0,
         rec.t1.append(t1)
         rec.t2.append(t2)
         rec.err.append(abs(t1 - t2))
-        if should_stop(k, rec.err, tol, stop_rule, stall_gate):
+        if should_stop(k, rec.err, abs(t1 - n_occ), tol, stop_rule, stall_gate):
             rec.converged = True
             break
         if k == max_iter:
@@ -212,7 +225,7 @@ def sp2(h, n_occ, tol=1e-10, max_iter=100, stop_rule=0, stall_gate=1.0,
 
 
 def sp2_scalar(w, n_occ, eps_min, eps_max, tol=1e-10, max_iter=100, stop_rule=0,
-               stall_gate=1.0):
+               stall_gate=STALL_GATE):
     """The same recursion applied to the eigenvalues ``w`` of ``H`` instead of
     the matrix: every layer acts on the spectrum only (the eigenvectors stay
     the same, Section II.C-D), so traces are plain sums over the mapped
@@ -226,7 +239,7 @@ def sp2_scalar(w, n_occ, eps_min, eps_max, tol=1e-10, max_iter=100, stop_rule=0,
         rec.t1.append(t1)
         rec.t2.append(t2)
         rec.err.append(abs(t1 - t2))
-        if should_stop(k, rec.err, tol, stop_rule, stall_gate):
+        if should_stop(k, rec.err, abs(t1 - n_occ), tol, stop_rule, stall_gate):
             rec.converged = True
             break
         if k == max_iter:

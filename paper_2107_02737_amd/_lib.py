@@ -148,8 +148,9 @@ SP2_FLAG_SPLIT_DERIVATIVES = 2
 
 
 def make_options(precision="bf16x3", refine="fp32", max_iter=100, stop_rule=1,
-                 checkpoint_every=0, tol=1e-5, stall_gate=1.0, time_layers=False,
+                 checkpoint_every=0, tol=1e-5, stall_gate=-1.0, time_layers=False,
                  bound_steps=0, bound_seed=0, split_derivatives=False):
+    """sp2_options; ``stall_gate`` < 0 selects the library's automatic gate."""
     lib = load_library()
     o = sp2_options()
     lib.sp2_default_options(ctypes.byref(o))

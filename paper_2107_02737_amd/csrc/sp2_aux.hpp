@@ -355,8 +355,8 @@ __global__ __launch_bounds__(kEwThreads) void k_fill_diag(float* __restrict__ P,
 // max_iter layers, evaluate the stop test on S_{max_iter} and record it.
 __global__ __launch_bounds__(256) void k_finish_loop(Ctrl* ctrl, Hist* hist,
                                                      const double* __restrict__ parts, int nparts,
-                                                     int max_iter, double tol, int stop_rule,
-                                                     double stall_gate) {
+                                                     int max_iter, double n_occ, double tol,
+                                                     int stop_rule, double stall_gate) {
   __shared__ double red[8];
   if (ctrl->stopped) return;
   double t1 = 0.0, t2 = 0.0;
@@ -368,8 +368,7 @@ __global__ __launch_bounds__(256) void k_finish_loop(Ctrl* ctrl, Hist* hist,
   if (threadIdx.x == 0) {
     const int n = max_iter;
     const double e = fabs(t1 - t2);
-    bool stop = e < tol;
-    if (!stop && stop_rule == 1 && n >= 2 && e < stall_gate && e >= hist->err[n - 2]) stop = true;
+    const bool stop = stop_test(t1, e, n, hist->err, n_occ, tol, stop_rule, stall_gate);
     hist->t1[n] = t1;
     hist->t2[n] = t2;
     hist->err[n] = e;

@@ -245,10 +245,24 @@ bool options_ok(const sp2_options& o) {
   return o.precision >= SP2_FP32 && o.precision <= SP2_FP16X3 && o.refine >= SP2_REFINE_NONE &&
          o.refine <= SP2_REFINE_SPLIT && o.max_iter >= 1 && o.max_iter <= SP2_MAX_ITER &&
          (o.stop_rule == 0 || o.stop_rule == 1) && o.checkpoint_every >= 0 &&
-         o.checkpoint_every <= SP2_MAX_ITER && o.tol >= 0.0 && o.stall_gate >= 0.0 &&
+         o.checkpoint_every <= SP2_MAX_ITER && o.tol >= 0.0 && o.stall_gate == o.stall_gate &&
          (o.flags & ~(SP2_FLAG_TIME_LAYERS | SP2_FLAG_SPLIT_DERIVATIVES)) == 0 &&
          (o.bound_steps == 0 ||
           (o.bound_steps >= SP2_MIN_BOUND_STEPS && o.bound_steps <= SP2_MAX_BOUND_STEPS));
+}
+
+// Stagnation gate of stop rule 1: the caller's, or (stall_gate < 0) the
+// larger of 3/16 and n u / 16, u the unit roundoff of the layer operands.
+// Below 3/16 every eigenvalue of S_n lies within 1/4 of 0 or 1; the second
+// term keeps the gate above the rounding floor of the error estimate, which
+// grows with n u.
+double stall_gate_of(const sp2_options& o, int precision, int64_t n) {
+  if (o.stall_gate >= 0.0) return o.stall_gate;
+  const double u = precision == SP2_BF16X1   ? 0x1p-8
+                   : precision == SP2_BF16X3 ? 0x1p-16
+                   : precision == SP2_FP16X3 ? 0x1p-22
+                                             : 0x1p-24;
+  return std::max(3.0 / 16.0, static_cast<double>(n) * u / 16.0);
 }
 
 int split_kind_of(int precision) {
@@ -478,7 +492,7 @@ sp2_status launch_layer(const WS& w, int precision, int n, int mode, const float
     d.nparts_in = nparts_of_layer(w, precision, n);
     d.n_occ = static_cast<double>(n_occ);
     d.tol = o->tol;
-    d.stall_gate = o->stall_gate;
+    d.stall_gate = stall_gate_of(*o, precision, w.L.n);
     d.stop_rule = o->stop_rule;
   }
   Epi e = make_epi(w.L);
@@ -612,7 +626,7 @@ void sp2_default_options(sp2_options* opt) {
   opt->stop_rule = 1;
   opt->checkpoint_every = 0;
   opt->tol = 1e-5;
-  opt->stall_gate = 1.0;
+  opt->stall_gate = -1.0;
 }
 
 const char* sp2_last_error(void) { return g_err.c_str(); }
@@ -752,8 +766,9 @@ sp2_status sp2_density_ex(const float* H, int64_t n, int64_t ld, int64_t n_occ,
   if (hm->ctrl[0].nonfinite) return fail(SP2_ERR_NONFINITE, "H holds NaN or Inf");
   if (!hm->ctrl[0].stopped) {
     k_finish_loop<<<1, 256, 0, st>>>(w.ctrl, w.hist, w.parts[o.max_iter & 1],
-                                     nparts_of_layer(w, prec, o.max_iter), o.max_iter, o.tol,
-                                     o.stop_rule, o.stall_gate);
+                                     nparts_of_layer(w, prec, o.max_iter), o.max_iter,
+                                     static_cast<double>(n_occ), o.tol, o.stop_rule,
+                                     stall_gate_of(o, prec, n));
     LAUNCH_TRY();
     n_iter = o.max_iter;
   } else {

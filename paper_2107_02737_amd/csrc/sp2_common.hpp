@@ -109,6 +109,20 @@ __device__ __forceinline__ void block_sum2(double& a, double& b, double* red) {
 // (2S - S^2), or 0 when the network has stopped.
 // ---------------------------------------------------------------------------
 
+// Stop test on the traces of S_n (Section II.E: idempotency estimated from
+// traces), e = |t1 - t2|.  No stop while |t1 - n_occ| >= 1/2: S_n does not
+// yet hold n_occ eigenvalues near 1 (an occupied eigenvalue can pass close to
+// 0 on the way, which makes e small long before convergence).  Then rule 0:
+// e < tol; rule 1 also stops once e < stall_gate and e >= e_{n-2} (two
+// layers brought no reduction, so rounding dominates).
+__device__ __forceinline__ bool stop_test(double t1, double e, int n, const double* err_hist,
+                                          double n_occ, double tol, int stop_rule,
+                                          double stall_gate) {
+  if (!(fabs(t1 - n_occ) < 0.5)) return false;
+  if (e < tol) return true;
+  return stop_rule == 1 && n >= 2 && e < stall_gate && e >= err_hist[n - 2];
+}
+
 template <int NT>
 __device__ __forceinline__ int decide_layer(const Decide& d, double* red) {
   if (d.mode == 2) return d.hist->branch[d.layer];
@@ -126,9 +140,7 @@ __device__ __forceinline__ int decide_layer(const Decide& d, double* red) {
   if (s_stopped) return 0;
   const int n = d.layer;
   const double e = fabs(t1 - t2);
-  bool stop = e < d.tol;
-  if (!stop && d.stop_rule == 1 && n >= 2 && e < d.stall_gate && e >= d.hist->err[n - 2])
-    stop = true;
+  const bool stop = stop_test(t1, e, n, d.hist->err, d.n_occ, d.tol, d.stop_rule, d.stall_gate);
   // Trace-closest sign: Tr(S^2) = t2 versus Tr(2S - S^2) = 2 t1 - t2; ties take S^2.
   const int sign = (fabs(t2 - d.n_occ) <= fabs(2.0 * t1 - t2 - d.n_occ)) ? 1 : -1;
   if (!d.quiet && blockIdx.x == 0 && threadIdx.x == 0) {

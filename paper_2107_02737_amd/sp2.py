@@ -27,7 +27,7 @@ def _as_matrix(H, symmetrize):
 
 
 def density(H, n_occ, tol=1e-5, precision="bf16x3", refine="fp32", max_iter=100, stop_rule=1,
-            stall_gate=1.0, checkpoint_every=0, symmetrize=False, return_info=False,
+            stall_gate=-1.0, checkpoint_every=0, symmetrize=False, return_info=False,
             workspace=None, time_layers=False, bound_steps=0, bound_seed=0,
             split_derivatives=False):
     """Density matrix of the symmetric ``H`` with ``n_occ`` occupied states.

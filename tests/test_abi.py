@@ -46,7 +46,7 @@ def test_default_options(lib):
     from paper_2107_02737_amd import _lib
     o = _lib.sp2_default_options()
     assert (o.precision, o.refine, o.max_iter, o.stop_rule, o.checkpoint_every) == (2, 1, 100, 1, 0)
-    assert o.tol == 1e-5 and o.stall_gate == 1.0
+    assert o.tol == 1e-5 and o.stall_gate == -1.0
     assert (o.bound_steps, o.bound_seed, o.flags) == (0, 0, 0)
 
 
@@ -95,6 +95,11 @@ def test_invalid_arguments_rejected_before_device_work(lib):
     st = lib.sp2_density_ex(fake, 8, 8, 2, ctypes.byref(opt), fake, ctypes.byref(info), br, 4,
                             ws, 1 << 30, None)
     assert st == _lib.SP2_ERR_INVALID_ARG
+    opt = _lib.sp2_default_options()
+    opt.stall_gate = float("nan")           # a negative gate is the automatic one; NaN is not
+    st = lib.sp2_density_ex(fake, 8, 8, 2, ctypes.byref(opt), fake, ctypes.byref(info), br, 4,
+                            ws, 1 << 30, None)
+    assert st == _lib.SP2_ERR_INVALID_ARG and "options" in _lib.sp2_last_error()
     opt = _lib.sp2_default_options()
     # workspace too small / misaligned / missing
     st = lib.sp2_density_ex(fake, 8, 8, 2, ctypes.byref(opt), fake, ctypes.byref(info), br, 4,
