@@ -14,3 +14,4 @@ from . import precision_emulation  # noqa: F401,E402
 from . import lanczos  # noqa: F401,E402
 from .lanczos import lanczos_bounds  # noqa: F401,E402
 from . import xlbomd  # noqa: F401,E402
+from . import canonical  # noqa: F401,E402

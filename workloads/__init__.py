@@ -1,7 +1,7 @@
 """Seeded synthetic inputs for the density-matrix solver.
 
 This package only draws inputs (Hamiltonians, perturbations, weights and
-the synthetic charge model).  It holds none of the solver's arithmetic, so
+the synthetic charge model, the inputs of the canonical integrator).  It holds none of the solver's arithmetic, so
 both the FP64 oracle and the GPU path can take their inputs from here
 without sharing any code with each other.
 """
@@ -22,4 +22,13 @@ from .charges import (  # noqa: F401
     random_charges,
     charge_shifted_hamiltonian,
     WATER_VALENCE,
+)
+from .canonical import (  # noqa: F401
+    AMU,
+    KB_EV,
+    morse_energy,
+    morse_force,
+    laplace_unit,
+    canonical_noise,
+    water_atom_masses,
 )
