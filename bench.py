@@ -15,7 +15,8 @@ on the same GPU, the roofline of the layer kernel (HIP-event durations
 recorded around every layer launch during the timed steps), the FP64
 oracle timed on the host cores and, outside the timed steps, the XL-BOMD
 kernel building block (one charge-space response and a rank-4 Krylov
-approximation of K f on the water box's synthetic charge model).
+approximation of K f on the water box's synthetic charge model) and the
+canonical integration step of Section IV on a large batch of coordinates.
 """
 
 import argparse
@@ -61,6 +62,9 @@ def parse():
     ap.add_argument("--xl-rank", type=int, default=4,
                     help="also time the XL-BOMD kernel building block (Krylov approximation of "
                          "K f of this rank on the water box's charge model; 0: skip)")
+    ap.add_argument("--nvt-coords", type=int, default=3 * 2 ** 24,
+                    help="also time the canonical integration step on this many FP64 "
+                         "coordinates (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM traffic counters)")
     return ap.parse_args()
@@ -315,6 +319,54 @@ def cpu_baseline(h32, n_occ, layers, n_iter_ref):
     }
 
 
+def canonical_step(pk, n, reps=20):
+    """Both halves of the canonical integration step (Section IV, Eq. 31) on
+    ``n`` FP64 coordinates (seeded, device-resident), timed with HIP events
+    on the stream they are launched on; algorithmic bytes per coordinate:
+    first half reads R, V, F, eta, M and writes R, V (56 B), second half
+    reads V, F, M and writes V (32 B).  Also the per-step time of the water
+    box's 3072 atoms (9216 coordinates), where launch latency dominates."""
+    import torch
+    from workloads import AMU, KB_EV
+
+    kt = 500.0 * KB_EV
+    p = pk.nvt_params(0.5, kt, pk.sp2_nvt_gamma_tc(1.5e-4, kt, 0.5), 1e-3, 0)
+
+    def run(count, iters):
+        g = torch.Generator(device="cuda").manual_seed(7)
+        rnd = lambda s: torch.randn(count, dtype=torch.float64, device="cuda", generator=g) * s
+        R, V, F, eta = rnd(1.0), rnd(0.01), rnd(1.0), rnd(1.0)
+        M = torch.full((count,), 16.0 * AMU, dtype=torch.float64, device="cuda")
+        for _ in range(3):
+            pk.sp2_nvt_first_half(R, V, F, M, p, eta=eta)
+            pk.sp2_nvt_second_half(V, F, M, p)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record()
+        for _ in range(iters):
+            pk.sp2_nvt_first_half(R, V, F, M, p, eta=eta)
+        ev[1].record()
+        for _ in range(iters):
+            pk.sp2_nvt_second_half(V, F, M, p)
+        ev[2].record()
+        torch.cuda.synchronize()
+        if not bool(torch.isfinite(R).all()):
+            raise RuntimeError("canonical step produced non-finite positions")
+        return ev[0].elapsed_time(ev[1]) / iters * 1e3, ev[1].elapsed_time(ev[2]) / iters * 1e3
+
+    t1, t2 = run(n, reps)
+    w1, w2 = run(9216, 200)
+    gbps = 88.0 * n / ((t1 + t2) * 1e-6) / 1e9
+    return {"workload": f"{n} independent coordinates (FP64 R, V, F, eta, M), scheme 0 with "
+                        "both friction terms", "n_coords": n,
+            "first_half_us": t1, "second_half_us": t2,
+            "first_half_gbps": 56.0 * n / (t1 * 1e-6) / 1e9,
+            "second_half_gbps": 32.0 * n / (t2 * 1e-6) / 1e9,
+            "roofline": {"bound": "hbm", "achieved": gbps, "peak": 8000.0, "unit": "GB/s",
+                         "frac": gbps / 8000.0, "traffic": None,
+                         "kernel": "k_nvt_first + k_nvt_second"},
+            "water_box_step_us": w1 + w2}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -428,6 +480,8 @@ def main():
         if args.precision == "bf16x3":
             out["xl_kernel_split_derivatives"] = xl_kernel(pk, int(gold["seed"]), args.xl_rank,
                                                            args.precision, args.refine, True)
+    if args.nvt_coords > 0:
+        out["canonical_step"] = canonical_step(pk, args.nvt_coords)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(h32, n_occ, args.cpu_layers, n_iter)
         cb["gpu_speedup_vs_oracle_sp2"] = out["value"] / cb["value"]

@@ -268,6 +268,52 @@ sp2_status sp2_xl_kernel(void* workspace, size_t ws_bytes, int64_t n_atoms,
                          const double* f, int32_t rank, double* kf, double* rho,
                          int32_t* rank_used, void* scratch, size_t scratch_bytes, void* stream);
 
+/* ---- Canonical integration with force noise as the heat bath (Section IV) ----
+ * One time step of Eq. 31 (scheme 0) or of the variant in the Supporting
+ * Information (scheme 1) for n independent scalar coordinates (x, y, z of
+ * every atom), FP64, split where the force is evaluated:
+ *   sp2_nvt_first_half:  R_k, V_k, F_k, eta_k -> R <- R_{k+1} and V <- W, the
+ *                        velocity before the last half kick;
+ *   (caller: F_{k+1} = force at R_{k+1}, including its noise sigma_TC xi)
+ *   sp2_nvt_second_half: W, F_{k+1} -> V <- V_{k+1}.
+ * Scheme 0: V' = V + h (F - gamma_tc V); R' = R + dt/2 V';
+ * W = c_L V' + sigma_L eta; R_{k+1} = R' + dt/2 W; V_{k+1} solves
+ * V_{k+1} = W + h (F_{k+1} - gamma_tc V_{k+1}).  Scheme 1: V' = V + h F;
+ * R' = R + dt/2 V'; W = s (c_L (s V') + sigma_L eta) with
+ * s = sqrt((1 - gamma_tc h) / (1 + gamma_tc h)); R_{k+1} = R' + dt/2 W;
+ * V_{k+1} = W + h F_{k+1}.  Here h = dt / (2M), c_L = (1 - gamma_l dt/2) /
+ * (1 + gamma_l dt/2), sigma_L = sqrt(kt (1 - c_L^2) / M) (Eq. 32).
+ * gamma_tc is a force per velocity (mass per time); Eq. 33 balances force
+ * noise of standard deviation sigma_TC with gamma_tc = sigma_TC^2 dt / (2 kT)
+ * (sp2_nvt_gamma_tc).  Scheme 1 needs gamma_tc dt < 2M for every coordinate
+ * (else its friction factor is imaginary and V becomes NaN).
+ * Arrays are DEVICE double[n]: R, V updated in place; F the force at the
+ * positions the step starts from (first half) or ends at (second half);
+ * eta standard normal Langevin noise, may be NULL when gamma_l = 0; mass the
+ * mass of every coordinate.  Units are the caller's, consistent (e.g. eV,
+ * Angstrom, fs, eV fs^2 / Angstrom^2).  Every operation is the correctly
+ * rounded FP64 evaluation of these formulas in the order written (no fused
+ * multiply-adds).  Asynchronous on stream; n = 0 is a no-op. */
+typedef struct {
+  double dt;          /* time step, > 0 */
+  double kt;          /* k_B T, >= 0 */
+  double gamma_tc;    /* friction balancing the force noise, force per velocity, >= 0 */
+  double gamma_l;     /* Langevin friction, per time, >= 0 (0: no Langevin term) */
+  int32_t scheme;     /* 0: Eq. 31; 1: the Supporting Information's variant */
+  int32_t reserved;   /* 0 */
+} sp2_nvt_params;
+
+/* gamma_tc = sigma_tc^2 dt / (2 kt) (Eq. 33); NaN unless sigma_tc >= 0,
+ * kt > 0 and dt > 0. */
+double sp2_nvt_gamma_tc(double sigma_tc, double kt, double dt);
+
+sp2_status sp2_nvt_first_half(double* R, double* V, const double* F, const double* eta,
+                              const double* mass, int64_t n, const sp2_nvt_params* p,
+                              void* stream);
+
+sp2_status sp2_nvt_second_half(double* V, const double* F, const double* mass, int64_t n,
+                               const sp2_nvt_params* p, void* stream);
+
 /* Thread-local text describing the last error of this thread ("" if none). */
 const char* sp2_last_error(void);
 

@@ -41,7 +41,7 @@ SP2_MAX_ITER = 256
 EXPORTED = ["sp2_default_options", "sp2_workspace_bytes", "sp2_density", "sp2_density_ex",
             "sp2_jvp", "sp2_vjp", "sp2_bounds", "sp2_spectral_bounds", "sp2_split", "sp2_layer",
             "sp2_mulliken", "sp2_xl_scratch_bytes", "sp2_xl_response", "sp2_xl_kernel",
-            "sp2_last_error"]
+            "sp2_nvt_gamma_tc", "sp2_nvt_first_half", "sp2_nvt_second_half", "sp2_last_error"]
 SP2_XL_MAX_RANK = 32
 
 
@@ -60,6 +60,11 @@ class sp2_info(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class sp2_nvt_params(ctypes.Structure):
+    _fields_ = [("dt", c_double), ("kt", c_double), ("gamma_tc", c_double),
+                ("gamma_l", c_double), ("scheme", c_int32), ("reserved", c_int32)]
 
 
 class SP2Error(RuntimeError):
@@ -116,6 +121,13 @@ def load_library(path=None):
     lib.sp2_xl_kernel.argtypes = [vp, c_size_t, c_int64, vp, vp, vp, vp, c_int32, vp,
                                   ctypes.POINTER(c_double), ctypes.POINTER(c_int32), vp, c_size_t, vp]
     lib.sp2_xl_kernel.restype = c_int32
+    lib.sp2_nvt_gamma_tc.argtypes = [c_double, c_double, c_double]
+    lib.sp2_nvt_gamma_tc.restype = c_double
+    lib.sp2_nvt_first_half.argtypes = [vp, vp, vp, vp, vp, c_int64,
+                                       ctypes.POINTER(sp2_nvt_params), vp]
+    lib.sp2_nvt_first_half.restype = c_int32
+    lib.sp2_nvt_second_half.argtypes = [vp, vp, vp, c_int64, ctypes.POINTER(sp2_nvt_params), vp]
+    lib.sp2_nvt_second_half.restype = c_int32
     lib.sp2_last_error.argtypes = []
     lib.sp2_last_error.restype = ctypes.c_char_p
     _LIB = lib
@@ -354,3 +366,38 @@ def sp2_xl_kernel(workspace, atom_ptr, gamma, f, rank, scratch, k0=None, kf=None
                              _stream(f.device)))
     return kf, list(rho), used.value
 
+
+def nvt_params(dt, kt, gamma_tc=0.0, gamma_l=0.0, scheme=0):
+    """sp2_nvt_params of one canonical integration step (Section IV)."""
+    return sp2_nvt_params(float(dt), float(kt), float(gamma_tc), float(gamma_l), int(scheme), 0)
+
+
+def sp2_nvt_gamma_tc(sigma_tc, kt, dt):
+    """Friction balancing force noise of standard deviation sigma_tc (Eq. 33)."""
+    return float(load_library().sp2_nvt_gamma_tc(float(sigma_tc), float(kt), float(dt)))
+
+
+def _nvt_vec(t, n, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 \
+            or not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{name} must be a contiguous float64 device tensor of {n} entries")
+    return c_void_p(t.data_ptr())
+
+
+def sp2_nvt_first_half(R, V, F, mass, params, eta=None):
+    """In place: R <- R_{k+1}, V <- the velocity before the last half kick."""
+    n = R.numel()
+    _check(load_library().sp2_nvt_first_half(
+        _nvt_vec(R, n, "R"), _nvt_vec(V, n, "V"), _nvt_vec(F, n, "F"),
+        _nvt_vec(eta, n, "eta") if eta is not None else None, _nvt_vec(mass, n, "mass"), n,
+        ctypes.byref(params), _stream(R.device)))
+    return R, V
+
+
+def sp2_nvt_second_half(V, F, mass, params):
+    """In place: V <- V_{k+1} from the intermediate velocity and F_{k+1}."""
+    n = V.numel()
+    _check(load_library().sp2_nvt_second_half(
+        _nvt_vec(V, n, "V"), _nvt_vec(F, n, "F"), _nvt_vec(mass, n, "mass"), n,
+        ctypes.byref(params), _stream(V.device)))
+    return V

@@ -18,6 +18,7 @@
 #include "sp2_common.hpp"
 #include "sp2_gemm.hpp"
 #include "sp2_lanczos.hpp"
+#include "sp2_nvt.hpp"
 #include "sp2_xl.hpp"
 
 using namespace sp2;
@@ -1392,6 +1393,69 @@ sp2_status sp2_xl_kernel(void* workspace, size_t ws_bytes, int64_t n_atoms,
   if (rho)
     for (int k = 0; k <= rank; ++k) rho[k] = hm->xl.rho[k];
   if (rank_used) *rank_used = hm->xl.used;
+  return SP2_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Canonical integration (Section IV, Eq. 31-33)
+// ---------------------------------------------------------------------------
+namespace {
+
+bool finite_nonneg(double x) { return x >= 0.0 && x <= 1.7976931348623157e308; }
+
+sp2_status nvt_check(const sp2_nvt_params* p, int64_t n) {
+  if (!p) return fail(SP2_ERR_INVALID_ARG, "NULL params");
+  if (p->scheme != 0 && p->scheme != 1) return fail(SP2_ERR_INVALID_ARG, "scheme must be 0 or 1");
+  if (!(finite_nonneg(p->dt) && p->dt > 0.0) || !finite_nonneg(p->kt) ||
+      !finite_nonneg(p->gamma_tc) || !finite_nonneg(p->gamma_l))
+    return fail(SP2_ERR_INVALID_ARG, "need dt > 0 and kt, gamma_tc, gamma_l >= 0, all finite");
+  if (n < 0) return fail(SP2_ERR_INVALID_ARG, "n < 0");
+  return SP2_OK;
+}
+
+int nvt_grid(int64_t n) {
+  return static_cast<int>(std::min<int64_t>(8192, (n + kNvtThreads - 1) / kNvtThreads));
+}
+
+}  // namespace
+
+extern "C" {
+
+double sp2_nvt_gamma_tc(double sigma_tc, double kt, double dt) {
+#pragma clang fp contract(off)
+  if (!(finite_nonneg(sigma_tc) && finite_nonneg(kt) && kt > 0.0 && finite_nonneg(dt) && dt > 0.0))
+    return __builtin_nan("");
+  return sigma_tc * sigma_tc * dt / (2.0 * kt);
+}
+
+sp2_status sp2_nvt_first_half(double* R, double* V, const double* F, const double* eta,
+                              const double* mass, int64_t n, const sp2_nvt_params* p,
+                              void* stream) {
+#pragma clang fp contract(off)
+  g_err.clear();
+  if (sp2_status s = nvt_check(p, n)) return s;
+  if (n == 0) return SP2_OK;
+  if (!R || !V || !F || !mass) return fail(SP2_ERR_INVALID_ARG, "NULL R, V, F or mass");
+  if (p->gamma_l > 0.0 && !eta) return fail(SP2_ERR_INVALID_ARG, "gamma_l > 0 needs eta");
+  const double c_l = (1.0 - 0.5 * p->gamma_l * p->dt) / (1.0 + 0.5 * p->gamma_l * p->dt);
+  k_nvt_first<<<nvt_grid(n), kNvtThreads, 0, static_cast<hipStream_t>(stream)>>>(
+      R, V, F, p->gamma_l > 0.0 ? eta : nullptr, mass, n, p->dt, p->kt, p->gamma_tc, c_l,
+      p->scheme);
+  LAUNCH_TRY();
+  return SP2_OK;
+}
+
+sp2_status sp2_nvt_second_half(double* V, const double* F, const double* mass, int64_t n,
+                               const sp2_nvt_params* p, void* stream) {
+  g_err.clear();
+  if (sp2_status s = nvt_check(p, n)) return s;
+  if (n == 0) return SP2_OK;
+  if (!V || !F || !mass) return fail(SP2_ERR_INVALID_ARG, "NULL V, F or mass");
+  k_nvt_second<<<nvt_grid(n), kNvtThreads, 0, static_cast<hipStream_t>(stream)>>>(
+      V, F, mass, n, p->dt, p->gamma_tc, p->scheme);
+  LAUNCH_TRY();
   return SP2_OK;
 }
 

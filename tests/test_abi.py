@@ -2,6 +2,7 @@
 host-only argument checks behave as documented.  No GPU work is issued."""
 
 import ctypes
+import math
 import os
 import re
 
@@ -153,3 +154,32 @@ def test_xl_entry_points_reject_bad_arguments(lib):
         _lib.SP2_ERR_INVALID_ARG
     assert lib.sp2_xl_response(fake, 1 << 30, 4, fake, fake, fake, fake,
                                ctypes.c_void_p(0x1010), 1 << 30, None) == _lib.SP2_ERR_INVALID_ARG
+
+
+def test_nvt_entry_points_reject_bad_arguments(lib):
+    from paper_2107_02737_amd import _lib
+    assert ctypes.sizeof(_lib.sp2_nvt_params) == 4 * 8 + 2 * 4
+    fake = ctypes.c_void_p(0x1000)
+    # Eq. 33: gamma_tc = sigma^2 dt / (2 kT); NaN outside the domain
+    assert _lib.sp2_nvt_gamma_tc(0.3, 0.04, 0.5) == 0.3 * 0.3 * 0.5 / (2.0 * 0.04)
+    for bad in ((-0.1, 0.04, 0.5), (0.1, 0.0, 0.5), (0.1, 0.04, 0.0), (float("nan"), 0.04, 0.5)):
+        assert math.isnan(_lib.sp2_nvt_gamma_tc(*bad))
+
+    def first(p, n=8, eta=fake):
+        return lib.sp2_nvt_first_half(fake, fake, fake, eta, fake, n,
+                                      ctypes.byref(p) if p is not None else None, None)
+
+    good = _lib.nvt_params(0.5, 0.04, 0.1, 1e-3, 0)
+    assert first(good, n=0) == _lib.SP2_OK                       # nothing to do, no launch
+    assert first(None) == _lib.SP2_ERR_INVALID_ARG
+    assert first(good, n=-1) == _lib.SP2_ERR_INVALID_ARG
+    assert first(good, eta=None) == _lib.SP2_ERR_INVALID_ARG     # gamma_l > 0 needs eta
+    assert "eta" in _lib.sp2_last_error()
+    for p in (_lib.nvt_params(0.0, 0.04), _lib.nvt_params(0.5, -1.0), _lib.nvt_params(0.5, 0.04, -1),
+              _lib.nvt_params(0.5, 0.04, 0.0, float("inf")), _lib.nvt_params(0.5, 0.04, scheme=2),
+              _lib.nvt_params(float("nan"), 0.04)):
+        assert first(p) == _lib.SP2_ERR_INVALID_ARG
+        assert lib.sp2_nvt_second_half(fake, fake, fake, 8, ctypes.byref(p), None) == \
+            _lib.SP2_ERR_INVALID_ARG
+    assert lib.sp2_nvt_second_half(None, fake, fake, 8, ctypes.byref(good), None) == \
+        _lib.SP2_ERR_INVALID_ARG

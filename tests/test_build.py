@@ -23,7 +23,7 @@ def test_every_kernel_present(resources):
     for k in ["k_gershgorin_rows", "k_bounds_final", "k_input_layer", "k_split", "k_sym_split",
               "k_sym_f32", "k_finish_loop", "k_split_tail", "k_mirror_upper", "k_lz_matvec",
               "k_lz_apply", "k_lz_bounds", "k_mulliken", "k_atom_matvec", "k_xl_step",
-              "k_xl_finish"]:
+              "k_xl_finish", "k_nvt_first", "k_nvt_second"]:
         assert k in names
 
 

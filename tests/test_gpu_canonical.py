@@ -1,0 +1,202 @@
+"""Canonical integration on the GPU (sp2_nvt_first_half / sp2_nvt_second_half,
+Section IV, Eq. 31-33) against the FP64 oracle (oracle/canonical.py).
+
+The step is elementwise FP64 arithmetic that both sides evaluate in the
+order of the formulas with correctly rounded operations (the kernels do not
+contract into fused multiply-adds), so single steps and harmonic
+trajectories (forces formed by the same two operations on both sides) are
+compared bit for bit.  Morse forces use torch's exp on the device and
+NumPy's on the host, so that trajectory is compared within 1e-9.  At size,
+2^20 independent Morse oscillators with Laplace force noise, started at
+rest, must sample the Boltzmann distribution (property test)."""
+
+import numpy as np
+import pytest
+
+from gpu_util import banner
+from oracle import canonical as C
+from workloads import AMU, KB_EV, canonical_noise, morse_energy, morse_force
+
+pytestmark = pytest.mark.gpu
+
+KT = 500.0 * KB_EV
+M7 = 7.0 * AMU
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import paper_2107_02737_amd as pk
+    pk.load_library()
+    return pk
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda")
+
+
+def _host(t):
+    return t.cpu().numpy()
+
+
+def _ulps(a, b):
+    ia = np.asarray(a, np.float64).view(np.int64)
+    ib = np.asarray(b, np.float64).view(np.int64)
+    return int(np.max(np.abs(ia - ib))) if ia.size else 0
+
+
+def _inputs(n, seed):
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal(n), 0.01 * rng.standard_normal(n), rng.standard_normal(n),
+            rng.standard_normal(n), rng.uniform(1.0, 16.0, n) * AMU, rng.standard_normal(n))
+
+
+CASES = [(0, 0.0, 0.0), (0, 0.05, 0.0), (0, 0.0, 1e-3), (0, 0.05, 1e-3),
+         (1, 0.05, 0.0), (1, 0.05, 1e-3), (1, 0.0, 1e-2)]
+
+
+@pytest.mark.parametrize("n", [1, 100003, 3 * 2 ** 21 + 7])
+@pytest.mark.parametrize("scheme,gamma_tc,gamma_l", CASES)
+def test_single_step_is_bitwise(pk, n, scheme, gamma_tc, gamma_l):
+    banner(f"nvt step n={n} scheme={scheme} gamma_tc={gamma_tc} gamma_l={gamma_l}")
+    r, v, f, eta, m, f1 = _inputs(n, seed=n % 97)
+    p = pk.nvt_params(0.5, KT, gamma_tc, gamma_l, scheme)
+    R, V = _dev(r), _dev(v)
+    pk.sp2_nvt_first_half(R, V, _dev(f), _dev(m), p, eta=_dev(eta))
+    r_ref, w_ref = C.first_half(r, v, f, eta, m, 0.5, KT, gamma_tc, gamma_l, scheme)
+    assert _ulps(_host(R), r_ref) == 0 and _ulps(_host(V), w_ref) == 0, \
+        (_ulps(_host(R), r_ref), _ulps(_host(V), w_ref))
+    pk.sp2_nvt_second_half(V, _dev(f1), _dev(m), p)
+    v_ref = C.second_half(w_ref, f1, m, 0.5, gamma_tc, scheme)
+    assert _ulps(_host(V), v_ref) == 0, _ulps(_host(V), v_ref)
+
+
+def test_empty_and_no_langevin_noise(pk):
+    import torch
+    banner("nvt n=0, eta omitted")
+    p = pk.nvt_params(0.5, KT, 0.05, 0.0, 0)
+    e = torch.empty(0, dtype=torch.float64, device="cuda")
+    pk.sp2_nvt_first_half(e, e, e, e, p)
+    pk.sp2_nvt_second_half(e, e, e, p)
+    r, v, f, _, m, _ = _inputs(1000, seed=3)
+    R, V = _dev(r), _dev(v)
+    pk.sp2_nvt_first_half(R, V, _dev(f), _dev(m), p)          # gamma_l = 0: no eta needed
+    r_ref, w_ref = C.first_half(r, v, f, np.zeros(1000), m, 0.5, KT, 0.05, 0.0, 0)
+    assert np.array_equal(_host(R), r_ref) and np.array_equal(_host(V), w_ref)
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_harmonic_trajectory_is_bitwise(pk, scheme):
+    import torch
+    banner(f"nvt harmonic trajectory scheme={scheme}")
+    n, steps, dt, kappa, sigma = 4099, 500, 0.5, 1.0, 0.1
+    gamma_tc = C.gamma_tc_from_noise(sigma, KT, dt)
+    assert pk.sp2_nvt_gamma_tc(sigma, KT, dt) == gamma_tc
+    rng = np.random.default_rng(5)
+    r0, v0 = 0.1 * rng.standard_normal(n), 0.005 * rng.standard_normal(n)
+    m = rng.uniform(1.0, 16.0, n) * AMU
+    eta, xi = canonical_noise(steps, n, seed=6)
+    p = pk.nvt_params(dt, KT, gamma_tc, 1e-3, scheme)
+    R, V, M = _dev(r0), _dev(v0), _dev(m)
+    ETA, XI = _dev(eta), _dev(xi)
+
+    def force(rt, k):
+        return rt * (-kappa) + XI[k] * sigma
+
+    F = force(R, 0)
+    for k in range(steps):
+        pk.sp2_nvt_first_half(R, V, F, M, p, eta=ETA[k])
+        F = force(R, k + 1)
+        pk.sp2_nvt_second_half(V, F, M, p)
+    torch.cuda.synchronize()
+    r_ref, v_ref = C.integrate(r0, v0, lambda x: -kappa * x, m, dt, KT, gamma_tc, 1e-3, steps,
+                               eta, xi, sigma, scheme)
+    assert _ulps(_host(R), r_ref) == 0 and _ulps(_host(V), v_ref) == 0
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_morse_trajectory_matches_oracle(pk, scheme):
+    import torch
+    banner(f"nvt Morse trajectory scheme={scheme}")
+    from workloads.canonical import MORSE_A, MORSE_D, MORSE_R0
+    n, steps, dt, sigma = 2048, 1000, 0.5, 0.1
+    gamma_tc = C.gamma_tc_from_noise(sigma, KT, dt)
+    rng = np.random.default_rng(8)
+    r0, v0 = MORSE_R0 + 0.1 * rng.standard_normal(n), 0.005 * rng.standard_normal(n)
+    m = np.full(n, M7)
+    eta, xi = canonical_noise(steps, n, seed=9)
+    p = pk.nvt_params(dt, KT, gamma_tc, 1e-3, scheme)
+    R, V, M, ETA, XI = _dev(r0), _dev(v0), _dev(m), _dev(eta), _dev(xi)
+
+    def force(rt, k):
+        x = torch.exp((rt - MORSE_R0) * (-MORSE_A))
+        return x * (1.0 - x) * (-2.0 * MORSE_D * MORSE_A) + XI[k] * sigma
+
+    F = force(R, 0)
+    for k in range(steps):
+        pk.sp2_nvt_first_half(R, V, F, M, p, eta=ETA[k])
+        F = force(R, k + 1)
+        pk.sp2_nvt_second_half(V, F, M, p)
+    r_ref, v_ref = C.integrate(r0, v0, morse_force, m, dt, KT, gamma_tc, 1e-3, steps, eta, xi,
+                               sigma, scheme)
+    print(f"  max |dR| {np.abs(_host(R) - r_ref).max():.2e}  max |dV| "
+          f"{np.abs(_host(V) - v_ref).max():.2e}", flush=True)
+    assert np.allclose(_host(R), r_ref, rtol=0, atol=1e-9)
+    assert np.allclose(_host(V), v_ref, rtol=0, atol=1e-11)
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_boltzmann_sampling_at_size(pk, scheme):
+    """2^20 Morse oscillators (M = 7 amu, T = 500 K, dt = 0.5 fs) with
+    Laplace force noise of 0.3 eV/A balanced by Eq. 33 and no Langevin
+    term, started at rest: the energy relaxes at the rate gamma_TC / M
+    (1/1.39 ps); after 8.6 relaxation times the positions and velocities
+    follow the Boltzmann distribution."""
+    import torch
+    banner(f"nvt Boltzmann sampling 2^20 scheme={scheme}")
+    from workloads.canonical import MORSE_A, MORSE_D, MORSE_R0
+    n, dt, sigma = 2 ** 20, 0.5, 0.3
+    gamma_tc = pk.sp2_nvt_gamma_tc(sigma, KT, dt)
+    p = pk.nvt_params(dt, KT, gamma_tc, 0.0, scheme)
+    g = torch.Generator(device="cuda").manual_seed(1234 + scheme)
+    R = torch.full((n,), MORSE_R0, dtype=torch.float64, device="cuda")
+    V = torch.zeros(n, dtype=torch.float64, device="cuda")
+    M = torch.full((n,), M7, dtype=torch.float64, device="cuda")
+
+    def force(rt):
+        u = torch.rand(n, dtype=torch.float64, device="cuda", generator=g) - 0.5
+        a = u.abs().clamp(max=0.5 - 2.0 ** -53)                           # rand() may give 0
+        lap = -torch.sign(u) * torch.log1p(-2.0 * a) / np.sqrt(2.0)        # unit variance
+        x = torch.exp((rt - MORSE_R0) * (-MORSE_A))
+        return x * (1.0 - x) * (-2.0 * MORSE_D * MORSE_A) + lap * sigma
+
+    F = force(R)
+    s1 = torch.zeros((), dtype=torch.float64, device="cuda")
+    s2 = torch.zeros_like(s1)
+    kin = torch.zeros_like(s1)
+    samples = 0
+    for k in range(32000):
+        pk.sp2_nvt_first_half(R, V, F, M, p)
+        F = force(R)
+        pk.sp2_nvt_second_half(V, F, M, p)
+        if k >= 24000 and k % 20 == 0:
+            s1 += R.sum()
+            s2 += (R * R).sum()
+            kin += (M * V * V).sum()
+            samples += 1
+        if k % 8000 == 0:
+            print(f"  step {k}", flush=True)
+    cnt = samples * n
+    mean = float(s1) / cnt
+    var = float(s2) / cnt - mean * mean
+    kin_t = float(kin) / cnt / KT
+    r = np.linspace(0.2, 6.0, 200001)
+    w = np.exp(-morse_energy(r) / KT)
+    z = np.trapezoid(w, r)
+    b_mean = np.trapezoid(r * w, r) / z
+    b_var = np.trapezoid((r - b_mean) ** 2 * w, r) / z
+    print(f"  mean {mean:.6f} (Boltzmann {b_mean:.6f})  var {var:.4e} ({b_var:.4e})  "
+          f"M<v^2>/kT {kin_t:.4f}", flush=True)
+    assert abs(mean - b_mean) < 0.01 * np.sqrt(b_var)
+    assert var == pytest.approx(b_var, rel=0.01)
+    assert kin_t == pytest.approx(1.0, abs=0.01)

@@ -109,7 +109,7 @@ def _boltzmann_moments(kt):
 def test_morse_well_with_laplace_noise_samples_boltzmann(scheme):
     rng = np.random.default_rng(11 + scheme)
     n, dt, sigma_tc = 4000, 0.5, 0.3
-    gamma_tc = C.gamma_tc_from_noise(sigma_tc, KT500, dt)   # relaxation M / gamma_TC ~ 1.4 ps
+    gamma_tc = C.gamma_tc_from_noise(sigma_tc, KT500, dt)   # energy relaxes in M / gamma_TC ~ 1.4 ps
     m = np.full(n, M7)
     r = np.full(n, 1.0)
     v = np.zeros(n)
