@@ -38,6 +38,8 @@ GOLDEN = os.path.join(ROOT, "tests", "golden", "water_m1024_seed0.npz")
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_sym_split_bf16x3_water6144_traffic.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2107_02737_amd", "csrc", f)
                   for f in ("sp2_common.hpp", "sp2_gemm.hpp")]
+NVT_PROFILE = os.path.join(ROOT, "profiles", "k_nvt_step_3x2e24coords.md")
+NVT_SOURCES = [os.path.join(ROOT, "paper_2107_02737_amd", "csrc", "sp2_nvt.hpp")]
 
 
 def parse():
@@ -84,23 +86,24 @@ def copy_calibration():
     print(json.dumps({"copy_calibration_bytes_per_launch": 4 * n, "launches": 3}), flush=True)
 
 
-def measured_traffic(precision):
-    """HBM bytes per layer launch from the committed counter summary
-    (FETCH_SIZE + WRITE_SIZE, calibrated against a plain copy), or None when
-    the summary is for another precision or the kernel source has changed
-    since the counters were taken."""
+def measured_traffic(precision, profile=TRAFFIC_PROFILE, sources=KERNEL_SOURCES,
+                     key="traffic_bytes_per_launch"):
+    """HBM bytes per launch from a committed counter summary (FETCH_SIZE +
+    WRITE_SIZE, calibrated against a plain copy), or None when the summary is
+    for another precision or the kernel source has changed since the
+    counters were taken."""
     import hashlib
-    if precision != "bf16x3" or not os.path.exists(TRAFFIC_PROFILE):
+    if precision != "bf16x3" or not os.path.exists(profile):
         return None
-    sha = hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SOURCES)).hexdigest()
+    sha = hashlib.sha256(b"".join(open(f, "rb").read() for f in sources)).hexdigest()
     fields = {}
-    for line in open(TRAFFIC_PROFILE):
+    for line in open(profile):
         if ":" in line and not line.startswith(("|", " ", "#")):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
-    if fields.get("kernel_source_sha256") != sha:
+    if fields.get("kernel_source_sha256") != sha or key not in fields:
         return None
-    return float(fields["traffic_bytes_per_launch"])
+    return float(fields[key])
 
 
 def trajectory(steps, precision, refine):
@@ -362,7 +365,10 @@ def canonical_step(pk, n, reps=20):
             "first_half_gbps": 56.0 * n / (t1 * 1e-6) / 1e9,
             "second_half_gbps": 32.0 * n / (t2 * 1e-6) / 1e9,
             "roofline": {"bound": "hbm", "achieved": gbps, "peak": 8000.0, "unit": "GB/s",
-                         "frac": gbps / 8000.0, "traffic": None,
+                         "frac": gbps / 8000.0,
+                         "traffic": measured_traffic("bf16x3", NVT_PROFILE, NVT_SOURCES,
+                                                     f"traffic_bytes_per_step_{n}")
+                         if n == 3 * 2 ** 24 else None,
                          "kernel": "k_nvt_first + k_nvt_second"},
             "water_box_step_us": w1 + w2}
 

@@ -1415,8 +1415,11 @@ sp2_status nvt_check(const sp2_nvt_params* p, int64_t n) {
   return SP2_OK;
 }
 
+// One coordinate per thread (all loads of a thread issued at once); the
+// kernels' grid-stride loop only runs past the first pass beyond 2^31 - 1
+// work-groups.
 int nvt_grid(int64_t n) {
-  return static_cast<int>(std::min<int64_t>(8192, (n + kNvtThreads - 1) / kNvtThreads));
+  return static_cast<int>(std::min<int64_t>(0x7fffffff, (n + kNvtThreads - 1) / kNvtThreads));
 }
 
 }  // namespace

@@ -14,7 +14,8 @@
 // (1 + gamma_TC h), gamma_TC a force per velocity.  Every operation is
 // written in the order of the formulas, without contraction into fused
 // multiply-adds, so the result is the correctly rounded evaluation of
-// exactly those formulas.
+// exactly those formulas.  Every array is streamed once: loads and stores
+// are non-temporal, and the launch gives each thread one coordinate.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -36,27 +37,29 @@ __global__ __launch_bounds__(kNvtThreads) void k_nvt_first(double* __restrict__ 
 #pragma clang fp contract(off)
   const int64_t stride = int64_t(gridDim.x) * kNvtThreads;
   for (int64_t i = int64_t(blockIdx.x) * kNvtThreads + threadIdx.x; i < n; i += stride) {
-    const double m = mass[i];
+    const double m = __builtin_nontemporal_load(mass + i);
+    const double v = __builtin_nontemporal_load(V + i);
+    const double f = __builtin_nontemporal_load(F + i);
+    const double r0 = __builtin_nontemporal_load(R + i);
     const double h = dt / (2.0 * m);
-    const double v = V[i];
     const double sigma_l = sqrt(kt * (1.0 - c_l * c_l) / m);
-    const double noise = eta ? sigma_l * eta[i] : 0.0;
+    const double noise = eta ? sigma_l * __builtin_nontemporal_load(eta + i) : 0.0;
     const double half = 0.5 * dt;
     double w;
     double r;
     if (scheme == 0) {
-      const double v1 = v + h * (F[i] - gamma_tc * v);      // V_{k+1/4}
-      r = R[i] + half * v1;                                 // R_{k+1/2}
+      const double v1 = v + h * (f - gamma_tc * v);         // V_{k+1/4}
+      r = r0 + half * v1;                                   // R_{k+1/2}
       w = c_l * v1 + noise;                                 // V_{k+3/4}
     } else {
       const double a = gamma_tc * dt / (2.0 * m);
       const double s = sqrt((1.0 - a) / (1.0 + a));        // sqrt(c_TC)
-      const double v1 = v + h * F[i];                       // V_{k+1/5}
-      r = R[i] + half * v1;                                 // R_{k+1/2}
+      const double v1 = v + h * f;                          // V_{k+1/5}
+      r = r0 + half * v1;                                   // R_{k+1/2}
       w = s * (c_l * (s * v1) + noise);                     // V_{k+4/5}
     }
-    R[i] = r + half * w;                                    // R_{k+1}
-    V[i] = w;
+    __builtin_nontemporal_store(r + half * w, R + i);       // R_{k+1}
+    __builtin_nontemporal_store(w, V + i);
   }
 }
 
@@ -68,9 +71,11 @@ __global__ __launch_bounds__(kNvtThreads) void k_nvt_second(double* __restrict__
 #pragma clang fp contract(off)
   const int64_t stride = int64_t(gridDim.x) * kNvtThreads;
   for (int64_t i = int64_t(blockIdx.x) * kNvtThreads + threadIdx.x; i < n; i += stride) {
-    const double m = mass[i];
-    const double kick = V[i] + dt / (2.0 * m) * F[i];
-    V[i] = scheme == 0 ? kick / (1.0 + gamma_tc * dt / (2.0 * m)) : kick;
+    const double m = __builtin_nontemporal_load(mass + i);
+    const double kick = __builtin_nontemporal_load(V + i) +
+                        dt / (2.0 * m) * __builtin_nontemporal_load(F + i);
+    __builtin_nontemporal_store(scheme == 0 ? kick / (1.0 + gamma_tc * dt / (2.0 * m)) : kick,
+                                V + i);
   }
 }
 
