@@ -341,12 +341,12 @@ def canonical_step(pk, n, reps=20):
         R, V, F, eta = rnd(1.0), rnd(0.01), rnd(1.0), rnd(1.0)
         M = torch.full((count,), 16.0 * AMU, dtype=torch.float64, device="cuda")
         for _ in range(3):
-            pk.sp2_nvt_first_half(R, V, F, M, p, eta=eta)
+            pk.sp2_nvt_first_half(R, V, F, eta, M, p)
             pk.sp2_nvt_second_half(V, F, M, p)
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
         ev[0].record()
         for _ in range(iters):
-            pk.sp2_nvt_first_half(R, V, F, M, p, eta=eta)
+            pk.sp2_nvt_first_half(R, V, F, eta, M, p)
         ev[1].record()
         for _ in range(iters):
             pk.sp2_nvt_second_half(V, F, M, p)

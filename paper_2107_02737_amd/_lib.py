@@ -384,8 +384,9 @@ def _nvt_vec(t, n, name):
     return c_void_p(t.data_ptr())
 
 
-def sp2_nvt_first_half(R, V, F, mass, params, eta=None):
-    """In place: R <- R_{k+1}, V <- the velocity before the last half kick."""
+def sp2_nvt_first_half(R, V, F, eta, mass, params):
+    """In place: R <- R_{k+1}, V <- the velocity before the last half kick.
+    ``eta`` may be None when the Langevin friction is 0."""
     n = R.numel()
     _check(load_library().sp2_nvt_first_half(
         _nvt_vec(R, n, "R"), _nvt_vec(V, n, "V"), _nvt_vec(F, n, "F"),

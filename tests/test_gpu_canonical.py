@@ -62,7 +62,7 @@ def test_single_step_is_bitwise(pk, n, scheme, gamma_tc, gamma_l):
     r, v, f, eta, m, f1 = _inputs(n, seed=n % 97)
     p = pk.nvt_params(0.5, KT, gamma_tc, gamma_l, scheme)
     R, V = _dev(r), _dev(v)
-    pk.sp2_nvt_first_half(R, V, _dev(f), _dev(m), p, eta=_dev(eta))
+    pk.sp2_nvt_first_half(R, V, _dev(f), _dev(eta), _dev(m), p)
     r_ref, w_ref = C.first_half(r, v, f, eta, m, 0.5, KT, gamma_tc, gamma_l, scheme)
     assert _ulps(_host(R), r_ref) == 0 and _ulps(_host(V), w_ref) == 0, \
         (_ulps(_host(R), r_ref), _ulps(_host(V), w_ref))
@@ -76,11 +76,11 @@ def test_empty_and_no_langevin_noise(pk):
     banner("nvt n=0, eta omitted")
     p = pk.nvt_params(0.5, KT, 0.05, 0.0, 0)
     e = torch.empty(0, dtype=torch.float64, device="cuda")
-    pk.sp2_nvt_first_half(e, e, e, e, p)
+    pk.sp2_nvt_first_half(e, e, e, None, e, p)
     pk.sp2_nvt_second_half(e, e, e, p)
     r, v, f, _, m, _ = _inputs(1000, seed=3)
     R, V = _dev(r), _dev(v)
-    pk.sp2_nvt_first_half(R, V, _dev(f), _dev(m), p)          # gamma_l = 0: no eta needed
+    pk.sp2_nvt_first_half(R, V, _dev(f), None, _dev(m), p)    # gamma_l = 0: no eta needed
     r_ref, w_ref = C.first_half(r, v, f, np.zeros(1000), m, 0.5, KT, 0.05, 0.0, 0)
     assert np.array_equal(_host(R), r_ref) and np.array_equal(_host(V), w_ref)
 
@@ -105,7 +105,7 @@ def test_harmonic_trajectory_is_bitwise(pk, scheme):
 
     F = force(R, 0)
     for k in range(steps):
-        pk.sp2_nvt_first_half(R, V, F, M, p, eta=ETA[k])
+        pk.sp2_nvt_first_half(R, V, F, ETA[k], M, p)
         F = force(R, k + 1)
         pk.sp2_nvt_second_half(V, F, M, p)
     torch.cuda.synchronize()
@@ -134,7 +134,7 @@ def test_morse_trajectory_matches_oracle(pk, scheme):
 
     F = force(R, 0)
     for k in range(steps):
-        pk.sp2_nvt_first_half(R, V, F, M, p, eta=ETA[k])
+        pk.sp2_nvt_first_half(R, V, F, ETA[k], M, p)
         F = force(R, k + 1)
         pk.sp2_nvt_second_half(V, F, M, p)
     r_ref, v_ref = C.integrate(r0, v0, morse_force, m, dt, KT, gamma_tc, 1e-3, steps, eta, xi,
@@ -176,7 +176,7 @@ def test_boltzmann_sampling_at_size(pk, scheme):
     kin = torch.zeros_like(s1)
     samples = 0
     for k in range(32000):
-        pk.sp2_nvt_first_half(R, V, F, M, p)
+        pk.sp2_nvt_first_half(R, V, F, None, M, p)
         F = force(R)
         pk.sp2_nvt_second_half(V, F, M, p)
         if k >= 24000 and k % 20 == 0:
