@@ -13,8 +13,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB_DIR = os.path.join(PKG, "lib")
 LIB_PATH = os.path.join(LIB_DIR, "libsp2.so")
-SOURCES = ["sp2_capi.hip"]
-HEADERS = ["sp2_common.hpp", "sp2_aux.hpp", "sp2_gemm.hpp"]
+SOURCES = ["sp2_capi.hip"]   # includes every csrc/*.hpp
 
 
 def hipcc():
