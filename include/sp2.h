@@ -83,7 +83,9 @@ typedef struct {
                                tape): sp2_jvp / sp2_vjp run the per-layer derivative
                                products S dS + dS S in the same BF16X3 split arithmetic as
                                the layers (one two-segment product [S|dS][dS|S]^T per layer)
-                               instead of FP32; the refinement's derivative stays FP32 */
+                               instead of FP32, and the refinement's derivative
+                               3M - (SM + MS) - (S^2 dS + dS S^2), M = S dS + dS S, in four
+                               BF16X3 products */
   int32_t bound_steps;      /* 0 (default): Gershgorin bounds.  k in SP2_MIN_BOUND_STEPS..
                                SP2_MAX_BOUND_STEPS: tighten them with k Lanczos steps (see
                                sp2_spectral_bounds) */

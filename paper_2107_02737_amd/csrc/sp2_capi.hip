@@ -1072,6 +1072,54 @@ sp2_status refine_derivative(const WS& w, const float* S, const float* D, float*
   return launch_f32(w, 4, A, B, e, make_decide(w, 0, 0), st);
 }
 
+// The same map in BF16X3 products (split derivatives): S given by its
+// planes in forward pair ps, D by its planes in derivative pair qd (its FP32
+// copy in work(qd) is overwritten).  Four products: M = SD + DS (planes in
+// derivative pair 1 - qd), S^2 (planes in forward pair 1 - ps),
+// T = 3M - (S^2 D + D S^2) into work(qd), out = T - (SM + MS).
+sp2_status refine_derivative_split(const WS& w, int ps, int qd, float* out, int64_t ld, int64_t n,
+                                   bool vec_ok, hipStream_t st) {
+  const int bf = split_code_of(SP2_BF16X3);
+  const Decide d0 = make_decide(w, 0, 0);
+  float* M = w.work(1 - qd);
+  float* T = w.work(qd);
+  sp2_status s;
+  {
+    Epi e = make_epi(w.L);
+    e.out = M;
+    e.split_out = bf;
+    e.hi_out = dhi(w, 1 - qd);
+    e.lo_out = dlo(w, 1 - qd);
+    if ((s = launch_split_pair(w, w.hi(ps), w.lo(ps), dhi(w, qd), dlo(w, qd), e, d0, st))) return s;
+  }
+  {
+    Epi e = make_epi(w.L);
+    e.out = w.slotf(3);
+    e.split_out = bf;
+    e.hi_out = w.hi(1 - ps);
+    e.lo_out = w.lo(1 - ps);
+    if ((s = launch_split(w, SP2_BF16X3, w.hi(ps), w.lo(ps), w.hi(ps), w.lo(ps), e, d0, st))) return s;
+  }
+  {
+    Epi e = make_epi(w.L);
+    e.c = M;
+    e.out = T;
+    e.alpha = -1.0f;
+    e.beta = 3.0f;
+    if ((s = launch_split_pair(w, w.hi(1 - ps), w.lo(1 - ps), dhi(w, qd), dlo(w, qd), e, d0, st)))
+      return s;
+  }
+  Epi e = make_epi(w.L);
+  e.c = T;
+  e.out = out;
+  e.ld_out = ld;
+  e.n_valid = static_cast<int>(n);
+  e.vec_ok = vec_ok;
+  e.alpha = -1.0f;
+  e.beta = 1.0f;
+  return launch_split_pair(w, w.hi(ps), w.lo(ps), dhi(w, 1 - qd), dlo(w, 1 - qd), e, d0, st);
+}
+
 // Bring checkpoint `slot` into the forward buffers as iterate S_c (FP32 at
 // dst, hi/lo planes in pair 0 for the split precisions).
 sp2_status load_checkpoint(const WS& w, int prec, int slot, float* dst, hipStream_t st) {
@@ -1121,7 +1169,12 @@ sp2_status jvp_run(const WS& w, const HostMirror* hm, const sp2_options& o, cons
   }
   const float* Y = w.work(nl & 1);
   if (o.refine != SP2_REFINE_NONE) {
-    if ((s = refine_derivative(w, s_f32(w, prec, nl), Y, P1, ld, n, vec_ok, st))) return s;
+    // S_nl's planes are in forward pair nl & 1, Y's in derivative pair nl & 1
+    if (sd)
+      s = refine_derivative_split(w, nl & 1, nl & 1, P1, ld, n, vec_ok, st);
+    else
+      s = refine_derivative(w, s_f32(w, prec, nl), Y, P1, ld, n, vec_ok, st);
+    if (s) return s;
   } else {
     k_copy_scaled<<<ew_grid(n * n), kEwThreads, 0, st>>>(Y, L.np, P1, ld, n, n, 1.0f, 0);
     LAUNCH_TRY();
@@ -1174,6 +1227,7 @@ sp2_status sp2_vjp(void* workspace, size_t ws_bytes, const float* W, int64_t ld,
   k_copy_scaled<<<ew_grid(L.np * L.np), kEwThreads, 0, st>>>(W, ld, w.work(0), L.np, n, L.np, 1.0f, 1);
   LAUNCH_TRY();
   int cur = 0;
+  const bool sd = split_derivatives(o);
   if (o.refine != SP2_REFINE_NONE) {
     // recompute S_L from its last checkpoint, then apply the refinement adjoint
     const int c = (nl / k) * k;
@@ -1182,11 +1236,16 @@ sp2_status sp2_vjp(void* workspace, size_t ws_bytes, const float* W, int64_t ld,
       if ((s = launch_layer(w, prec, m, 2, s_f32(w, prec, m), s_f32(w, prec, m + 1), (m - c) & 1,
                             (m - c + 1) & 1, nullptr, st, &o, 0)))
         return s;
-    if ((s = refine_derivative(w, s_f32(w, prec, nl), w.work(0), w.work(1), L.np, L.np, true, st)))
-      return s;
+    if (sd) {
+      // S_L's planes are in forward pair (nl - c) & 1; G's go to derivative pair 0
+      if ((s = split_derivative(w, w.work(0), 0, st))) return s;
+      s = refine_derivative_split(w, (nl - c) & 1, 0, w.work(1), L.np, L.np, true, st);
+    } else {
+      s = refine_derivative(w, s_f32(w, prec, nl), w.work(0), w.work(1), L.np, L.np, true, st);
+    }
+    if (s) return s;
     cur = 1;
   }
-  const bool sd = split_derivatives(o);
   if (sd && (s = split_derivative(w, w.work(cur), cur, st))) return s;
   const int nseg = (nl + k - 1) / k;
   for (int j = nseg - 1; j >= 0; --j) {
