@@ -308,6 +308,16 @@ def cpu_baseline(h32, n_occ, layers, n_iter_ref):
     t3 = time.perf_counter()
     oracle.density_matrix_eigh(h, n_occ)
     t_eigh = time.perf_counter() - t3
+    # sanity line: plain FP32 NumPy layers (SGEMM square, traces summed in FP64)
+    lo, hi = oracle.gershgorin_bounds(h)
+    x = ((hi * np.eye(h.shape[0]) - h) / (hi - lo)).astype(np.float32)
+    t4 = time.perf_counter()
+    for _ in range(layers):
+        t1_ = float(np.trace(x, dtype=np.float64))
+        t2_ = float(np.sum(x * x, dtype=np.float64))
+        x2 = x @ x
+        x = x2 if oracle.choose_branch(t1_, t2_, n_occ) > 0 else np.float32(2.0) * x - x2
+    t_fp32 = (time.perf_counter() - t4) / layers * n_iter_ref
     return {
         "value": 1.0 / t_solve,
         "unit": "solves/s",
@@ -319,6 +329,7 @@ def cpu_baseline(h32, n_occ, layers, n_iter_ref):
         "blas": blas,
         "host_cpus": os.cpu_count(),
         "eigh_seconds": t_eigh,
+        "fp32_numpy_sp2_seconds_per_solve": t_fp32,
     }
 
 
