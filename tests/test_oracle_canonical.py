@@ -12,6 +12,12 @@ results that do not come from the oracle itself:
   balanced by Eq. 33, kappa <R^2> = kT / (1 - kappa dt^2 / (4M)), the
   velocity-Verlet harmonic factor, for any noise level.  A factor-2 slip in
   Eq. 33 gives 0.5 instead;
+* force-free decay: without forces and noise one step multiplies V by the
+  friction factors, which must approximate the continuous decay
+  exp(-(gamma_L + gamma_TC / M) dt) to third order (they are its (1,1) Pade
+  approximants, error below (g dt)^3 / 12 per factor); the stationary tests
+  cannot see a wrong time scale, since c V + sqrt(kT (1 - c^2) / M) eta
+  keeps the Maxwell distribution for any c;
 * Morse well, Laplace-distributed force noise (the non-Gaussian case of
   Section IV), started at rest: after equilibration the sampled mean and
   variance of r and the kinetic temperature match the Boltzmann
@@ -95,6 +101,19 @@ def test_both_channels_together(scheme):
     conf, kin = _stationary(1.0, M7, dt, KT500, C.gamma_tc_from_noise(sigma_tc, KT500, dt), 1e-3,
                             sigma_tc, scheme)
     assert conf == pytest.approx(1.0, abs=2e-4) and kin == pytest.approx(1.0, abs=1e-3)
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+@pytest.mark.parametrize("gamma_l,gamma_tc", [(1e-3, 0.0), (2e-2, 0.0), (0.0, 5.0), (1e-2, 3.0)])
+def test_force_free_decay_follows_the_friction_rates(scheme, gamma_l, gamma_tc):
+    dt, m = 0.5, np.array([M7, 2.0 * AMU])
+    zero = np.zeros(2)
+    _, w = C.first_half(zero, np.ones(2), zero, zero, m, dt, KT500, gamma_tc, gamma_l, scheme)
+    factor = C.second_half(w, zero, m, dt, gamma_tc, scheme)
+    exact = np.exp(-(gamma_l + gamma_tc / m) * dt)
+    bound = ((gamma_l * dt) ** 3 + (gamma_tc / m * dt) ** 3) / 12.0 + 1e-15
+    assert np.all(np.abs(factor - exact) <= 1.01 * bound), (factor - exact, bound)
+    assert np.all(factor < 1.0) if gamma_l + gamma_tc > 0 else True
 
 
 def _boltzmann_moments(kt):
