@@ -205,6 +205,34 @@ def test_stop_rule_at_extreme_occupations(n_occ):
     assert hit
 
 
+def test_single_layer_rise_does_not_stop_the_network():
+    """Few occupied states: the error estimate of the exact-arithmetic
+    network rises for one layer inside the stagnation gate while the run is
+    still far from converged (0.1775, 0.0748, 0.0752, then falling), so a
+    stagnation test that compared one layer back would stop there; the rule
+    compares two layers back and runs on to the floor."""
+    w = np.concatenate([np.linspace(-3.0, -0.5, 5), np.linspace(0.5, 3.0, 95)])
+    _, rec = oracle.sp2_scalar(w, 5, -4.0, 4.0, tol=0.0, max_iter=80)
+    k = 15
+    assert rec.err[k - 1] < rec.err[k] < min(rec.err[k - 2], oracle.STALL_GATE)
+    assert abs(rec.t1[k] - 5) < 0.5
+    assert not oracle.should_stop(k, rec.err, abs(rec.t1[k] - 5), 0.0, 1, oracle.STALL_GATE)
+    _, r1 = oracle.sp2_scalar(w, 5, -4.0, 4.0, tol=1e-12, max_iter=80, stop_rule=1)
+    assert r1.converged and r1.err[-1] < 1e-12
+
+
+def test_vjp_of_nonsymmetric_weight_is_the_symmetric_gradient():
+    """The gradient of Tr(W P) over symmetric perturbations of H is symmetric
+    and depends on W only through sym(W)."""
+    h, _, _ = _c1(64, 32, seed=3)
+    _, rec = oracle.sp2(h, 32, tol=1e-12, refine=True)
+    wm = np.random.default_rng(8).standard_normal((64, 64))
+    g = oracle.sp2_vjp(h, wm, rec)
+    scale = np.abs(g).max()
+    assert np.allclose(g, g.T, rtol=0, atol=1e-13 * scale)
+    assert np.allclose(g, oracle.sp2_vjp(h, 0.5 * (wm + wm.T), rec), rtol=0, atol=1e-13 * scale)
+
+
 def test_mcweeny_acts_as_cubic_on_eigenvalues():
     rng = np.random.default_rng(2)
     q, _ = np.linalg.qr(rng.standard_normal((30, 30)))

@@ -61,6 +61,22 @@ def test_response_matches_finite_differences():
     assert abs(dq.sum()) <= 1e-12 * np.abs(dq).max()
 
 
+def test_jacobian_is_the_derivative_of_the_residual():
+    # J = d f / d n for f(n) = q0[n] - n, against central differences of f
+    mod, charges, h = _model()
+    n = h.shape[0]
+    jmat = xlbomd.jacobian(n, mod["atom_ptr"], mod["gamma"], xlbomd.dmpt_jvp(h, mod["n_occ"]))
+    v = np.random.default_rng(12).standard_normal(charges.size)
+    step = 1e-5
+
+    def f(c):
+        return xlbomd.residual(mod["h0"], mod["n_occ"], mod["atom_ptr"], mod["z"], mod["gamma"], c,
+                               charge_shifted_hamiltonian)
+
+    fd = (f(charges + step * v) - f(charges - step * v)) / (2 * step)
+    assert np.abs(jmat @ v - fd).max() <= 1e-7 * np.abs(fd).max()
+
+
 def test_full_rank_equals_dense_solve():
     mod, charges, h = _model()
     n = h.shape[0]
