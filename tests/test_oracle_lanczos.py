@@ -80,6 +80,23 @@ def test_bounds_enclose_the_spectrum_and_tighten_gershgorin(case, steps):
         assert hi - lo < 0.6 * (g_hi - g_lo)
 
 
+def test_full_reorthogonalisation_keeps_the_basis_orthonormal():
+    # 64 steps (the most the solver takes): with one Gram-Schmidt pass the
+    # basis drifts to ~1e-9 here as Ritz values converge; two passes stay
+    # orthonormal to rounding
+    h = random_orthogonal_hamiltonian(256, 128, seed=0)
+    _, _, v = lz.lanczos(h, 64, return_vectors=True)
+    assert np.abs(v.T @ v - np.eye(v.shape[1])).max() <= 1e-13
+
+
+def test_exact_gershgorin_interval_is_kept():
+    # diagonal H: the Gershgorin interval is the exact spectral range, so the
+    # widened Ritz interval is clipped back to it exactly
+    d = np.linspace(-2.0, 3.0, 200)
+    h = np.diag(np.random.default_rng(2).permutation(d))
+    assert lz.lanczos_bounds(h, 32) == oracle.gershgorin_bounds(h) == (-2.0, 3.0)
+
+
 def test_zero_steps_is_gershgorin():
     h = water_box_hamiltonian(20, seed=2)
     assert lz.lanczos_bounds(h, 0) == oracle.gershgorin_bounds(h)
