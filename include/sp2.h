@@ -8,7 +8,11 @@
  * Eq. 19 and Fig. 1): S_0 maps the spectrum of H linearly onto [0, 1] in
  * reverse order, and each layer is S_n = S_{n-1}^2 or 2 S_{n-1} - S_{n-1}^2.
  * The matrix squares run on MFMA matrix cores, optionally in the dual 16-bit
- * representation X = X0 + X1 of Eq. (20)-(22).
+ * representation X = X0 + X1 of Eq. (20)-(22).  Around the solver: its
+ * forward derivative and adjoint (sp2_jvp, sp2_vjp), the charge-space pieces
+ * of the XL-BOMD kernel K f (Section III, sp2_mulliken, sp2_xl_*) and one
+ * step of the canonical integration scheme that treats force noise as a
+ * heat bath (Section IV, sp2_nvt_*).
  *
  * Conventions shared by every entry point:
  *   - Matrix pointers are DEVICE pointers (HIP device memory) owned by the
