@@ -122,6 +122,46 @@ def test_jvp_and_vjp_match_oracle(pk, name, n, n_occ, precision, refine, tol, sp
     assert abs(lhs - rhs) <= tol * np.linalg.norm(w) * np.linalg.norm(j)
 
 
+@pytest.mark.parametrize("precision,tol,split", [("fp32", 1e-4, False), ("bf16x3", 1e-3, True)])
+def test_derivatives_with_lanczos_bounds(pk, precision, tol, split):
+    """The derivative holds the bounds the forward used: with 16 Lanczos
+    steps those are the tightened ones (checked against the oracle's
+    Lanczos bounds), and the network differentiated is the one they map."""
+    banner(f"jvp/vjp water N=300 {precision} bound_steps=16 split_derivatives={split}")
+    h32 = _hamiltonian("water")
+    n, n_occ = 300, 200
+    h64 = h32.astype(np.float64)
+    h1 = symmetric_normal(n, 2, std=1e-3).astype(np.float32)
+    w = symmetric_normal(n, 1).astype(np.float32)
+    P, info = pk.density(to_dev(h32), n_occ, precision=precision, refine="fp32",
+                         checkpoint_every=3, bound_steps=16, return_info=True,
+                         split_derivatives=split)
+    lo, hi = oracle.lanczos_bounds(h64, 16)
+    assert info["eps_min"] == pytest.approx(lo, abs=1e-9 * (hi - lo))
+    assert info["eps_max"] == pytest.approx(hi, abs=1e-9 * (hi - lo))
+    g_lo, g_hi = oracle.gershgorin_bounds(h64)
+    assert g_lo < info["eps_min"] and info["eps_max"] < g_hi
+    signs = [1 if b else -1 for b in info["branches"]]
+    rec = oracle.SP2Record(eps_min=info["eps_min"], eps_max=info["eps_max"], branches=signs,
+                           refine=True)
+    for k, (sign, s_k) in enumerate(zip(signs, oracle.sp2_oracle._replay(h64, rec))):
+        t1, t2 = float(np.trace(s_k)), float(np.sum(s_k * s_k))
+        if oracle.choose_branch(t1, t2, n_occ) != sign:
+            assert abs(abs(t2 - n_occ) - abs(2 * t1 - t2 - n_occ)) <= MARGIN[precision] * n, k
+    P1 = to_dev(np.zeros((n, n)))
+    pk.sp2_jvp(info["workspace"], to_dev(h1), P1)
+    G = to_dev(np.zeros((n, n)))
+    pk.sp2_vjp(info["workspace"], to_dev(w), G)
+    j, g = to_host(P1), to_host(G)
+    j_ref = oracle.sp2_jvp(h64, h1.astype(np.float64), rec)
+    g_ref = oracle.sp2_vjp(h64, w.astype(np.float64), rec)
+    j_dm = oracle.dmpt_response(h64, n_occ, h1.astype(np.float64))
+    print(f"  n_iter={info['n_iter']} jvp rel={_rel(j, j_ref):.2e} vjp rel={_rel(g, g_ref):.2e} "
+          f"vs DMPT {_rel(j, j_dm):.2e}", flush=True)
+    assert _rel(j, j_ref) <= tol and _rel(g, g_ref) <= tol
+    assert _rel(j, j_dm) <= max(tol, _rel(j_ref, j_dm) + tol)
+
+
 def test_vjp_equals_jvp_and_checkpoint_independence(pk):
     import torch
     banner("vjp == jvp; checkpoint spacing")
