@@ -158,6 +158,15 @@ __device__ __forceinline__ int decide_layer(const Decide& d, double* red) {
   return stop ? 0 : sign;
 }
 
+// The decision of a layer as recorded by that layer's product launch, for a
+// kernel that follows it on the stream: 0 once the network has stopped.
+__device__ __forceinline__ int recorded_branch(const Decide& d) {
+  if (d.mode == 2) return d.hist->branch[d.layer];
+  if (d.mode != 1) return 1;
+  if (__atomic_load_n(&d.ctrl->stopped, __ATOMIC_RELAXED)) return 0;
+  return d.hist->branch[d.layer];
+}
+
 // ---------------------------------------------------------------------------
 // 16-bit dual representation X = X0 + X1 (Eq. 20-21), round to nearest even.
 // ---------------------------------------------------------------------------

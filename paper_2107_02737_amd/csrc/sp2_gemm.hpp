@@ -153,7 +153,7 @@ __device__ __forceinline__ void store_planes8(const Epi& p, int64_t o, const flo
 template <int H>
 __device__ __forceinline__ void epilogue_passes(const Epi& p, float as, float beta, int ti, int tj,
                                                 int hr, float* img, double& t1, double& t2) {
-  static_assert(H == 32 || H == 128, "image height");
+  static_assert(H == 16 || H == 32 || H == 128, "image height");
   constexpr int BM = 256, S = kEpiLd, G = BM / H;
   const int64_t np = p.np;
   const bool diag = ti == tj;
@@ -566,20 +566,20 @@ void k_sym_split(SplitArgs p) {
 }
 
 // ---------------------------------------------------------------------------
-// Split-K tail of k_sym_split, spread over the machine: work-group
-// (tail tile, strip) sums the nsplit stored pieces of 32 rows of the tile in
-// piece order (so the result does not depend on which piece finished last)
-// and runs the epilogue passes on that strip.  Strip s holds rows
-// 32 s .. 32 s + 31, i.e. accumulator block mi = s % 4 of the two waves with
-// wm = s / 4.  Trace partials go to parts_out[nfull + 8 * tail + s].
+// Split-K tail of k_sym_split and k_sym_f32, spread over the machine:
+// work-group (tail tile, strip s) sums the nsplit stored pieces of rows
+// 16 s .. 16 s + 15 of the tile in piece order (so the result does not depend
+// on which piece finished last) and runs the epilogue passes on that strip;
+// 16 strips per tile keep the work-groups many and small enough to spread
+// evenly over the CUs.  The branch is the one the layer's product launch
+// recorded.  Trace partials go to parts_out[nfull + 16 * tail + s].
 // ---------------------------------------------------------------------------
-constexpr int kTailStrips = 8;
-
+constexpr int kTailStrips = 16;
 __global__ __launch_bounds__(256) void k_split_tail(SplitArgs p) {
-  constexpr int NT = 256, H = 32, S = kEpiLd, NI = 4;
+  constexpr int NT = 256, H = 16, S = kEpiLd, NI = 4;
   __shared__ float img[H * S];
   __shared__ double red[2 * (NT / kWave)];
-  const int sign = decide_layer<NT>(p.dec, red);
+  const int sign = recorded_branch(p.dec);
   if (sign == 0) return;
   float alpha = p.epi.alpha, beta = p.epi.beta;
   if (p.dec.mode != 0) {
@@ -591,37 +591,41 @@ __global__ __launch_bounds__(256) void k_split_tail(SplitArgs p) {
   const int tile = dc.nfull + tail;
   int ti, tj;
   tile_of(tile, dc.nb, dc.band, ti, tj);
-  const int wm = s / 4, mi = s % 4, t = threadIdx.x;
-  // item j = t + 256 k (k = 0..7): wave wn = j / 1024, block (ni, r4) =
-  // (j % 1024) / 64, lane j % 64 -- consecutive threads read consecutive
-  // 16-byte pieces of a piece's accumulator.
-  f32x4 sum[8];
+  // Strip s lies in the 128-row half wm = s / 8, 32-row block mi = (s / 2) % 4,
+  // accumulator rows 8 r4 + 4 (lane / 32) + e of that block with
+  // r4 in {2 hf, 2 hf + 1}, hf = s % 2.  Item j = t + 256 k (k = 0..3): wave
+  // wn = j / 512, block (ni, r4 - 2 hf) = (j % 512) / 64, lane j % 64 --
+  // consecutive threads read consecutive 16-byte pieces of an accumulator.
+  const int wm = s >> 3, mi = (s >> 1) & 3, hf = s & 1, t = threadIdx.x;
+  int off[4];
 #pragma clang loop unroll(full)
-  for (int k = 0; k < 8; ++k) sum[k] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int k = 0; k < 4; ++k) {
+    const int j = t + 256 * k, wn = j >> 9, blk = (j & 511) >> 6, ln = j & 63;
+    const int v = (mi * NI + (blk >> 1)) * 4 + 2 * hf + (blk & 1);
+    off[k] = (v * NT + (2 * wm + wn) * kWave + ln) * 4;
+  }
+  f32x4 sum[4];
+#pragma clang loop unroll(full)
+  for (int k = 0; k < 4; ++k) sum[k] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
   for (int q = 0; q < dc.nsplit; ++q) {
     const float* src = dc.partial + (int64_t(tail) * dc.nsplit + q) * (NT * 4 * NI * 16);
-    f32x4 x[8];
+    f32x4 x[4];
 #pragma clang loop unroll(full)
-    for (int k = 0; k < 8; ++k) {
-      const int j = t + 256 * k, wn = j >> 10, blk = (j & 1023) >> 6, ln = j & 63;
-      const int v = mi * NI * 4 + blk;
-      const int tid = (2 * wm + wn) * kWave + ln;
-      x[k] = *reinterpret_cast<const f32x4*>(src + (int64_t(v) * NT + tid) * 4);
-    }
+    for (int k = 0; k < 4; ++k) x[k] = *reinterpret_cast<const f32x4*>(src + off[k]);
 #pragma clang loop unroll(full)
-    for (int k = 0; k < 8; ++k) sum[k] += x[k];
+    for (int k = 0; k < 4; ++k) sum[k] += x[k];
   }
 #pragma clang loop unroll(full)
-  for (int k = 0; k < 8; ++k) {
-    const int j = t + 256 * k, wn = j >> 10, blk = (j & 1023) >> 6, ln = j & 63;
-    const int ni = blk >> 2, r4 = blk & 3;
-    const int col = wn * 128 + ni * 32 + (ln & 31);
+  for (int k = 0; k < 4; ++k) {
+    const int j = t + 256 * k, wn = j >> 9, blk = (j & 511) >> 6, ln = j & 63;
+    const int col = wn * 128 + (blk >> 1) * 32 + (ln & 31);
+    const int row = 8 * (blk & 1) + 4 * (ln >> 5);
 #pragma clang loop unroll(full)
-    for (int e = 0; e < 4; ++e) img[(8 * r4 + 4 * (ln >> 5) + e) * S + col] = sum[k][e];
+    for (int e = 0; e < 4; ++e) img[(row + e) * S + col] = sum[k][e];
   }
   __syncthreads();
   double t1 = 0.0, t2 = 0.0;
-  epilogue_passes<H>(p.epi, alpha * p.epi.oscale, beta, ti, tj, 32 * s, img, t1, t2);
+  epilogue_passes<H>(p.epi, alpha * p.epi.oscale, beta, ti, tj, H * s, img, t1, t2);
   if (p.epi.parts_out) {
     block_sum2<NT>(t1, t2, red);
     if (threadIdx.x == 0) {
