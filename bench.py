@@ -387,8 +387,8 @@ def canonical_step(pk, n, reps=20):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver has no "
-              "multi-GPU path in this build.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the solver has no "
+              "multi-GPU path.", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
