@@ -53,7 +53,12 @@ sp2_status fail(sp2_status s, const char* fmt, ...) {
 
 constexpr int64_t kPad = 256;          // matrices are padded to a multiple of this
 constexpr int kBand = 4;               // tile-rows per band of the tile schedule
-constexpr int kChunk = 8;              // layers launched between stop-flag polls
+// Layers launched between stop-flag polls: 8, or 2 once a layer is long
+// (np >= 4096: ~0.5 ms and more), so that few launches run after the stop
+// while the queued chunk still covers the host's poll.
+constexpr int kChunk = 8;
+constexpr int kChunkLarge = 2;
+constexpr int64_t kChunkLargeNp = 4096;
 constexpr int kInitBlocksMax = 1024;   // partial pairs written by the input layer
 constexpr size_t kPartialBytes = size_t(64) << 20;   // split-K tail accumulators
 constexpr int kMaxTailTiles = 1024;                   // split-K tail tiles per launch
@@ -721,7 +726,7 @@ sp2_status sp2_density_ex(const float* H, int64_t n, int64_t ld, int64_t n_occ,
   bool stopped = false;
   sp2_status err = SP2_OK;
   while (!stopped && launched < o.max_iter && err == SP2_OK) {
-    const int end = std::min(o.max_iter, launched + kChunk);
+    const int end = std::min(o.max_iter, launched + (L.np >= kChunkLargeNp ? kChunkLarge : kChunk));
     for (int k = launched; k < end && err == SP2_OK; ++k) {
       const float* src = s_f32(w, prec, k);
       float* dst = s_f32(w, prec, k + 1);

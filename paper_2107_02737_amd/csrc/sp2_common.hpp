@@ -128,16 +128,18 @@ __device__ __forceinline__ int decide_layer(const Decide& d, double* red) {
   if (d.mode == 2) return d.hist->branch[d.layer];
   if (d.mode != 1) return 1;
   // One read of the stop flag per work-group, shared through LDS, so that
-  // all of its waves take the same exit.
+  // all of its waves take the same exit -- before the partial sums, so that
+  // launches queued after the stop leave at once.
   __shared__ int s_stopped;
   if (threadIdx.x == 0) s_stopped = __atomic_load_n(&d.ctrl->stopped, __ATOMIC_RELAXED);
+  __syncthreads();
+  if (s_stopped) return 0;
   double t1 = 0.0, t2 = 0.0;
   for (int i = threadIdx.x; i < d.nparts_in; i += NT) {
     t1 += d.parts_in[2 * i];
     t2 += d.parts_in[2 * i + 1];
   }
-  block_sum2<NT>(t1, t2, red);   // its barriers publish s_stopped
-  if (s_stopped) return 0;
+  block_sum2<NT>(t1, t2, red);
   const int n = d.layer;
   const double e = fabs(t1 - t2);
   const bool stop = stop_test(t1, e, n, d.hist->err, d.n_occ, d.tol, d.stop_rule, d.stall_gate);
