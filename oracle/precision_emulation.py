@@ -8,6 +8,14 @@ against the exact density matrix, from which the end-to-end test
 tolerances are derived.  The accumulation order differs from the GPU's
 MFMA, so agreement with the GPU is statistical, not bitwise
 (parity unpinned for bitwise equality).
+
+Pins (tests/test_oracle_emulation.py): on operands exactly representable in
+each mode, ``square_emulated`` equals the exact FP64 sum of the products of
+Eq. (22) (with the 2^-28 rescale for the scaled FP16 pair; X0 X0 alone for the
+single pass); ``automatic_stall_gate`` against closed forms;
+``sp2_emulated("fp32")`` bitwise against a plain FP32 loop written out in
+the test; every mode's error against the exact density matrix within
+[1/64, 2] of its operand roundoff times the Gershgorin width.
 """
 
 from __future__ import annotations
