@@ -141,7 +141,11 @@ sp2_status sp2_density(const float* H, int64_t n, int64_t n_occ, double tol, flo
 /* Full form of sp2_density: leading dimension ld for H and P, explicit
  * options (NULL = defaults; opt->tol is used), and an info record (may be
  * NULL).  With opt->checkpoint_every > 0 the workspace keeps the tape used
- * by sp2_jvp / sp2_vjp until the next call on the same workspace. */
+ * by sp2_jvp / sp2_vjp (and the spectral bounds of the recorded network)
+ * until the next call on the same workspace.  The tape is kept only for a
+ * converged solve: after SP2_ERR_NOT_CONVERGED the derivative entry points
+ * return SP2_ERR_TAPE.  sp2_bounds, sp2_spectral_bounds and sp2_layer on the
+ * same workspace drop it as well. */
 sp2_status sp2_density_ex(const float* H, int64_t n, int64_t ld, int64_t n_occ,
                           const sp2_options* opt, float* P, sp2_info* info,
                           uint8_t* branches, int32_t branches_cap,
@@ -155,7 +159,8 @@ sp2_status sp2_density_ex(const float* H, int64_t n, int64_t ld, int64_t n_occ,
  * recomputed forward iterates; the refinement contributes its own
  * derivative.  The derivative products run in FP32 MFMA.  H1 (symmetric) and
  * P1: n x n with leading dimension ld.  Returns SP2_ERR_TAPE when the
- * forward call kept no tape. */
+ * workspace holds no usable tape (the forward kept none, did not converge,
+ * or another call has reused the workspace since). */
 sp2_status sp2_jvp(void* workspace, size_t ws_bytes, const float* H1, int64_t ld, float* P1,
                    void* stream);
 
@@ -213,6 +218,21 @@ sp2_status sp2_split(const float* X, int64_t n, int64_t ld, int32_t precision,
  * until done. */
 sp2_status sp2_layer(const float* X, int64_t n, int64_t ld, int32_t precision, int32_t sign,
                      float* Y, void* workspace, size_t ws_bytes, void* stream);
+
+/* Per-layer trace history of the last sp2_density_ex / sp2_density call on
+ * this workspace: the traces of every examined approximation S_k, which
+ * decide each branch and the stop (Section II.D-E: idempotency estimated
+ * from traces), for k = 0 .. n_iter:
+ *   t1[k] = Tr S_k, t2[k] = ||S_k||_F^2 (= Tr S_k^2), err[k] = |t1[k] - t2[k]|,
+ * FP64 sums over the FP32 iterate as the layer kernels formed them.  Host
+ * arrays of `cap` entries (any of them may be NULL; all NULL only with
+ * cap = 0); min(cap, n_iter + 1) entries are written and *count (may be
+ * NULL) receives n_iter + 1.  After a trivial occupation (n_occ in {0, n}),
+ * a bound error, or another call that reuses the workspace (sp2_bounds,
+ * sp2_spectral_bounds, sp2_layer), the history holds one meaningless entry.
+ * Blocks until the copy is done. */
+sp2_status sp2_history(void* workspace, size_t ws_bytes, int32_t cap, double* t1, double* t2,
+                       double* err, int32_t* count, void* stream);
 
 /* ---- XL-BOMD kernel building block (Section III, Eq. 27-28) ----------------
  * Extended-Lagrangian dynamics propagates one net charge n_I per atom and

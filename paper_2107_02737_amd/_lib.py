@@ -41,7 +41,8 @@ SP2_MAX_ITER = 256
 EXPORTED = ["sp2_default_options", "sp2_workspace_bytes", "sp2_density", "sp2_density_ex",
             "sp2_jvp", "sp2_vjp", "sp2_bounds", "sp2_spectral_bounds", "sp2_split", "sp2_layer",
             "sp2_mulliken", "sp2_xl_scratch_bytes", "sp2_xl_response", "sp2_xl_kernel",
-            "sp2_nvt_gamma_tc", "sp2_nvt_first_half", "sp2_nvt_second_half", "sp2_last_error"]
+            "sp2_nvt_gamma_tc", "sp2_nvt_first_half", "sp2_nvt_second_half", "sp2_last_error",
+            "sp2_history"]
 SP2_XL_MAX_RANK = 32
 
 
@@ -128,6 +129,8 @@ def load_library(path=None):
     lib.sp2_nvt_first_half.restype = c_int32
     lib.sp2_nvt_second_half.argtypes = [vp, vp, vp, c_int64, ctypes.POINTER(sp2_nvt_params), vp]
     lib.sp2_nvt_second_half.restype = c_int32
+    lib.sp2_history.argtypes = [vp, c_size_t, c_int32, vp, vp, vp, ctypes.POINTER(c_int32), vp]
+    lib.sp2_history.restype = c_int32
     lib.sp2_last_error.argtypes = []
     lib.sp2_last_error.restype = ctypes.c_char_p
     _LIB = lib
@@ -283,6 +286,19 @@ def sp2_layer(X, precision, sign, Y, workspace):
                          _dev_ptr(Y, name="Y"), c_void_p(workspace.data_ptr()), workspace.numel(),
                          _stream(X.device)))
     return Y
+
+
+def sp2_history(workspace, cap=SP2_MAX_ITER + 1):
+    """Per-layer traces of the last solve on ``workspace``: a dict of lists
+    ``t1`` (Tr S_k), ``t2`` (||S_k||_F^2) and ``err`` (|t1 - t2|) for
+    k = 0 .. n_iter."""
+    lib = load_library()
+    t1, t2, err = (c_double * cap)(), (c_double * cap)(), (c_double * cap)()
+    cnt = c_int32(0)
+    _check(lib.sp2_history(c_void_p(workspace.data_ptr()), workspace.numel(), int(cap), t1, t2,
+                           err, ctypes.byref(cnt), _stream(workspace.device)))
+    m = min(cnt.value, cap)
+    return {"t1": list(t1[:m]), "t2": list(t2[:m]), "err": list(err[:m])}
 
 
 def sp2_last_error():

@@ -65,7 +65,11 @@ constexpr int kMaxTailTiles = 1024;                   // split-K tail tiles per 
 
 int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
-// Tape description kept in the workspace for sp2_jvp / sp2_vjp.
+// Tape description kept in the workspace for sp2_jvp / sp2_vjp.  The
+// bounds of the recorded network are copied here when the forward call
+// seals the tape, so that a later bound computation on the same workspace
+// (which rewrites the control block) cannot rescale the derivative; such
+// calls also clear `valid`.
 struct Meta {
   int64_t n, np;
   int32_t precision, refine, every, n_iter;
@@ -73,6 +77,7 @@ struct Meta {
   int32_t max_iter;
   int32_t flags;       // options flags of the forward call (SP2_FLAG_SPLIT_DERIVATIVES)
   int32_t reserved;
+  double eps_min, eps_max, inv_range;   // spectral bounds of the recorded network
   int64_t magic;
 };
 constexpr int64_t kMetaMagic = 0x5350324d45544131LL;
@@ -540,6 +545,20 @@ int ew_grid(int64_t elems) {
 
 __global__ void k_write_meta(Meta* m, Meta v) { *m = v; }
 
+// Seal the tape of a finished forward call: the description `v` with the
+// bounds the input layer used, usable only for a converged, non-degenerate
+// network (the derivative of an unconverged one is not that of P).
+__global__ void k_seal_tape(Meta* m, Meta v, const Ctrl* c) {
+  v.eps_min = c->eps_min;
+  v.eps_max = c->eps_max;
+  v.inv_range = c->inv_range;
+  if (v.valid == 1 && !(c->converged && !c->degenerate)) v.valid = 0;
+  *m = v;
+}
+
+// A call that reuses the workspace header for other work drops the tape.
+__global__ void k_drop_tape(Meta* m) { m->valid = 0; }
+
 // Timing events for SP2_FLAG_TIME_LAYERS: a start and an end event around
 // every layer launch and around the refinement.
 struct LayerTimer {
@@ -674,7 +693,7 @@ sp2_status sp2_density_ex(const float* H, int64_t n, int64_t ld, int64_t n_occ,
   sp2_status s;
 
   {
-    Meta none{n, L.np, prec, o.refine, 0, 0, 0, o.max_iter, 0, 0, kMetaMagic};
+    Meta none{n, L.np, prec, o.refine, 0, 0, 0, o.max_iter, 0, 0, 0.0, 0.0, 0.0, kMetaMagic};
     k_write_meta<<<1, 1, 0, st>>>(w.meta, none);
     LAUNCH_TRY();
   }
@@ -694,8 +713,9 @@ sp2_status sp2_density_ex(const float* H, int64_t n, int64_t ld, int64_t n_occ,
     if ((s = read_back(w, hm, false, st))) return s;
     if (hm->ctrl[0].nonfinite) return fail(SP2_ERR_NONFINITE, "H holds NaN or Inf");
     if (o.checkpoint_every > 0) {
-      Meta m{n, L.np, prec, o.refine, o.checkpoint_every, 0, 2, o.max_iter, o.flags, 0, kMetaMagic};
-      k_write_meta<<<1, 1, 0, st>>>(w.meta, m);
+      Meta m{n, L.np, prec, o.refine, o.checkpoint_every, 0, 2, o.max_iter, o.flags, 0,
+             0.0, 0.0, 0.0, kMetaMagic};
+      k_seal_tape<<<1, 1, 0, st>>>(w.meta, m, w.ctrl);
       LAUNCH_TRY();
     }
     if (info) {
@@ -806,9 +826,9 @@ sp2_status sp2_density_ex(const float* H, int64_t n, int64_t ld, int64_t n_occ,
     LAUNCH_TRY();
   }
   if (o.checkpoint_every > 0) {
-    Meta m{n, L.np, prec, o.refine, o.checkpoint_every, n_iter, hm->ctrl[0].degenerate ? 0 : 1,
-           o.max_iter, o.flags, 0, kMetaMagic};
-    k_write_meta<<<1, 1, 0, st>>>(w.meta, m);
+    Meta m{n, L.np, prec, o.refine, o.checkpoint_every, n_iter, 1, o.max_iter, o.flags, 0,
+           0.0, 0.0, 0.0, kMetaMagic};
+    k_seal_tape<<<1, 1, 0, st>>>(w.meta, m, w.ctrl);
     LAUNCH_TRY();
   }
   if ((s = read_back(w, hm, true, st))) return s;
@@ -868,6 +888,8 @@ sp2_status sp2_bounds(const float* H, int64_t n, int64_t ld, double* eps_min, do
   hipStream_t st = static_cast<hipStream_t>(stream);
   WS w;
   bind(w, workspace, L);
+  k_drop_tape<<<1, 1, 0, st>>>(w.meta);
+  LAUNCH_TRY();
   k_gershgorin_rows<<<L.gersh_blocks, kRowThreads, 0, st>>>(H, n, ld, w.gersh);
   LAUNCH_TRY();
   k_bounds_final<<<1, 256, 0, st>>>(w.gersh, L.gersh_blocks, w.ctrl, 1);
@@ -900,6 +922,8 @@ sp2_status sp2_spectral_bounds(const float* H, int64_t n, int64_t ld, int32_t st
   hipStream_t st = static_cast<hipStream_t>(stream);
   WS w;
   bind(w, workspace, L);
+  k_drop_tape<<<1, 1, 0, st>>>(w.meta);
+  LAUNCH_TRY();
   k_gershgorin_rows<<<L.gersh_blocks, kRowThreads, 0, st>>>(H, n, ld, w.gersh);
   LAUNCH_TRY();
   k_bounds_final<<<1, 256, 0, st>>>(w.gersh, L.gersh_blocks, w.ctrl, 1);
@@ -942,6 +966,8 @@ sp2_status sp2_layer(const float* X, int64_t n, int64_t ld, int32_t precision, i
   hipStream_t st = static_cast<hipStream_t>(stream);
   WS w;
   bind(w, workspace, L);
+  k_drop_tape<<<1, 1, 0, st>>>(w.meta);
+  LAUNCH_TRY();
   float* Xp = w.slotf(0);
   k_copy_scaled<<<ew_grid(L.np * L.np), kEwThreads, 0, st>>>(X, ld, Xp, L.np, n, L.np, 1.0f, 0);
   LAUNCH_TRY();
@@ -966,6 +992,32 @@ sp2_status sp2_layer(const float* X, int64_t n, int64_t ld, int32_t precision, i
   }
   if (s) return s;
   HIP_TRY(hipStreamSynchronize(st));
+  return SP2_OK;
+}
+
+sp2_status sp2_history(void* workspace, size_t ws_bytes, int32_t cap, double* t1, double* t2,
+                       double* err, int32_t* count, void* stream) {
+  g_err.clear();
+  if (cap < 0 || (cap > 0 && !t1 && !t2 && !err)) return fail(SP2_ERR_INVALID_ARG, "bad cap or outputs");
+  sp2_options d;
+  sp2_default_options(&d);
+  Layout L0;
+  make_layout(256, d, L0);   // header offsets do not depend on n
+  if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 || ws_bytes < L0.off_meta)
+    return fail(SP2_ERR_WORKSPACE, "workspace missing, misaligned or too small");
+  HostMirror* hm;
+  if (sp2_status s = host_mirror(&hm)) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  WS w;
+  bind(w, workspace, L0);
+  if (sp2_status s = read_back(w, hm, true, st)) return s;
+  const int32_t nk = std::min(std::max(hm->ctrl[0].n_iter, 0), kMaxIter) + 1;
+  for (int32_t k = 0; k < std::min(nk, cap); ++k) {
+    if (t1) t1[k] = hm->hist.t1[k];
+    if (t2) t2[k] = hm->hist.t2[k];
+    if (err) err[k] = hm->hist.err[k];
+  }
+  if (count) *count = nk;
   return SP2_OK;
 }
 
@@ -1151,7 +1203,7 @@ sp2_status jvp_run(const WS& w, const HostMirror* hm, const sp2_options& o, cons
   }
   const int prec = o.precision;
   const int nl = hm->meta.n_iter;
-  const float inv = static_cast<float>(hm->ctrl[0].inv_range);
+  const float inv = static_cast<float>(hm->meta.inv_range);
   // dS_0 = -H1 / (eps_max - eps_min)  (H1 symmetrised)
   k_copy_scaled<<<ew_grid(L.np * L.np), kEwThreads, 0, st>>>(H1, ld, w.work(0), L.np, n, L.np, -inv, 1);
   LAUNCH_TRY();
@@ -1226,7 +1278,7 @@ sp2_status sp2_vjp(void* workspace, size_t ws_bytes, const float* W, int64_t ld,
   const int prec = o.precision;
   const int nl = hm->meta.n_iter;
   const int k = L.every;
-  const float inv = static_cast<float>(hm->ctrl[0].inv_range);
+  const float inv = static_cast<float>(hm->meta.inv_range);
   sp2_status s;
   // G_L = sym(W)
   k_copy_scaled<<<ew_grid(L.np * L.np), kEwThreads, 0, st>>>(W, ld, w.work(0), L.np, n, L.np, 1.0f, 1);

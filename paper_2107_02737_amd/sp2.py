@@ -29,7 +29,7 @@ def _as_matrix(H, symmetrize):
 def density(H, n_occ, tol=1e-5, precision="bf16x3", refine="fp32", max_iter=100, stop_rule=1,
             stall_gate=-1.0, checkpoint_every=0, symmetrize=False, return_info=False,
             workspace=None, time_layers=False, bound_steps=0, bound_seed=0,
-            split_derivatives=False):
+            split_derivatives=False, allow_unconverged=False):
     """Density matrix of the symmetric ``H`` with ``n_occ`` occupied states.
 
     Returns ``P`` (FP32, same device), or ``(P, info)`` with ``info`` holding
@@ -37,6 +37,10 @@ def density(H, n_occ, tol=1e-5, precision="bf16x3", refine="fp32", max_iter=100,
     ``idem_err``, ``status`` and the ``branches`` string (1 = S^2).
     ``split_derivatives`` (BF16X3 with a tape) runs the JVP/VJP layer
     products in BF16X3 instead of FP32.
+
+    A solve that does not meet the stop test raises ``SP2Error``
+    (``SP2_ERR_NOT_CONVERGED``) unless ``allow_unconverged``; then the last
+    iterate is returned, and the workspace holds no derivative tape.
     """
     H = _as_matrix(H, symmetrize)
     n = H.shape[0]
@@ -46,6 +50,9 @@ def density(H, n_occ, tol=1e-5, precision="bf16x3", refine="fp32", max_iter=100,
         workspace = _lib.allocate_workspace(n, opt, H.device)
     P = torch.empty_like(H)
     st, info, branches = _lib.sp2_density_ex(H, n_occ, opt, P, workspace)
+    if st == _lib.SP2_ERR_NOT_CONVERGED and not allow_unconverged:
+        raise _lib.SP2Error(st, _lib.sp2_last_error() + " (pass allow_unconverged=True to "
+                            "receive the last iterate)")
     if return_info:
         d = info.as_dict()
         d["branches"] = branches
@@ -58,12 +65,16 @@ class SP2Density(torch.autograd.Function):
     """``P = SP2Density.apply(H, n_occ, options_dict)``; differentiable in H
     with the spectral bounds and branch signs held fixed (exact at
     convergence).  ``options_dict`` takes the keyword arguments of
-    ``density`` (``checkpoint_every`` defaults to 4)."""
+    ``density`` (``checkpoint_every`` defaults to 4).  The forward raises
+    ``SP2Error`` when the solve does not converge: an unconverged network has
+    no derivative tape."""
 
     @staticmethod
     def forward(ctx, H, n_occ, opts=None):
         opts = dict(opts or {})
         opts.setdefault("checkpoint_every", 4)
+        if opts.get("allow_unconverged"):
+            raise ValueError("SP2Density needs a converged solve (allow_unconverged is refused)")
         P, info = density(H, n_occ, return_info=True, **opts)
         ctx.workspace = info["workspace"]
         ctx.info = info

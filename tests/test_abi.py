@@ -125,6 +125,22 @@ def test_invalid_arguments_rejected_before_device_work(lib):
                                        ws, 1 << 30, None) == _lib.SP2_ERR_INVALID_ARG
 
 
+def test_history_rejects_bad_arguments(lib):
+    from paper_2107_02737_amd import _lib
+    buf = (ctypes.c_double * 4)()
+    cnt = ctypes.c_int32(0)
+    ws = ctypes.c_void_p(0x100000)
+    assert lib.sp2_history(ws, 1 << 30, -1, buf, None, None, ctypes.byref(cnt), None) == \
+        _lib.SP2_ERR_INVALID_ARG
+    assert lib.sp2_history(ws, 1 << 30, 4, None, None, None, ctypes.byref(cnt), None) == \
+        _lib.SP2_ERR_INVALID_ARG
+    assert lib.sp2_history(None, 1 << 30, 4, buf, None, None, ctypes.byref(cnt), None) == \
+        _lib.SP2_ERR_WORKSPACE
+    assert lib.sp2_history(ctypes.c_void_p(0x100010), 1 << 30, 4, buf, None, None, None, None) == \
+        _lib.SP2_ERR_WORKSPACE
+    assert lib.sp2_history(ws, 64, 4, buf, None, None, None, None) == _lib.SP2_ERR_WORKSPACE
+
+
 def test_xl_entry_points_reject_bad_arguments(lib):
     from paper_2107_02737_amd import _lib
     fake = ctypes.c_void_p(0x1000)

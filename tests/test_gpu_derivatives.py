@@ -67,6 +67,12 @@ def validated_record(h64, n_occ, info, precision, refine):
     return rec, flips
 
 
+# Relative Frobenius distance from first-order perturbation theory allowed
+# to the GPU derivative, by (FP32 layers, refinement): FP32 networks stop at
+# e_n ~ 1e-5 or below; split networks stop at their rounding floor.
+DM_TOL = {(True, False): 2e-4, (True, True): 2e-4, (False, False): 4e-3, (False, True): 2e-3}
+
+
 def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
@@ -104,12 +110,12 @@ def test_jvp_and_vjp_match_oracle(pk, name, n, n_occ, precision, refine, tol, sp
     j_dm = oracle.dmpt_response(h64, n_occ, h1.astype(np.float64))
     g_dm = oracle.dmpt_response(h64, n_occ, w.astype(np.float64))
     j, g = to_host(P1), to_host(G)
-    # against perturbation theory: the network itself (its FP64 derivative,
-    # j_ref / g_ref) is this far from the step function's response -- near
-    # 1e-3 for a split network stopped at its rounding floor without
-    # refinement -- and the GPU may add its own rounding on top
-    dm_tol = 1e-4 if precision == "fp32" else 1e-3
-    dm_tol = max(dm_tol, max(_rel(j_ref, j_dm), _rel(g_ref, g_dm)) + tol)
+    # against perturbation theory: a fixed bound per arithmetic, independent
+    # of the GPU's own network (an FP64 network stopped at e_n ~ 1e-2 without
+    # refinement is 0.8e-3 (c1) and 1.4e-3 (water) from the step function's
+    # response, which is where an unrefined split network stops; with the
+    # refinement 1.6e-6 and 7.9e-6)
+    dm_tol = DM_TOL[(precision == "fp32", refine != "none")]
     print(f"  n_iter={info['n_iter']} flips={flips} jvp rel={_rel(j, j_ref):.2e} "
           f"vjp rel={_rel(g, g_ref):.2e} vs DMPT: jvp {_rel(j, j_dm):.2e} vjp {_rel(g, g_dm):.2e}",
           flush=True)
@@ -159,7 +165,7 @@ def test_derivatives_with_lanczos_bounds(pk, precision, tol, split):
     print(f"  n_iter={info['n_iter']} jvp rel={_rel(j, j_ref):.2e} vjp rel={_rel(g, g_ref):.2e} "
           f"vs DMPT {_rel(j, j_dm):.2e}", flush=True)
     assert _rel(j, j_ref) <= tol and _rel(g, g_ref) <= tol
-    assert _rel(j, j_dm) <= max(tol, _rel(j_ref, j_dm) + tol)
+    assert _rel(j, j_dm) <= DM_TOL[(precision == "fp32", True)]
 
 
 def test_vjp_equals_jvp_and_checkpoint_independence(pk):
@@ -261,3 +267,49 @@ def test_trivial_occupation_has_zero_derivative(pk):
     G = to_dev(np.ones((256, 256)))
     pk.sp2_vjp(info["workspace"], to_dev(h32), G)
     assert torch.count_nonzero(G) == 0
+
+
+def test_bound_call_on_the_workspace_drops_the_tape(pk):
+    """The tape keeps the bounds of the network it recorded; a later bound
+    computation on the same workspace (which rewrites the control block)
+    leaves the derivative either unchanged or refused, never rescaled."""
+    import torch
+    banner("tape after sp2_bounds on the same workspace")
+    h32 = _hamiltonian("water")
+    h1 = to_dev(symmetric_normal(300, 2, std=1e-3).astype(np.float32))
+    _, info = pk.density(to_dev(h32), 200, precision="fp32", refine="fp32", checkpoint_every=3,
+                         bound_steps=16, return_info=True)
+    P1 = torch.empty_like(h1)
+    pk.sp2_jvp(info["workspace"], h1, P1)
+    lo, hi = pk.sp2_bounds(to_dev(h32), info["workspace"])
+    assert lo < info["eps_min"] and hi > info["eps_max"]        # Gershgorin: wider
+    with pytest.raises(pk.SP2Error) as ei:
+        pk.sp2_jvp(info["workspace"], h1, torch.empty_like(h1))
+    assert ei.value.status == 6
+    with pytest.raises(pk.SP2Error) as ei:
+        pk.sp2_vjp(info["workspace"], h1, torch.empty_like(h1))
+    assert ei.value.status == 6
+    # a fresh forward on the workspace restores the same derivative bitwise
+    pk.density(to_dev(h32), 200, precision="fp32", refine="fp32", checkpoint_every=3,
+               bound_steps=16, workspace=info["workspace"])
+    P1b = torch.empty_like(h1)
+    pk.sp2_jvp(info["workspace"], h1, P1b)
+    assert torch.equal(P1, P1b)
+
+
+def test_unconverged_forward_has_no_tape(pk):
+    banner("layer cap with a tape")
+    h32 = _hamiltonian("c1")
+    H = to_dev(h32)
+    with pytest.raises(pk.SP2Error) as ei:
+        pk.density(H, 128, max_iter=3, checkpoint_every=2)
+    assert ei.value.status == 3
+    with pytest.raises(pk.SP2Error) as ei:
+        pk.SP2Density.apply(H.clone().requires_grad_(True), 128, {"max_iter": 3})
+    assert ei.value.status == 3
+    P, info = pk.density(H, 128, max_iter=3, checkpoint_every=2, allow_unconverged=True,
+                         return_info=True)
+    assert info["status"] == 3 and info["converged"] == 0 and info["n_iter"] == 3
+    with pytest.raises(pk.SP2Error) as ei:
+        pk.sp2_jvp(info["workspace"], H, to_dev(np.zeros((256, 256))))
+    assert ei.value.status == 6

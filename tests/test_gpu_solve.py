@@ -218,3 +218,29 @@ def test_layer_timing_flag(pk, c1):
     P, info = _run(pk, h32, n_occ, time_layers=True)
     assert info["layer_ms"] > 0 and info["refine_ms"] > 0
     assert not math.isnan(info["layer_ms"])
+
+
+def test_trace_history_follows_the_oracle(pk, c1):
+    """sp2_history returns the traces that decided every branch and the stop:
+    they match the FP64 traces of the same network (replayed in the oracle
+    with the GPU's bounds and branch string) to FP32 accuracy."""
+    h32, n_occ, _ = c1
+    banner("trace history c1 fp32")
+    P, info = _run(pk, h32, n_occ, precision="fp32", refine="none")
+    hist = pk.sp2_history(info["workspace"])
+    nl = info["n_iter"]
+    assert len(hist["t1"]) == nl + 1
+    signs = [1 if b else -1 for b in info["branches"]]
+    rec = oracle.SP2Record(eps_min=info["eps_min"], eps_max=info["eps_max"], branches=signs)
+    iters = oracle.sp2_oracle._replay(h32.astype(np.float64), rec)
+    for k, s_k in enumerate(iters):
+        t1, t2 = float(np.trace(s_k)), float(np.sum(s_k * s_k))
+        assert abs(hist["t1"][k] - t1) < 1e-4 and abs(hist["t2"][k] - t2) < 1e-4, k
+        assert hist["err"][k] == abs(hist["t1"][k] - hist["t2"][k])
+    # the stop was taken on the last entry's traces, the branches on the others'
+    assert abs(hist["t1"][nl] - n_occ) < 0.5 and hist["err"][nl] < 3.0 / 16.0
+    for k in range(nl):
+        assert signs[k] == oracle.choose_branch(hist["t1"][k], hist["t2"][k], n_occ)
+    # the partial-sum history of a capped buffer
+    short = pk.sp2_history(info["workspace"], cap=3)
+    assert short["t1"] == hist["t1"][:3]
