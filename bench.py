@@ -1,22 +1,24 @@
 """Benchmark: DNN-SP2 density-matrix solves/s at N = 6144 on one MI355X.
 
 One step = one full ``sp2_density_ex`` call on a device-resident FP32
-Hamiltonian: Gershgorin bounds, input layer, every SP2 layer (split 16-bit
-MFMA products with FP64 trace-driven branch/stop decisions on the device)
-and the FP32 McWeeny refinement, ending with P in a caller buffer.
+Hamiltonian in the FP32-equivalent mode: Gershgorin discs tightened by 32
+Lanczos steps, the input layer, every SP2 layer as an FP16 hi/lo split
+product on MFMA (Eq. 20-22; FP64 trace-driven branch and stop decided on
+the device) and the FP32 McWeeny refinement, ending with P in a caller
+buffer.  This mode meets the stated ||P - P_ref||_F / sqrt(N) <= 1e-6.
 
 Workload: seeded tight-binding water box, 1024 molecules, N = 6144,
 n_occ = 4096, H in FP32 (synthetic stand-in for the paper's SCC-DFTB water).
 
 Prints ONE JSON line.  Also reported: effective TFLOPS (3 products of
-2 N^3 per split layer + 2 N^3 per refinement product), the error against the
-FP64 oracle from stored samples of the exact density matrix, plain FP32 SP2
-on the same GPU, the roofline of the layer kernel (HIP-event durations
-recorded around every layer launch during the timed steps), the FP64
-oracle timed on the host cores and, outside the timed steps, the XL-BOMD
-kernel building block (one charge-space response and a rank-4 Krylov
-approximation of K f on the water box's synthetic charge model) and the
-canonical integration step of Section IV on a large batch of coordinates.
+2 N^3 per split layer + 2 N^3 per refinement product), the error of every
+entry against the FP64 oracle's diagonalisation, the roofline of the layer
+kernel (HIP events around every layer launch on the solve's stream, in a
+second timed pass of the same solves), side legs in the other arithmetics
+(BF16 pair, single-pass BF16, plain FP32 MFMA SP2) timed over as many
+steps, the FP64 oracle timed on the host cores and, outside the timed
+steps, the XL-BOMD kernel building block and the canonical integration step
+of Section IV on a large batch of coordinates.
 """
 
 import argparse
@@ -35,7 +37,12 @@ METRIC = "SP2 density-matrix solves/s + effective TFLOPS at N=6144; error vs FP6
 PEAK_TFLOPS = {"bf16x3": 2500.0, "fp16x3": 2500.0, "bf16x1": 2500.0, "fp32": 157.3}
 PRODUCTS = {"bf16x3": 3, "fp16x3": 3, "bf16x1": 1, "fp32": 1}
 GOLDEN = os.path.join(ROOT, "tests", "golden", "water_m1024_seed0.npz")
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_sym_split_bf16x3_water6144_traffic.md")
+TRAFFIC_PROFILES = {p: os.path.join(ROOT, "profiles", f"k_sym_split_{p}_water6144_traffic.md")
+                    for p in ("bf16x3", "fp16x3")}
+# Stated bounds on ||P - P_ref||_F / sqrt(N): FP32-equivalent mode and
+# single-pass BF16.
+TOL_FP32_EQUIVALENT = 1e-6
+TOL_SINGLE_PASS_BF16 = 1e-3
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2107_02737_amd", "csrc", f)
                   for f in ("sp2_common.hpp", "sp2_gemm.hpp")]
 NVT_PROFILE = os.path.join(ROOT, "profiles", "k_nvt_step_3x2e24coords.md")
@@ -47,13 +54,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", default="bf16x3", choices=list(PRODUCTS))
+    ap.add_argument("--precision", default="fp16x3", choices=list(PRODUCTS))
     ap.add_argument("--refine", default="fp32", choices=["none", "fp32", "split"])
-    ap.add_argument("--no-fp32-compare", action="store_true")
-    ap.add_argument("--bound-steps", type=int, default=0,
+    ap.add_argument("--bound-steps", type=int, default=32,
                     help="Lanczos steps tightening the Gershgorin bounds (0: Gershgorin only)")
-    ap.add_argument("--compare-bound-steps", type=int, default=24,
-                    help="also time solves with this many Lanczos bound steps (0: skip)")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the side legs in other arithmetics")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-layers", type=int, default=4,
                     help="FP64 oracle layers timed for the CPU baseline sample")
@@ -61,6 +67,8 @@ def parse():
                     help="instead of the benchmark: run STEPS steps of the N=16384 trajectory "
                          "workload H(t) = H0 + 0.01 sin(0.1 t) H_p (adjoint on the last step) "
                          "and print per-step times and the drift of Tr P and idempotency")
+    ap.add_argument("--traj-precision", default="bf16x3", choices=list(PRODUCTS),
+                    help="layer arithmetic of the trajectory run")
     ap.add_argument("--xl-rank", type=int, default=4,
                     help="also time the XL-BOMD kernel building block (Krylov approximation of "
                          "K f of this rank on the water box's charge model; 0: skip)")
@@ -86,14 +94,15 @@ def copy_calibration():
     print(json.dumps({"copy_calibration_bytes_per_launch": 4 * n, "launches": 3}), flush=True)
 
 
-def measured_traffic(precision, profile=TRAFFIC_PROFILE, sources=KERNEL_SOURCES,
+def measured_traffic(precision, profile=None, sources=KERNEL_SOURCES,
                      key="traffic_bytes_per_launch"):
     """HBM bytes per launch from a committed counter summary (FETCH_SIZE +
-    WRITE_SIZE, calibrated against a plain copy), or None when the summary is
-    for another precision or the kernel source has changed since the
+    WRITE_SIZE, calibrated against a plain copy), or None when there is no
+    summary for this precision or the kernel source has changed since the
     counters were taken."""
     import hashlib
-    if precision != "bf16x3" or not os.path.exists(profile):
+    profile = profile or TRAFFIC_PROFILES.get(precision)
+    if profile is None or not os.path.exists(profile):
         return None
     sha = hashlib.sha256(b"".join(open(f, "rb").read() for f in sources)).hexdigest()
     fields = {}
@@ -207,9 +216,20 @@ def timed_solves(pk, H, n_occ, precision, refine, steps, warmup, time_layers, bo
     return P, infos, (t1 - t0) / steps
 
 
+def full_error(P, p_ref):
+    """Every entry of P against the exact P_ref (FP64, host):
+    ||P - P_ref||_F / sqrt(N), ||P - P_ref||_F / N and max |P - P_ref|."""
+    d = P.detach().double().cpu().numpy() - p_ref
+    n = d.shape[0]
+    fro = float(np.linalg.norm(d))
+    return {"fro_over_sqrt_n": fro / math.sqrt(n), "fro_over_n": fro / n,
+            "max_abs": float(np.max(np.abs(d))), "entries": "all"}
+
+
 def sampled_error(P, gold):
     """||P - P_ref||_F / sqrt(N) estimated from uniformly sampled entries of the
-    exact P_ref, plus the exact diagonal error."""
+    exact P_ref, plus the exact diagonal error (used when the CPU leg, which
+    computes the exact P_ref, is skipped)."""
     n = int(gold["n"])
     p = P.detach()
     pi = np.asarray(gold["pair_i"], dtype=np.int64)
@@ -219,10 +239,10 @@ def sampled_error(P, gold):
     d = got.double().cpu().numpy() - gold["pair_val"]
     diag = torch.diagonal(p).double().cpu().numpy() - gold["diag"]
     return {
-        "fro_over_sqrt_n_est": math.sqrt(n * float(np.mean(d * d))),
-        "max_abs_sampled": float(np.max(np.abs(d))),
+        "fro_over_sqrt_n": math.sqrt(n * float(np.mean(d * d))),
+        "max_abs": float(np.max(np.abs(d))),
         "diag_rms": float(np.sqrt(np.mean(diag * diag))),
-        "samples": int(d.size),
+        "entries": f"{int(d.size)} sampled + diagonal",
     }
 
 
@@ -305,8 +325,9 @@ def cpu_baseline(h32, n_occ, layers, n_iter_ref):
     per_layer = max(0.0, (t2 - t1) - setup) / layers
     t_solve = setup + n_iter_ref * per_layer
     # the plain definition: FP64 diagonalisation and the occupied outer product
+    # (its result is also the reference for the GPU's error report)
     t3 = time.perf_counter()
-    oracle.density_matrix_eigh(h, n_occ)
+    p_ref, _, _ = oracle.density_matrix_eigh(h, n_occ)
     t_eigh = time.perf_counter() - t3
     # sanity line: plain FP32 NumPy layers (SGEMM square, traces summed in FP64)
     lo, hi = oracle.gershgorin_bounds(h)
@@ -318,7 +339,7 @@ def cpu_baseline(h32, n_occ, layers, n_iter_ref):
         x2 = x @ x
         x = x2 if oracle.choose_branch(t1_, t2_, n_occ) > 0 else np.float32(2.0) * x - x2
     t_fp32 = (time.perf_counter() - t4) / layers * n_iter_ref
-    return {
+    return p_ref, {
         "value": 1.0 / t_solve,
         "unit": "solves/s",
         "cores": int(threads),
@@ -377,7 +398,7 @@ def canonical_step(pk, n, reps=20):
             "second_half_gbps": 32.0 * n / (t2 * 1e-6) / 1e9,
             "roofline": {"bound": "hbm", "achieved": gbps, "peak": 8000.0, "unit": "GB/s",
                          "frac": gbps / 8000.0,
-                         "traffic": measured_traffic("bf16x3", NVT_PROFILE, NVT_SOURCES,
+                         "traffic": measured_traffic(None, NVT_PROFILE, NVT_SOURCES,
                                                      f"traffic_bytes_per_step_{n}")
                          if n == 3 * 2 ** 24 else None,
                          "kernel": "k_nvt_first + k_nvt_second"},
@@ -394,7 +415,7 @@ def main():
         copy_calibration()
         return
     if args.trajectory:
-        trajectory(args.trajectory, args.precision, args.refine)
+        trajectory(args.trajectory, args.traj_precision, args.refine)
         return
     import torch
 
@@ -409,23 +430,39 @@ def main():
         raise RuntimeError("water-box generator drifted from the stored golden values")
     H = torch.from_numpy(h32).to("cuda")
     pk.load_library()
+    print(f"# bench: water N={n} {args.precision} refine={args.refine} "
+          f"bound_steps={args.bound_steps}", file=sys.stderr, flush=True)
 
+    # the timed steps: solves only, no per-layer events
     P, infos, sec = timed_solves(pk, H, n_occ, args.precision, args.refine, args.steps,
-                                 args.warmup, True, args.bound_steps)
+                                 args.warmup, False, args.bound_steps)
     n_iter = infos[-1]["n_iter"]
     solve_ms = np.array([d["solve_ms"] for d in infos])
     prods = PRODUCTS[args.precision]
     nref = 2 if args.refine != "none" else 0
     eff_flop = (n_iter * prods + nref) * 2.0 * n ** 3
-    layer_ms = float(np.mean([d["layer_ms"] / max(1, d["n_iter"]) for d in infos]))
+    # the same solves again with HIP events around every layer launch on the
+    # solve's stream: the layer kernel's average launch duration
+    _, tinfos, tsec = timed_solves(pk, H, n_occ, args.precision, args.refine, args.steps, 1,
+                                   True, args.bound_steps)
+    layer_ms = float(np.mean([d["layer_ms"] / max(1, d["n_iter"]) for d in tinfos]))
     # algorithmic work of one layer launch: upper-triangle tiles only, i.e.
     # prods * N^3 FMA = 2 * prods * N^3 / 2 flop
     layer_flop = prods * float(n) ** 3
     achieved = layer_flop / (layer_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
+    print(f"# headline {1.0 / sec:.2f} solves/s, layer {layer_ms:.3f} ms", file=sys.stderr,
+          flush=True)
 
-    err = sampled_error(P, gold)
+    p_ref, cb = None, None
+    if not args.no_cpu_baseline:
+        print("# cpu baseline (FP64 oracle on the host cores)", file=sys.stderr, flush=True)
+        p_ref, cb = cpu_baseline(h32, n_occ, args.cpu_layers, n_iter)
+    err = full_error(P, p_ref) if p_ref is not None else sampled_error(P, gold)
     err.update(device_checks(P, n_occ))
+    tol = TOL_FP32_EQUIVALENT if args.precision in ("fp16x3", "bf16x3", "fp32") else TOL_SINGLE_PASS_BF16
+    err["stated_tolerance"] = tol
+    err["meets_tolerance"] = bool(err["fro_over_sqrt_n"] <= tol)
 
     out = {
         "metric": METRIC,
@@ -444,7 +481,7 @@ def main():
                                f"seed {int(gold['seed'])}, H fp32 on device",
                    "n": n, "n_occ": n_occ, "precision": args.precision, "refine": args.refine,
                    "bounds": "gershgorin" if args.bound_steps == 0
-                   else f"lanczos {args.bound_steps} steps",
+                   else f"gershgorin + lanczos {args.bound_steps} steps",
                    "parallelism": "single GPU"},
         "n_iter": n_iter,
         "solve_ms": {"median": float(np.median(solve_ms)), "p10": float(np.percentile(solve_ms, 10)),
@@ -453,54 +490,49 @@ def main():
         "error_vs_oracle": err,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": measured_traffic(args.precision),
-                     "kernel": f"k_sym_split ({args.precision} layer product)"
-                               if args.precision != "fp32" else "k_sym_f32 (fp32 layer product)",
+                     "kernel": f"k_sym_split<{args.precision}> + k_split_tail (layer product)"
+                               if args.precision != "fp32" else "k_sym_f32 + k_split_tail",
                      "layer_ms": layer_ms,
-                     "refine_ms": float(np.mean([d["refine_ms"] for d in infos]))},
+                     "layer_flop": layer_flop,
+                     "refine_ms": float(np.mean([d["refine_ms"] for d in tinfos])),
+                     "timing": f"HIP events around every layer launch, {args.steps} solves "
+                               "after the timed ones",
+                     "solves_per_s_with_layer_events": 1.0 / tsec},
     }
-    if args.compare_bound_steps and args.compare_bound_steps != args.bound_steps:
-        Pl, linfo, lsec = timed_solves(pk, H, n_occ, args.precision, args.refine, 5, 1, True,
-                                       args.compare_bound_steps)
-        lerr = sampled_error(Pl, gold)
-        out["with_bound_steps"] = {
-            "bound_steps": args.compare_bound_steps, "solves_per_s": 1.0 / lsec,
-            "n_iter": linfo[-1]["n_iter"], "eps": [linfo[-1]["eps_min"], linfo[-1]["eps_max"]],
-            "fro_over_sqrt_n_est": lerr["fro_over_sqrt_n_est"]}
+
+    def leg(precision, refine, bound_steps, label):
+        print(f"# leg {label}", file=sys.stderr, flush=True)
+        Pl, linfo, lsec = timed_solves(pk, H, n_occ, precision, refine, args.steps, args.warmup,
+                                       False, bound_steps)
+        lerr = full_error(Pl, p_ref) if p_ref is not None else sampled_error(Pl, gold)
         del Pl
-    if args.refine == "fp32" and not args.no_fp32_compare:
-        # the FP32-equivalent mode: FP16x3 layers, FP32 refinement, 32 Lanczos bound steps
-        Pe, einfo, esec = timed_solves(pk, H, n_occ, "fp16x3", "fp32", 5, 1, True, 32)
-        eerr = sampled_error(Pe, gold)
-        out["fp32_equivalent"] = {"precision": "fp16x3", "refine": "fp32", "bound_steps": 32,
-                                  "solves_per_s": 1.0 / esec, "n_iter": einfo[-1]["n_iter"],
-                                  "fro_over_sqrt_n_est": eerr["fro_over_sqrt_n_est"],
-                                  "tolerance": 1e-6}
-        del Pe
-    if args.refine == "fp32":
-        # the same solve with the FP32-equivalent split refinement (FP16x3 products)
-        Ps, sinfo, ssec = timed_solves(pk, H, n_occ, args.precision, "split", 5, 1, True,
-                                       args.bound_steps)
-        serr = sampled_error(Ps, gold)
-        out["with_split_refine"] = {"solves_per_s": 1.0 / ssec,
-                                    "refine_ms": float(np.mean([d["refine_ms"] for d in sinfo])),
-                                    "fro_over_sqrt_n_est": serr["fro_over_sqrt_n_est"]}
-        del Ps
-    if not args.no_fp32_compare and args.precision != "fp32":
-        _, finfo, fsec = timed_solves(pk, H, n_occ, "fp32", args.refine, 3, 1, True)
-        f_layer_ms = float(np.mean([d["layer_ms"] / max(1, d["n_iter"]) for d in finfo]))
-        out["fp32_sp2"] = {"solves_per_s": 1.0 / fsec, "n_iter": finfo[-1]["n_iter"],
-                           "layer_ms": f_layer_ms,
-                           "layer_tflops": float(n) ** 3 / (f_layer_ms * 1e-3) / 1e12,
-                           "speedup_of_split": fsec / sec}
+        return {"precision": precision, "refine": refine, "bound_steps": bound_steps,
+                "solves_per_s": 1.0 / lsec, "steps": args.steps, "n_iter": linfo[-1]["n_iter"],
+                "converged": bool(linfo[-1]["converged"]),
+                "fro_over_sqrt_n": lerr["fro_over_sqrt_n"], "max_abs": lerr["max_abs"]}
+
+    if not args.no_legs:
+        legs = {}
+        legs["fp16x3_lanczos32_split_refine"] = leg("fp16x3", "split", 32, "FP16 pair, split refinement")
+        legs["bf16x3_gershgorin"] = leg("bf16x3", "fp32", 0, "BF16 pair, Gershgorin bounds")
+        legs["bf16x3_lanczos24"] = leg("bf16x3", "fp32", 24, "BF16 pair, 24 Lanczos steps")
+        sp = leg("bf16x1", "fp32", 32, "single-pass BF16")
+        sp["stated_tolerance"] = TOL_SINGLE_PASS_BF16
+        sp["meets_tolerance"] = bool(sp["fro_over_sqrt_n"] <= TOL_SINGLE_PASS_BF16)
+        legs["bf16x1_single_pass"] = sp
+        f32 = leg("fp32", "fp32", args.bound_steps, "plain FP32 MFMA SP2")
+        f32["speedup_of_headline"] = out["value"] / f32["solves_per_s"]
+        legs["fp32_sp2"] = f32
+        out["legs"] = legs
     if args.xl_rank > 0:
-        out["xl_kernel"] = xl_kernel(pk, int(gold["seed"]), args.xl_rank, args.precision, args.refine)
-        if args.precision == "bf16x3":
-            out["xl_kernel_split_derivatives"] = xl_kernel(pk, int(gold["seed"]), args.xl_rank,
-                                                           args.precision, args.refine, True)
+        print("# XL-BOMD kernel block", file=sys.stderr, flush=True)
+        out["xl_kernel"] = xl_kernel(pk, int(gold["seed"]), args.xl_rank, "bf16x3", args.refine)
+        out["xl_kernel_split_derivatives"] = xl_kernel(pk, int(gold["seed"]), args.xl_rank,
+                                                       "bf16x3", args.refine, True)
     if args.nvt_coords > 0:
+        print("# canonical step", file=sys.stderr, flush=True)
         out["canonical_step"] = canonical_step(pk, args.nvt_coords)
-    if not args.no_cpu_baseline:
-        cb = cpu_baseline(h32, n_occ, args.cpu_layers, n_iter)
+    if cb is not None:
         cb["gpu_speedup_vs_oracle_sp2"] = out["value"] / cb["value"]
         cb["gpu_speedup_vs_oracle_eigh"] = cb["eigh_seconds"] * out["value"]
         out["cpu_baseline"] = cb

@@ -559,21 +559,48 @@ __global__ void k_seal_tape(Meta* m, Meta v, const Ctrl* c) {
 // A call that reuses the workspace header for other work drops the tape.
 __global__ void k_drop_tape(Meta* m) { m->valid = 0; }
 
+// Events of this thread on the current device, created on first use and
+// kept until the process ends (a solve records into them; creating and
+// destroying hundreds of events per solve would cost more than the
+// records).  Timing events for SP2_FLAG_TIME_LAYERS; two untimed events for
+// the stop-flag polls.
+struct EventPool {
+  int dev = -1;
+  std::vector<hipEvent_t> timed;
+  hipEvent_t poll[2] = {nullptr, nullptr};
+};
+
+hipError_t event_pool(EventPool** out, size_t timed) {
+  thread_local EventPool pools[16];
+  int dev = 0;
+  hipError_t r = hipGetDevice(&dev);
+  if (r != hipSuccess) return r;
+  if (dev < 0 || dev >= 16) return hipErrorInvalidDevice;
+  EventPool& p = pools[dev];
+  if (!p.poll[0]) {
+    for (auto& e : p.poll)
+      if ((r = hipEventCreateWithFlags(&e, hipEventDisableTiming)) != hipSuccess) return r;
+  }
+  while (p.timed.size() < timed) {
+    hipEvent_t e = nullptr;
+    if ((r = hipEventCreate(&e)) != hipSuccess) return r;
+    p.timed.push_back(e);
+  }
+  *out = &p;
+  return hipSuccess;
+}
+
 // Timing events for SP2_FLAG_TIME_LAYERS: a start and an end event around
 // every layer launch and around the refinement.
 struct LayerTimer {
-  std::vector<hipEvent_t> ev;
+  hipEvent_t* ev = nullptr;
   bool on = false;
-  ~LayerTimer() {
-    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
-  }
   hipError_t init(int max_iter) {
+    EventPool* p = nullptr;
+    hipError_t r = event_pool(&p, size_t(2 * max_iter + 2));
+    if (r != hipSuccess) return r;
+    ev = p->timed.data();
     on = true;
-    ev.assign(2 * max_iter + 2, nullptr);
-    for (auto& e : ev) {
-      hipError_t r = hipEventCreate(&e);
-      if (r != hipSuccess) return r;
-    }
     return hipSuccess;
   }
   hipError_t mark(int idx, hipStream_t st) { return on ? hipEventRecord(ev[idx], st) : hipSuccess; }
@@ -739,9 +766,9 @@ sp2_status sp2_density_ex(const float* H, int64_t n, int64_t ld, int64_t n_occ,
   const int refine_ev = o.max_iter;   // event pair index of the refinement
 
   // Layer loop in chunks; poll the stop flag of chunk c while chunk c+1 runs.
-  hipEvent_t ev[2];
-  HIP_TRY(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
-  HIP_TRY(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+  EventPool* pool = nullptr;
+  HIP_TRY(event_pool(&pool, 0));
+  hipEvent_t* ev = pool->poll;
   int launched = 0, chunk = 0;
   bool stopped = false;
   sp2_status err = SP2_OK;
@@ -783,8 +810,6 @@ sp2_status sp2_density_ex(const float* H, int64_t n, int64_t ld, int64_t n_occ,
     hipError_t e = hipStreamSynchronize(st);
     if (e != hipSuccess) err = fail(SP2_ERR_DEVICE, "sync: %s", hipGetErrorString(e));
   }
-  (void)hipEventDestroy(ev[0]);
-  (void)hipEventDestroy(ev[1]);
   if (err != SP2_OK) return err;
 
   // The freshest control block: the loop has drained, read it again.

@@ -7,8 +7,8 @@ water_m1024_seed0.npz -- tight-binding water box, 1024 molecules, seed 0,
 N = 6144, n_occ = 4096, H cast to FP32 (the matrix the GPU receives).
 Holds sampled entries of the exact density matrix P_ref = theta(mu I - H)
 (Eq. 17-18): every diagonal entry and 8192 uniformly drawn (i, j) pairs
-(rng seed 1234), plus the Gershgorin bounds, the HOMO/LUMO gap and
-checksums of H that detect generator drift.
+(rng seed 1234), plus the Gershgorin bounds, the HOMO/LUMO levels, the
+ends of the spectrum and checksums of H that detect generator drift.
 
 water_m682_n4096_deriv.npz -- derivative workload: 682 molecules (4092
 orbitals) zero-padded to N = 4096, n_occ = 2728 (four doubly occupied states
@@ -70,7 +70,7 @@ def water6144():
         n=n, n_occ=n_occ, molecules=m, seed=seed,
         diag=np.diag(p_ref).copy(),
         pair_i=ri.astype(np.uint16), pair_j=rj.astype(np.uint16), pair_val=p_ref[ri, rj],
-        eps_min=lo, eps_max=hi, homo=w[n_occ - 1], lumo=w[n_occ],
+        eps_min=lo, eps_max=hi, homo=w[n_occ - 1], lumo=w[n_occ], lam_min=w[0], lam_max=w[-1],
         h_sum=float(h.sum()), h_sumsq=float((h * h).sum()))
     print(f"wrote water_m1024_seed0.npz: gap={w[n_occ] - w[n_occ - 1]:.4f} bounds=({lo:.4f}, {hi:.4f})")
 
@@ -90,7 +90,7 @@ def deriv4096():
     ri, rj = _pairs(n)
     out = dict(n=n, n_occ=n_occ, molecules=m, seed=0, seed_w=1, seed_h1=2, h1_std=1e-3,
                fd_step=fd_step, pair_i=ri.astype(np.uint16), pair_j=rj.astype(np.uint16),
-               eps_min=lo, eps_max=hi, homo=w[n_occ - 1], lumo=w[n_occ],
+               eps_min=lo, eps_max=hi, homo=w[n_occ - 1], lumo=w[n_occ], lam_min=w[0], lam_max=w[-1],
                h_sum=float(h.sum()), h1_sum=float(h1.sum()), w_sum=float(wm.sum()),
                w_dot_p1=float(np.sum(wm * p1)), w_dot_p1_fd=fd,
                trace_p1=float(np.trace(p1)), p1_fro=float(np.linalg.norm(p1)),
