@@ -15,3 +15,4 @@ from . import lanczos  # noqa: F401,E402
 from .lanczos import lanczos_bounds  # noqa: F401,E402
 from . import xlbomd  # noqa: F401,E402
 from . import canonical  # noqa: F401,E402
+from . import accelerated  # noqa: F401,E402

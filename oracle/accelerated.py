@@ -1,0 +1,186 @@
+"""Accelerated DNN-SP2 with HOMO/LUMO estimates -- TEST INFRASTRUCTURE ONLY.
+
+Imported by tests, the smoke check and the benchmark's CPU-baseline leg;
+never by the product path.
+
+Section II.E notes that the layer count of DNN-SP2 can be cut further (by up
+to half) when estimates of the highest occupied and lowest unoccupied
+eigenvalues are known beforehand, citing the accelerated (scaled and
+shifted, nonmonotonic) recursive expansions of Rubensson and co-workers.
+The paper gives no formulas.  Reading used here, derived from the spectral
+picture of Section II.D:
+
+* With the input layer of Eq. (19) the occupied eigenvalues of ``S_0`` lie
+  in ``[h, 1]`` and the virtual ones in ``[0, l]``, where
+  ``h = (eps_max - homo) / (eps_max - eps_min)`` and
+  ``l = (eps_max - lumo) / (eps_max - eps_min)``, ``l < h`` (estimates:
+  ``homo`` at or above the true HOMO, ``lumo`` at or below the true LUMO).
+* A layer keeps the DNN form ``S_n = W_n X_n + B_n``, ``X_n = S_{n-1}^2``,
+  now with ``W_n = a I`` and ``B_n = b S_{n-1} + c I``, i.e. the quadratic
+  ``p(x) = a x^2 + b x + c`` on every eigenvalue.  The two families are
+  ``p+(x) = ((x - s) / (1 - s))^2`` (pushes the virtual interval to 0,
+  folding ``[0, l]`` about ``s``) and its mirror
+  ``p-(x) = 1 - p+(1 - x)`` (pushes the occupied interval to 1), with shift
+  ``0 <= s <= 1/2``.  ``s = 0`` gives the plain SP2 layers ``x^2`` and
+  ``2x - x^2``; every such map sends [0, 1] into [0, 1].
+* Schedule: ``+`` when the virtual interval is the wider one
+  (``l >= 1 - h``), else ``-``; the shift is half the width of the interval
+  being folded (``s = l/2`` for ``+``, ``(1 - h)/2`` for ``-``), which
+  minimises the folded interval's image.  The interval ends follow the
+  same maps exactly, so the whole schedule is fixed by ``(l, h)`` before
+  the first product.  It runs while ``max(l, 1 - h) >= ACC_END``; after it
+  the trace-driven branch rule of plain DNN-SP2 takes over, so a schedule
+  built on poor estimates still ends with the right occupation or with no
+  convergence (the stop test keeps its trace condition), never with a
+  wrong P reported as converged.
+* The stop test and refinement are those of ``sp2_oracle.sp2``.
+
+Pins (tests/test_oracle_accelerated.py): agreement with the diagonalisation
+(``density_matrix_eigh``); the scalar recursion on the eigenvalues
+(``sp2_accelerated_scalar``) reproduces traces and, through the spectral
+theorem, P; each layer polynomial against its defining values (``p+(s) =
+0``, ``p+(1) = 1``, ``p+'(s) = 0`` and the mirror); the interval ends are
+images of eigenvalues placed exactly at them; [0, 1] maps into itself for
+every shift; zero-width intervals give no schedule (plain SP2 bit for bit);
+fewer layers than plain SP2 on the c1/water workloads (scalar probe: 26 ->
+16, 28 -> 16 with Gershgorin bounds); estimates that miss the gap still end
+in the right P through the trace-driven tail.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+from .sp2_oracle import (SP2Record, STALL_GATE, apply_layer, choose_branch, gershgorin_bounds,
+                         input_layer, mcweeny, should_stop)
+
+# The schedule stops once both mapped intervals are this close to 0 and 1.
+ACC_END = 1e-14
+
+
+def mapped_interval(eps_min, eps_max, homo, lumo):
+    """``(l, h)``: upper end of the virtual and lower end of the occupied
+    interval of ``S_0``, clipped to [0, 1]."""
+    r = eps_max - eps_min
+    lo = (eps_max - lumo) / r
+    hi = (eps_max - homo) / r
+    return min(max(lo, 0.0), 1.0), min(max(hi, 0.0), 1.0)
+
+
+def layer_polynomial(sign, shift):
+    """Coefficients ``(a, b, c)`` of ``p(x) = a x^2 + b x + c``:
+    ``sign = +1``: ``((x - s)/(1 - s))^2``; ``sign = -1``:
+    ``1 - ((1 - x - s)/(1 - s))^2``."""
+    d = 1.0 - shift
+    if sign > 0:
+        return 1.0 / (d * d), -2.0 * shift / (d * d), shift * shift / (d * d)
+    return -1.0 / (d * d), 2.0 / d, 0.0
+
+
+def acceleration_schedule(l, h, max_len=100, end=ACC_END):
+    """Signs and shifts of the accelerated layers for mapped interval ends
+    ``(l, h)``, with the interval ends after each layer.  Returns a list of
+    ``(sign, shift, l_after, h_after)``; empty when ``l >= h``."""
+    out = []
+    if not l < h:
+        return out
+    while len(out) < max_len and max(l, 1.0 - h) >= end:
+        if l >= 1.0 - h:
+            s = 0.5 * l
+            d = 1.0 - s
+            q, r = s / d, (h - s) / d
+            l, h = q * q, r * r
+            out.append((1, s, l, h))
+        else:
+            s = 0.5 * (1.0 - h)
+            d = 1.0 - s
+            q, r = (1.0 - l - s) / d, s / d
+            l, h = 1.0 - q * q, 1.0 - r * r
+            out.append((-1, s, l, h))
+    return out
+
+
+def _schedule_coefs(rec, homo, lumo, max_iter):
+    l, h = mapped_interval(rec.eps_min, rec.eps_max, homo, lumo)
+    return [layer_polynomial(sg, s) for sg, s, _, _ in acceleration_schedule(l, h, max_iter)]
+
+
+def sp2_accelerated(h, n_occ, homo, lumo, tol=1e-10, max_iter=100, stop_rule=0,
+                    stall_gate=STALL_GATE, bounds=None, refine=False, return_iterates=False):
+    """DNN-SP2 whose first layers follow the accelerated schedule of the
+    estimates ``homo < lumo`` (energies), then the trace-driven rule.
+
+    Returns ``(D, record)``; ``record.coefs`` holds ``(a, b, c)`` of every
+    applied layer (``record.branches`` its sign)."""
+    h = np.asarray(h, dtype=np.float64)
+    n = h.shape[0]
+    if not 0 <= n_occ <= n:
+        raise ValueError("n_occ out of range")
+    if not homo < lumo:
+        raise ValueError("need homo < lumo")
+    eps_min, eps_max = gershgorin_bounds(h) if bounds is None else bounds
+    rec = SP2Record(eps_min=eps_min, eps_max=eps_max, refine=refine)
+    if n_occ == 0 or n_occ == n:
+        rec.converged = True
+        rec.trivial = True
+        d = np.zeros((n, n)) if n_occ == 0 else np.eye(n)
+        return (d, rec, [d]) if return_iterates else (d, rec)
+    if not eps_max > eps_min:
+        raise ValueError("degenerate spectrum: no gap to place the step in")
+    sched = _schedule_coefs(rec, homo, lumo, max_iter)
+    s = input_layer(h, eps_min, eps_max)
+    iterates = [s]
+    for k in range(max_iter + 1):
+        t1 = float(np.trace(s))
+        t2 = float(np.sum(s * s))
+        rec.t1.append(t1)
+        rec.t2.append(t2)
+        rec.err.append(abs(t1 - t2))
+        if should_stop(k, rec.err, abs(t1 - n_occ), tol, stop_rule, stall_gate):
+            rec.converged = True
+            break
+        if k == max_iter:
+            break
+        if k < len(sched):
+            a, b, c = sched[k]
+        else:
+            a, b, c = (1.0, 0.0, 0.0) if choose_branch(t1, t2, n_occ) > 0 else (-1.0, 2.0, 0.0)
+        s = apply_layer(s, s @ s, (a, b, c))       # S_{k+1} = W f(S_k) + B
+        rec.branches.append(1 if a > 0 else -1)
+        rec.coefs.append((a, b, c))
+        if return_iterates:
+            iterates.append(s)
+    if refine:
+        s = mcweeny(s)
+    if return_iterates:
+        return s, rec, iterates
+    return s, rec
+
+
+def sp2_accelerated_scalar(w, n_occ, eps_min, eps_max, homo, lumo, tol=1e-10, max_iter=100,
+                           stop_rule=0, stall_gate=STALL_GATE):
+    """The same network on the eigenvalues ``w`` of ``H`` (every layer is a
+    polynomial of ``S_0``, which shares the eigenvectors of ``H``).
+    Returns ``(p(x), record)``."""
+    x = (eps_max - np.asarray(w, dtype=np.float64)) / (eps_max - eps_min)
+    rec = SP2Record(eps_min=eps_min, eps_max=eps_max)
+    sched = _schedule_coefs(rec, homo, lumo, max_iter)
+    for k in range(max_iter + 1):
+        t1 = float(np.sum(x))
+        t2 = float(np.sum(x * x))
+        rec.t1.append(t1)
+        rec.t2.append(t2)
+        rec.err.append(abs(t1 - t2))
+        if should_stop(k, rec.err, abs(t1 - n_occ), tol, stop_rule, stall_gate):
+            rec.converged = True
+            break
+        if k == max_iter:
+            break
+        if k < len(sched):
+            a, b, c = sched[k]
+        else:
+            a, b, c = (1.0, 0.0, 0.0) if choose_branch(t1, t2, n_occ) > 0 else (-1.0, 2.0, 0.0)
+        x = a * (x * x) + b * x + c
+        rec.branches.append(1 if a > 0 else -1)
+        rec.coefs.append((a, b, c))
+    return x, rec

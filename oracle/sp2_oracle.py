@@ -50,6 +50,7 @@ __all__ = [
     "sp2_scalar",
     "mcweeny",
     "SP2Record",
+    "apply_layer",
     "sp2_jvp",
     "sp2_vjp",
     "daleckii_krein_jvp",
@@ -157,10 +158,20 @@ class SP2Record:
     converged: bool = False
     refine: bool = False
     trivial: bool = False     # n_occ in {0, N}: P = 0 or I, independent of H
+    coefs: list = field(default_factory=list)   # (a, b, c) per layer when not plain
 
     @property
     def n_iter(self):
         return len(self.branches)
+
+    @property
+    def layer_coefs(self):
+        """``(a, b, c)`` of every applied layer ``S_{k+1} = a S_k^2 + b S_k + c I``:
+        the recorded ones, or ``(1, 0, 0)`` / ``(-1, 2, 0)`` from the signs of
+        plain SP2 layers."""
+        if len(self.coefs) == len(self.branches):
+            return list(self.coefs)
+        return [(1.0, 0.0, 0.0) if s > 0 else (-1.0, 2.0, 0.0) for s in self.branches]
 
     @property
     def branch_bits(self):
@@ -261,13 +272,23 @@ def mcweeny(s):
 # Derivatives with branches and bounds held fixed
 # ---------------------------------------------------------------------------
 
+def apply_layer(s, x, coef):
+    """``S_{k+1} = a X + b S_k + c I`` with ``X = S_k^2`` (Eq. 19 with
+    ``W = a I`` and ``B = b S_k + c I``; plain SP2 has ``(1, 0, 0)`` and
+    ``(-1, 2, 0)``)."""
+    a, b, c = coef
+    out = a * x + b * s
+    if c:
+        out[np.diag_indices(s.shape[0])] += c
+    return out
+
+
 def _replay(h, rec):
-    """All approximations ``S_0 .. S_L`` for the recorded bounds and branches."""
+    """All approximations ``S_0 .. S_L`` for the recorded bounds and layers."""
     s = input_layer(h, rec.eps_min, rec.eps_max)
     out = [s]
-    for sign in rec.branches:
-        x = s @ s
-        s = x if sign > 0 else 2.0 * s - x
+    for coef in rec.layer_coefs:
+        s = apply_layer(s, s @ s, coef)
         out.append(s)
     return out
 
@@ -277,7 +298,8 @@ def sp2_jvp(h, h1, rec):
     density-matrix response needed by the XL-BOMD kernel of Section III).
     With the bounds fixed, ``dS_0 = -H_1 / (eps_max - eps_min)``; each layer
     differentiates to ``dS_n = S dS + dS S`` (sign +) or
-    ``2 dS - (S dS + dS S)`` (sign -); the refinement contributes
+    ``2 dS - (S dS + dS S)`` (sign -), in general ``a (S dS + dS S) + b dS``
+    for the layer ``a S^2 + b S + c I``; the refinement contributes
     ``3 (S dS + dS S) - 2 (S^2 dS + S dS S + dS S^2)``."""
     h1 = np.asarray(h1, dtype=np.float64)
     n = h.shape[0]
@@ -285,9 +307,9 @@ def sp2_jvp(h, h1, rec):
         return np.zeros((n, n))
     iters = _replay(h, rec)
     y = -h1 / (rec.eps_max - rec.eps_min)
-    for sign, s in zip(rec.branches, iters[:-1]):
+    for (a, b, _), s in zip(rec.layer_coefs, iters[:-1]):
         sy = s @ y + y @ s
-        y = sy if sign > 0 else 2.0 * y - sy
+        y = a * sy + b * y
     if rec.refine:
         s = iters[-1]
         s2 = s @ s
@@ -301,7 +323,8 @@ def sp2_vjp(h, wmat, rec):
     ``Tr(W P)`` with respect to ``H`` (bounds and branches fixed).  ``W`` is
     symmetrised first.  Walks the layers backwards: the adjoint of
     ``dS -> S dS + dS S`` is the same map, so ``G <- S G + G S`` (sign +) or
-    ``2 G - (S G + G S)`` (sign -), ending with ``-G / (eps_max - eps_min)``."""
+    ``2 G - (S G + G S)`` (sign -), in general ``a (S G + G S) + b G``,
+    ending with ``-G / (eps_max - eps_min)``."""
     n = h.shape[0]
     if rec.trivial:               # P does not depend on H
         return np.zeros((n, n))
@@ -311,9 +334,9 @@ def sp2_vjp(h, wmat, rec):
         s = iters[-1]
         s2 = s @ s
         g = 3.0 * (s @ g + g @ s) - 2.0 * (s2 @ g + s @ g @ s + g @ s2)
-    for sign, s in zip(reversed(rec.branches), reversed(iters[:-1])):
+    for (a, b, _), s in zip(reversed(rec.layer_coefs), reversed(iters[:-1])):
         sg = s @ g + g @ s
-        g = sg if sign > 0 else 2.0 * g - sg
+        g = a * sg + b * g
     return -g / (rec.eps_max - rec.eps_min)
 
 
@@ -324,17 +347,18 @@ def daleckii_krein_jvp(h, h1, rec):
     ``V [Gamma o (V^T X_1 V)] V^T`` with the divided differences
     ``Gamma_ij = p[x_i, x_j]``.  Each divided difference is built layer by
     layer from the chain rule ``(g o f)[x, y] = g[f(x), f(y)] f[x, y]`` with
-    ``[x, y] -> x + y`` for ``x^2`` and ``2 - x - y`` for ``2x - x^2`` (and
+    ``[x, y] -> x + y`` for ``x^2`` and ``2 - x - y`` for ``2x - x^2``, in
+    general ``a (x + y) + b`` for ``a x^2 + b x + c`` (and
     ``3(x+y) - 2(x^2 + x y + y^2)`` for the McWeeny step), which stays exact
     for close or equal eigenvalues."""
     w, v = np.linalg.eigh(np.asarray(h, dtype=np.float64))
     x = (rec.eps_max - w) / (rec.eps_max - rec.eps_min)
     gam = np.ones((x.size, x.size))
     u = x.copy()
-    for sign in rec.branches:
+    for a, b, c in rec.layer_coefs:
         uu = u[:, None] + u[None, :]
-        gam *= uu if sign > 0 else 2.0 - uu
-        u = u * u if sign > 0 else 2.0 * u - u * u
+        gam *= a * uu + b
+        u = a * (u * u) + (b * u + c)
     if rec.refine:
         a, b = u[:, None], u[None, :]
         gam *= 3.0 * (a + b) - 2.0 * (a * a + a * b + b * b)
