@@ -106,3 +106,65 @@ def lanczos_bounds(h, steps, seed=0, margin=0.01):
     th_lo, r_lo, th_hi, r_hi = ritz_extremes(alpha, beta)
     m = margin * (th_hi - th_lo)
     return max(g_lo, th_lo - r_lo - m), min(g_hi, th_hi + r_hi + m)
+
+
+# ---------------------------------------------------------------------------
+# HOMO/LUMO estimates from a density matrix (input of the accelerated
+# network, Section II.E)
+# ---------------------------------------------------------------------------
+
+def projected_lanczos(h, p, side, steps, shift, seed=0):
+    """Lanczos recurrence (as ``lanczos``) on the operator
+    ``A v = Q ((H - shift I) v)`` with ``Q = P`` (``side = "occupied"``) or
+    ``Q = I - P`` (``side = "virtual"``), started from ``Q u / ||Q u||``
+    (``u`` the SplitMix64 start vector).  For a projector ``P`` commuting
+    with ``H`` the vectors stay in the range of ``Q``, where ``A`` is
+    ``H - shift I`` restricted to the occupied (virtual) eigenstates.
+    Returns ``(alpha, beta)``."""
+    h = np.asarray(h, dtype=np.float64)
+    p = np.asarray(p, dtype=np.float64)
+    n = h.shape[0]
+
+    def q_of(y):
+        py = p @ y
+        return py if side == "occupied" else y - py
+
+    u = q_of(start_vector(n, seed))
+    vecs = [u * (1.0 / float(np.linalg.norm(u)))]
+    alpha, beta = [], []
+    for j in range(min(steps, n)):
+        w = q_of(h @ vecs[j] - shift * vecs[j])
+        basis = np.array(vecs).T
+        c = basis.T @ w
+        w = w - basis @ c
+        w = w - basis @ (basis.T @ w)
+        b = float(np.linalg.norm(w))
+        alpha.append(float(c[j]))
+        beta.append(b)
+        if not b > 1e-300:
+            break
+        vecs.append(w * (1.0 / b))
+    return np.array(alpha), np.array(beta)
+
+
+def homo_lumo_estimates(h, p, steps=24, seed=0, margin=0.05, bounds=None):
+    """Estimates of the highest occupied and lowest unoccupied eigenvalue of
+    ``H`` from a density matrix ``P`` of it: the largest eigenvalue of
+    ``H`` on the range of ``P`` and the smallest on the range of ``I - P``,
+    each from ``steps`` Lanczos steps (``projected_lanczos``; shifts
+    ``eps_min`` and ``eps_max``, the spectral bounds, so that the zero
+    eigenvalue of the complement stays on the inner side), widened outwards
+    by its Ritz residual norm (HOMO up, LUMO down), then the interval
+    between them shrunk by ``margin`` of its width on each side.  Returns
+    ``(homo, lumo)``, or ``None`` when no gap remains."""
+    eps_min, eps_max = gershgorin_bounds(h) if bounds is None else bounds
+    a, b = projected_lanczos(h, p, "occupied", steps, eps_min, seed)
+    _, _, th_hi, r_hi = ritz_extremes(a, b)
+    a, b = projected_lanczos(h, p, "virtual", steps, eps_max, seed)
+    th_lo, r_lo, _, _ = ritz_extremes(a, b)
+    homo = th_hi + eps_min + r_hi
+    lumo = th_lo + eps_max - r_lo
+    gap = lumo - homo
+    if not gap > 0.0:
+        return None
+    return homo + margin * gap, lumo - margin * gap

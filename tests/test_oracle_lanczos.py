@@ -109,3 +109,51 @@ def test_tighter_bounds_need_fewer_layers_same_result():
     p_ref = oracle.density_matrix_eigh(h, 400)[0]
     assert rec_l.n_iter < rec_g.n_iter
     assert np.max(np.abs(p_l - p_ref)) < 1e-8 and np.max(np.abs(p_g - p_ref)) < 1e-8
+
+
+# --- HOMO/LUMO estimates from a density matrix -------------------------------
+
+def test_projected_lanczos_is_exact_on_the_projected_subspace():
+    """With k equal to the dimension of the range of Q and distinct
+    eigenvalues there, the Ritz values are exactly those eigenvalues of H
+    (minus the shift): the recurrence stays in the occupied (virtual)
+    eigenspace of H."""
+    h, q, e = random_orthogonal_hamiltonian(24, 10, seed=4, return_factors=True)
+    order = np.argsort(e)
+    p = q[:, order[:10]] @ q[:, order[:10]].T
+    for side, idx, shift in (("occupied", order[:10], -3.0), ("virtual", order[10:], 3.0)):
+        k = len(idx)
+        a, b = lz.projected_lanczos(h, p, side, k + 1, shift)
+        t = np.diag(a[:k]) + np.diag(b[:k - 1], 1) + np.diag(b[:k - 1], -1)
+        np.testing.assert_allclose(np.linalg.eigvalsh(t), np.sort(e[idx]) - shift, atol=1e-10)
+        assert abs(b[k]) < 1e-12   # one step more: the Krylov space is exhausted
+
+
+@pytest.mark.parametrize("m,seed", [(32, 0), (64, 0), (32, 3)])
+def test_homo_lumo_estimates_lie_inside_the_gap(m, seed):
+    """The estimates bracket a sub-interval of the true HOMO-LUMO gap (the
+    side the accelerated network needs) and keep most of its width."""
+    h = water_box_hamiltonian(m, seed=seed)
+    n_occ = 4 * m
+    p, w, _ = oracle.density_matrix_eigh(h, n_occ)
+    for steps in (16, 24):
+        homo, lumo = lz.homo_lumo_estimates(h, p, steps)
+        assert w[n_occ - 1] <= homo < lumo <= w[n_occ]
+        assert lumo - homo >= 0.6 * (w[n_occ] - w[n_occ - 1])
+
+
+def test_homo_lumo_estimates_c1():
+    h, q, e = random_orthogonal_hamiltonian(256, 128, seed=0, return_factors=True)
+    p = oracle.density_matrix_eigh(h, 128)[0]
+    homo, lumo = lz.homo_lumo_estimates(h, p, 24, margin=0.0)
+    assert e[:128].max() <= homo < lumo <= e[128:].min()
+    assert lumo - homo >= 0.5 * (e[128:].min() - e[:128].max())
+
+
+def test_homo_lumo_estimates_margin_shrinks_symmetrically():
+    h = water_box_hamiltonian(32, seed=0)
+    p = oracle.density_matrix_eigh(h, 128)[0]
+    h0, l0 = lz.homo_lumo_estimates(h, p, 16, margin=0.0)
+    h1, l1 = lz.homo_lumo_estimates(h, p, 16, margin=0.1)
+    assert h1 - h0 == pytest.approx(0.1 * (l0 - h0), rel=1e-12)
+    assert l0 - l1 == pytest.approx(0.1 * (l0 - h0), rel=1e-12)
