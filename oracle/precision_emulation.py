@@ -14,14 +14,17 @@ each mode, ``square_emulated`` equals the exact FP64 sum of the products of
 Eq. (22) (with the 2^-28 rescale for the scaled FP16 pair; X0 X0 alone for the
 single pass); ``automatic_stall_gate`` against closed forms;
 ``sp2_emulated("fp32")`` bitwise against a plain FP32 loop written out in
-the test; every mode's error against the exact density matrix within
-[1/64, 2] of its operand roundoff times the Gershgorin width.
+the test (plain and accelerated); every mode's error against the exact
+density matrix within [1/64, 2] of its operand roundoff times the
+Gershgorin width (plain and accelerated); estimates outside the spectrum
+leave the plain network bit for bit.
 """
 
 from __future__ import annotations
 
 import numpy as np
 
+from .accelerated import acceleration_schedule, layer_polynomial, mapped_interval
 from .sp2_oracle import (FP16_SPLIT_SCALE_LOG2, STALL_GATE, choose_branch, gershgorin_bounds,
                          should_stop, split_bf16, split_fp16_scaled)
 
@@ -63,10 +66,13 @@ def automatic_stall_gate(n, mode):
 
 
 def sp2_emulated(h, n_occ, mode, tol=1e-5, max_iter=100, stop_rule=1, stall_gate=None,
-                 refine=True, bounds=None):
+                 refine=True, bounds=None, homo=None, lumo=None):
     """FP32-stored DNN-SP2 with the layer squares of ``mode``; the traces,
     bounds and decisions are FP64 as on the GPU.  ``bounds`` overrides the
     Gershgorin bounds; ``stall_gate=None`` takes ``automatic_stall_gate``.
+    With ``homo`` and ``lumo`` the first layers follow the accelerated
+    schedule (``oracle.accelerated``), ``S <- a S^2 + b S + c I`` with the
+    coefficients rounded to FP32 and ``c`` added to the diagonal.
     Returns ``(P, n_iter)``."""
     h = np.asarray(h, dtype=np.float32)
     n = h.shape[0]
@@ -74,6 +80,11 @@ def sp2_emulated(h, n_occ, mode, tol=1e-5, max_iter=100, stop_rule=1, stall_gate
         stall_gate = automatic_stall_gate(n, mode)
     lo_b, hi_b = gershgorin_bounds(h.astype(np.float64)) if bounds is None else bounds
     s = ((hi_b * np.eye(n) - h.astype(np.float64)) / (hi_b - lo_b)).astype(np.float32)
+    sched = []
+    if homo is not None:
+        l, hh = mapped_interval(lo_b, hi_b, homo, lumo)
+        sched = [layer_polynomial(sg, sh) for sg, sh, _, _ in acceleration_schedule(l, hh, max_iter)]
+    diag = np.diag_indices(n)
     errs = []
     layers = 0
     for k in range(max_iter + 1):
@@ -83,9 +94,14 @@ def sp2_emulated(h, n_occ, mode, tol=1e-5, max_iter=100, stop_rule=1, stall_gate
         errs.append(abs(t1 - t2))
         if should_stop(k, errs, abs(t1 - n_occ), tol, stop_rule, stall_gate) or k == max_iter:
             break
-        sign = choose_branch(t1, t2, n_occ)
         sq = square_emulated(s, mode).astype(np.float32)
-        s = sq if sign > 0 else np.float32(2.0) * s - sq
+        if k < len(sched):
+            a, b, c = sched[k]
+            s = np.float32(a) * sq + np.float32(b) * s
+            s[diag] += np.float32(c)
+        else:
+            sign = choose_branch(t1, t2, n_occ)
+            s = sq if sign > 0 else np.float32(2.0) * s - sq
         s = np.triu(s) + np.triu(s, 1).T          # upper triangle mirrored, as computed
         layers += 1
     if refine:

@@ -95,7 +95,7 @@ def test_automatic_stall_gate_closed_forms():
     assert emu.automatic_stall_gate(2 ** 28, "fp32") == 1.0
 
 
-def _plain_fp32_sp2(h, n_occ, tol, stall_gate, refine):
+def _plain_fp32_sp2(h, n_occ, tol, stall_gate, refine, coefs=()):
     """FP32-stored SP2 written out step by step: FP64 Gershgorin discs, the
     reversed linear map rounded to FP32, then per layer FP64 traces of the
     FP32 iterate, the stop test and branch rule of the FP64 oracle, an FP32
@@ -116,8 +116,14 @@ def _plain_fp32_sp2(h, n_occ, tol, stall_gate, refine):
         if orc.should_stop(k, errs, abs(t1 - n_occ), tol, 1, stall_gate) or k == 100:
             break
         sq = np.matmul(s, s, dtype=np.float32)
-        plus = abs(t2 - n_occ) <= abs(2.0 * t1 - t2 - n_occ)
-        s = sq if plus else np.float32(2.0) * s - sq
+        if k < len(coefs):     # accelerated layer: a S^2 + b S, then c on the diagonal
+            a, b, c = coefs[k]
+            s = np.float32(a) * sq + np.float32(b) * s
+            for i in range(n):
+                s[i, i] = s[i, i] + np.float32(c)
+        else:
+            plus = abs(t2 - n_occ) <= abs(2.0 * t1 - t2 - n_occ)
+            s = sq if plus else np.float32(2.0) * s - sq
         s = np.triu(s) + np.triu(s, 1).T
         layers += 1
     if refine:
@@ -135,6 +141,47 @@ def test_fp32_emulation_equals_a_plain_fp32_loop(refine, n_occ):
     assert nl == ml and nl > 10
     assert p.dtype == np.float32
     assert np.array_equal(p, q)       # the same FP32 operations in the same order
+
+
+def test_accelerated_fp32_emulation_equals_a_plain_fp32_loop():
+    from oracle import accelerated as acc
+    h, q, e = random_orthogonal_hamiltonian(48, 20, seed=3, return_factors=True)
+    h = h.astype(np.float32)
+    homo, lumo = e[:20].max() + 0.02, e[20:].min() - 0.02
+    lo_b, hi_b = orc.gershgorin_bounds(h.astype(np.float64))
+    l, hh = acc.mapped_interval(lo_b, hi_b, homo, lumo)
+    coefs = [acc.layer_polynomial(sg, sh) for sg, sh, _, _ in acc.acceleration_schedule(l, hh)]
+    p, nl = emu.sp2_emulated(h, 20, "fp32", tol=1e-5, refine=True, homo=homo, lumo=lumo)
+    q2, ml = _plain_fp32_sp2(h, 20, 1e-5, emu.automatic_stall_gate(48, "fp32"), True, coefs)
+    assert nl == ml and 5 < nl < 15
+    assert np.array_equal(p, q2)
+
+
+def test_emulation_with_estimates_outside_the_spectrum_is_the_plain_network():
+    h = random_orthogonal_hamiltonian(48, 20, seed=5).astype(np.float32)
+    _, hi_b = orc.gershgorin_bounds(h.astype(np.float64))
+    for mode in ("fp32", "bf16x3"):
+        p0, n0 = emu.sp2_emulated(h, 20, mode)
+        p1, n1 = emu.sp2_emulated(h, 20, mode, homo=hi_b + 1.0, lumo=hi_b + 2.0)
+        assert n0 == n1 and np.array_equal(p0, p1)
+
+
+@pytest.mark.parametrize("mode,bits", [("fp32", 24), ("fp16x3", 22), ("bf16x3", 16), ("bf16x1", 8)])
+def test_accelerated_emulated_error_follows_operand_precision(mode, bits):
+    """The accelerated network lands in the same band, [1/64, 2] of u times
+    the Gershgorin width, with fewer layers."""
+    for seed in (6, 7):
+        h, q, e = random_orthogonal_hamiltonian(96, 48, seed=seed, return_factors=True)
+        h = h.astype(np.float32)
+        p_ref = oracle.density_matrix_eigh(h.astype(np.float64), 48)[0]
+        lo_b, hi_b = orc.gershgorin_bounds(h.astype(np.float64))
+        homo, lumo = e[:48].max(), e[48:].min()
+        p, nl = emu.sp2_emulated(h, 48, mode, tol=1e-7, homo=homo, lumo=lumo)
+        _, nl0 = emu.sp2_emulated(h, 48, mode, tol=1e-7)
+        err = oracle.error_metrics(p, p_ref)["fro_over_sqrt_n"]
+        scale = 2.0 ** -bits * (hi_b - lo_b)
+        assert scale / 64 < err < 2 * scale
+        assert nl < nl0
 
 
 @pytest.mark.parametrize("mode,bits", [("fp32", 24), ("fp16x3", 22), ("bf16x3", 16), ("bf16x1", 8)])
