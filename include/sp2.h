@@ -151,6 +151,27 @@ sp2_status sp2_density_ex(const float* H, int64_t n, int64_t ld, int64_t n_occ,
                           uint8_t* branches, int32_t branches_cap,
                           void* workspace, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the solve
+ * of sp2_density_ex without a caller workspace.  The library keeps its
+ * workspace in a static device array of SP2_NOALLOC_SCRATCH_BYTES (136 MiB),
+ * one copy per device, held until the process ends; this call runs no
+ * allocating routine (no hipMalloc/hipFree, no pinned host memory, no event
+ * creation) and reads its status back through plain host memory,
+ * synchronising the stream once per chunk of layers.  Arguments, layout and results are those of
+ * sp2_density_ex; the caller still owns H and P.
+ * Limits: no derivative tape (opt->checkpoint_every must be 0) and no layer
+ * timing (SP2_FLAG_TIME_LAYERS must be clear); n must satisfy
+ * sp2_workspace_bytes(n, opt) <= SP2_NOALLOC_SCRATCH_BYTES (n <= 2048 with
+ * default options).  Violations return SP2_ERR_INVALID_ARG before any work.
+ * Every call on a device shares that device's array and overwrites what the
+ * previous call left there, so calls that overlap in time on one device
+ * (several host threads or streams) race; serialise them. */
+#define SP2_NOALLOC_SCRATCH_BYTES ((size_t)136 << 20)
+sp2_status sp2_density_noalloc(const float* H, int64_t n, int64_t ld, int64_t n_occ,
+                               const sp2_options* opt, float* P, sp2_info* info,
+                               uint8_t* branches, int32_t branches_cap, void* stream);
+
 /* Forward derivative (density-matrix response, as needed for the XL-BOMD
  * kernel of Section III): P1 = dP/dH [H1] of the network recorded by the
  * last sp2_density_ex call on this workspace, with the spectral bounds and

@@ -42,7 +42,7 @@ EXPORTED = ["sp2_default_options", "sp2_workspace_bytes", "sp2_density", "sp2_de
             "sp2_jvp", "sp2_vjp", "sp2_bounds", "sp2_spectral_bounds", "sp2_split", "sp2_layer",
             "sp2_mulliken", "sp2_xl_scratch_bytes", "sp2_xl_response", "sp2_xl_kernel",
             "sp2_nvt_gamma_tc", "sp2_nvt_first_half", "sp2_nvt_second_half", "sp2_last_error",
-            "sp2_history"]
+            "sp2_history", "sp2_density_noalloc"]
 SP2_XL_MAX_RANK = 32
 
 
@@ -98,6 +98,9 @@ def load_library(path=None):
     lib.sp2_density_ex.argtypes = [vp, c_int64, c_int64, c_int64, ctypes.POINTER(sp2_options), vp,
                                    ctypes.POINTER(sp2_info), vp, c_int32, vp, c_size_t, vp]
     lib.sp2_density_ex.restype = c_int32
+    lib.sp2_density_noalloc.argtypes = [vp, c_int64, c_int64, c_int64, ctypes.POINTER(sp2_options),
+                                        vp, ctypes.POINTER(sp2_info), vp, c_int32, vp]
+    lib.sp2_density_noalloc.restype = c_int32
     lib.sp2_jvp.argtypes = [vp, c_size_t, vp, c_int64, vp, vp]
     lib.sp2_jvp.restype = c_int32
     lib.sp2_vjp.argtypes = [vp, c_size_t, vp, c_int64, vp, vp]
@@ -230,6 +233,23 @@ def sp2_density_ex(H, n_occ, opt, P, workspace, branches_cap=SP2_MAX_ITER, check
     st = lib.sp2_density_ex(_dev_ptr(H, name="H"), n, H.stride(0), int(n_occ), ctypes.byref(opt),
                             _dev_ptr(P, name="P"), ctypes.byref(info), br, branches_cap,
                             c_void_p(workspace.data_ptr()), workspace.numel(), _stream(H.device))
+    if check:
+        _check(st, allow=(SP2_ERR_NOT_CONVERGED,))
+    return st, info, bytes(br[:min(info.n_iter, branches_cap)])
+
+
+def sp2_density_noalloc(H, n_occ, opt, P, branches_cap=SP2_MAX_ITER, check=True):
+    """``sp2_density_ex`` on the library's static scratch (no workspace).
+    Returns ``(status, info, branches)``."""
+    lib = load_library()
+    n = H.shape[0]
+    if P.stride(0) != H.stride(0):
+        raise ValueError("H and P must have the same leading dimension")
+    info = sp2_info()
+    br = (ctypes.c_uint8 * max(1, branches_cap))()
+    st = lib.sp2_density_noalloc(_dev_ptr(H, name="H"), n, H.stride(0), int(n_occ),
+                                 ctypes.byref(opt), _dev_ptr(P, name="P"), ctypes.byref(info), br,
+                                 branches_cap, _stream(H.device))
     if check:
         _check(st, allow=(SP2_ERR_NOT_CONVERGED,))
     return st, info, bytes(br[:min(info.n_iter, branches_cap)])

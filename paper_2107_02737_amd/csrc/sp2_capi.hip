@@ -11,6 +11,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <string>
 #include <vector>
 
@@ -22,6 +23,14 @@
 #include "sp2_xl.hpp"
 
 using namespace sp2;
+
+// Library-owned workspace of sp2_density_noalloc, for callers that cannot
+// allocate device memory.  Each device that runs the library holds its own
+// copy until the process ends; every sp2_density_noalloc call on a device
+// uses that device's copy (calls that overlap in time on one device race).
+// Host code reaches it only through the address hipGetSymbolAddress returns.
+static constexpr size_t kNoAllocScratchBytes = SP2_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 
 namespace {
 
@@ -661,6 +670,17 @@ sp2_status read_back(const WS& w, HostMirror* hm, bool with_hist, hipStream_t st
   return SP2_OK;
 }
 
+constexpr int kMaxDevices = 64;
+
+sp2_status check_density_args(const float* H, int64_t n, int64_t ld, int64_t n_occ,
+                              const sp2_options& o, const float* P, const uint8_t* branches,
+                              int32_t branches_cap, Layout& L);
+sp2_status noalloc_scratch(void** out);
+sp2_status density_impl(const float* H, int64_t n, int64_t ld, int64_t n_occ, const sp2_options& o,
+                        const Layout& L, float* P, sp2_info* info, uint8_t* branches,
+                        int32_t branches_cap, void* workspace, hipStream_t st, HostMirror* hm,
+                        bool pinned);
+
 }  // namespace
 
 // ===========================================================================
@@ -700,18 +720,81 @@ sp2_status sp2_density_ex(const float* H, int64_t n, int64_t ld, int64_t n_occ,
   sp2_options o;
   sp2_default_options(&o);
   if (opt) o = *opt;
+  Layout L;
+  if (sp2_status s = check_density_args(H, n, ld, n_occ, o, P, branches, branches_cap, L)) return s;
+  if (sp2_status s = check_ws(L, workspace, ws_bytes)) return s;
+  HostMirror* hm;
+  if (sp2_status s = host_mirror(&hm)) return s;
+  return density_impl(H, n, ld, n_occ, o, L, P, info, branches, branches_cap, workspace,
+                      static_cast<hipStream_t>(stream), hm, true);
+}
+
+sp2_status sp2_density_noalloc(const float* H, int64_t n, int64_t ld, int64_t n_occ,
+                               const sp2_options* opt, float* P, sp2_info* info,
+                               uint8_t* branches, int32_t branches_cap, void* stream) {
+  g_err.clear();
+  sp2_options o;
+  sp2_default_options(&o);
+  if (opt) o = *opt;
+  Layout L;
+  if (sp2_status s = check_density_args(H, n, ld, n_occ, o, P, branches, branches_cap, L)) return s;
+  if (o.checkpoint_every != 0)
+    return fail(SP2_ERR_INVALID_ARG, "sp2_density_noalloc keeps no derivative tape");
+  if (o.flags & SP2_FLAG_TIME_LAYERS)
+    return fail(SP2_ERR_INVALID_ARG, "sp2_density_noalloc does not time layers");
+  if (L.total > kNoAllocScratchBytes)
+    return fail(SP2_ERR_INVALID_ARG, "n = %lld needs %zu bytes of scratch; the static scratch holds %zu",
+                static_cast<long long>(n), L.total, kNoAllocScratchBytes);
+  void* ws = nullptr;
+  if (sp2_status s = noalloc_scratch(&ws)) return s;
+  thread_local HostMirror pageable;   // plain host memory: no pinned allocation
+  return density_impl(H, n, ld, n_occ, o, L, P, info, branches, branches_cap, ws,
+                      static_cast<hipStream_t>(stream), &pageable, false);
+}
+
+}  // extern "C"
+
+namespace {
+
+sp2_status check_density_args(const float* H, int64_t n, int64_t ld, int64_t n_occ,
+                              const sp2_options& o, const float* P, const uint8_t* branches,
+                              int32_t branches_cap, Layout& L) {
   if (!H || !P) return fail(SP2_ERR_INVALID_ARG, "H and P must be non-NULL");
   if (n <= 0 || ld < n) return fail(SP2_ERR_INVALID_ARG, "need n > 0 and ld >= n");
   if (n_occ < 0 || n_occ > n) return fail(SP2_ERR_INVALID_ARG, "n_occ must lie in [0, n]");
   if (!options_ok(o)) return fail(SP2_ERR_INVALID_ARG, "invalid options");
   if (branches_cap < 0 || (branches_cap > 0 && !branches))
     return fail(SP2_ERR_INVALID_ARG, "branches buffer missing");
-  Layout L;
   if (!make_layout(n, o, L)) return fail(SP2_ERR_INVALID_ARG, "matrix order out of range");
-  if (sp2_status s = check_ws(L, workspace, ws_bytes)) return s;
-  HostMirror* hm;
-  if (sp2_status s = host_mirror(&hm)) return s;
-  hipStream_t st = static_cast<hipStream_t>(stream);
+  return SP2_OK;
+}
+
+// Device address of the static scratch array on the current device, looked
+// up once per device (each device holds its own copy of the array).
+sp2_status noalloc_scratch(void** out) {
+  static std::atomic<void*> table[kMaxDevices];
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(SP2_ERR_DEVICE, "device index %d out of range", dev);
+  void* p = table[dev].load(std::memory_order_acquire);
+  if (!p) {
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p || reinterpret_cast<uintptr_t>(p) % 256)
+      return fail(SP2_ERR_DEVICE, "static scratch missing or misaligned");
+    table[dev].store(p, std::memory_order_release);
+  }
+  *out = p;
+  return SP2_OK;
+}
+
+// One solve on a bound workspace.  `pinned`: hm is pinned host memory, and
+// the layer loop polls the stop flag of chunk c asynchronously (events)
+// while chunk c+1 runs; otherwise (plain host memory) it synchronises the
+// stream after every chunk.
+sp2_status density_impl(const float* H, int64_t n, int64_t ld, int64_t n_occ, const sp2_options& o,
+                        const Layout& L, float* P, sp2_info* info, uint8_t* branches,
+                        int32_t branches_cap, void* workspace, hipStream_t st, HostMirror* hm,
+                        bool pinned) {
   WS w;
   bind(w, workspace, L);
   const int prec = o.precision;
@@ -766,9 +849,12 @@ sp2_status sp2_density_ex(const float* H, int64_t n, int64_t ld, int64_t n_occ,
   const int refine_ev = o.max_iter;   // event pair index of the refinement
 
   // Layer loop in chunks; poll the stop flag of chunk c while chunk c+1 runs.
-  EventPool* pool = nullptr;
-  HIP_TRY(event_pool(&pool, 0));
-  hipEvent_t* ev = pool->poll;
+  hipEvent_t* ev = nullptr;
+  if (pinned) {
+    EventPool* pool = nullptr;
+    HIP_TRY(event_pool(&pool, 0));
+    ev = pool->poll;
+  }
   int launched = 0, chunk = 0;
   bool stopped = false;
   sp2_status err = SP2_OK;
@@ -797,6 +883,13 @@ sp2_status sp2_density_ex(const float* H, int64_t n, int64_t ld, int64_t n_occ,
     if (err != SP2_OK) break;
     const int slot = chunk & 1;
     hipError_t e = hipMemcpyAsync(&hm->ctrl[slot], w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st);
+    if (!pinned) {
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) { err = fail(SP2_ERR_DEVICE, "poll: %s", hipGetErrorString(e)); break; }
+      if (hm->ctrl[slot].stopped) stopped = true;
+      ++chunk;
+      continue;
+    }
     if (e == hipSuccess) e = hipEventRecord(ev[slot], st);
     if (e != hipSuccess) { err = fail(SP2_ERR_DEVICE, "poll: %s", hipGetErrorString(e)); break; }
     if (chunk > 0) {
@@ -882,6 +975,10 @@ sp2_status sp2_density_ex(const float* H, int64_t n, int64_t ld, int64_t n_occ,
   if (info) info->status = ret;
   return ret;
 }
+
+}  // namespace
+
+extern "C" {
 
 sp2_status sp2_density(const float* H, int64_t n, int64_t n_occ, double tol, float* P,
                        int32_t* n_iter, uint8_t* branches, int32_t branches_cap, void* workspace,

@@ -199,3 +199,28 @@ def test_nvt_entry_points_reject_bad_arguments(lib):
             _lib.SP2_ERR_INVALID_ARG
     assert lib.sp2_nvt_second_half(None, fake, fake, 8, ctypes.byref(good), None) == \
         _lib.SP2_ERR_INVALID_ARG
+
+
+def test_noalloc_limits_rejected_before_device_work(lib):
+    """sp2_density_noalloc refuses a tape, layer timing and orders whose
+    workspace exceeds the static scratch, before any HIP call."""
+    from paper_2107_02737_amd import _lib
+    limit = 136 << 20
+    o = _lib.sp2_default_options()
+    assert _lib.sp2_workspace_bytes(2048, o) <= limit < _lib.sp2_workspace_bytes(2049, o)
+    info = _lib.sp2_info()
+    dummy = ctypes.c_void_p(256)
+
+    def call(n, opt):
+        return lib.sp2_density_noalloc(dummy, n, n, n // 2, ctypes.byref(opt), dummy,
+                                       ctypes.byref(info), None, 0, None)
+    assert call(2049, o) == _lib.SP2_ERR_INVALID_ARG
+    assert "static scratch" in _lib.sp2_last_error()
+    o.checkpoint_every = 4
+    assert call(256, o) == _lib.SP2_ERR_INVALID_ARG
+    o = _lib.sp2_default_options()
+    o.flags = _lib.SP2_FLAG_TIME_LAYERS
+    assert call(256, o) == _lib.SP2_ERR_INVALID_ARG
+    o = _lib.sp2_default_options()
+    assert call(0, o) == _lib.SP2_ERR_INVALID_ARG
+
