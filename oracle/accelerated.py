@@ -29,10 +29,14 @@ picture of Section II.D:
   minimises the folded interval's image.  The interval ends follow the
   same maps exactly, so the whole schedule is fixed by ``(l, h)`` before
   the first product.  It runs while ``max(l, 1 - h) >= ACC_END``; after it
-  the trace-driven branch rule of plain DNN-SP2 takes over, so a schedule
-  built on poor estimates still ends with the right occupation or with no
-  convergence (the stop test keeps its trace condition), never with a
-  wrong P reported as converged.
+  the trace-driven branch rule of plain DNN-SP2 takes over.
+* Check at the end of the schedule: with estimates that bracket part of the
+  gap, every eigenvalue has been driven to its side by then, so
+  ``|Tr S - n_occ| < 1/2``.  If not, the estimates were wrong; the
+  eigenvalues they put on the wrong side sit next to those of the right
+  one (in finite precision they can no longer be told apart), so the
+  iterate is dropped and the plain network runs from the start
+  (``record.fallback``).
 * The stop test and refinement are those of ``sp2_oracle.sp2``.
 
 Pins (tests/test_oracle_accelerated.py): agreement with the diagonalisation
@@ -43,8 +47,8 @@ theorem, P; each layer polynomial against its defining values (``p+(s) =
 images of eigenvalues placed exactly at them; [0, 1] maps into itself for
 every shift; zero-width intervals give no schedule (plain SP2 bit for bit);
 fewer layers than plain SP2 on the c1/water workloads (scalar probe: 26 ->
-16, 28 -> 16 with Gershgorin bounds); estimates that miss the gap still end
-in the right P through the trace-driven tail.
+16, 28 -> 16 with Gershgorin bounds); estimates that miss the gap fail the
+end-of-schedule check and end in the plain network's P.
 """
 
 from __future__ import annotations
@@ -52,7 +56,7 @@ from __future__ import annotations
 import numpy as np
 
 from .sp2_oracle import (SP2Record, STALL_GATE, apply_layer, choose_branch, gershgorin_bounds,
-                         input_layer, mcweeny, should_stop)
+                         input_layer, mcweeny, should_stop, sp2, sp2_scalar)
 
 # The schedule stops once both mapped intervals are this close to 0 and 1.
 ACC_END = 1e-14
@@ -141,6 +145,10 @@ def sp2_accelerated(h, n_occ, homo, lumo, tol=1e-10, max_iter=100, stop_rule=0,
             break
         if k == max_iter:
             break
+        if sched and k == len(sched) and not abs(t1 - n_occ) < 0.5:
+            d, rec0 = sp2(h, n_occ, tol, max_iter, stop_rule, stall_gate, (eps_min, eps_max), refine)
+            rec0.fallback = True
+            return (d, rec0, None) if return_iterates else (d, rec0)
         if k < len(sched):
             a, b, c = sched[k]
         else:
@@ -176,6 +184,10 @@ def sp2_accelerated_scalar(w, n_occ, eps_min, eps_max, homo, lumo, tol=1e-10, ma
             break
         if k == max_iter:
             break
+        if sched and k == len(sched) and not abs(t1 - n_occ) < 0.5:
+            x0, rec0 = sp2_scalar(w, n_occ, eps_min, eps_max, tol, max_iter, stop_rule, stall_gate)
+            rec0.fallback = True
+            return x0, rec0
         if k < len(sched):
             a, b, c = sched[k]
         else:

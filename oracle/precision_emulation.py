@@ -72,7 +72,8 @@ def sp2_emulated(h, n_occ, mode, tol=1e-5, max_iter=100, stop_rule=1, stall_gate
     Gershgorin bounds; ``stall_gate=None`` takes ``automatic_stall_gate``.
     With ``homo`` and ``lumo`` the first layers follow the accelerated
     schedule (``oracle.accelerated``), ``S <- a S^2 + b S + c I`` with the
-    coefficients rounded to FP32 and ``c`` added to the diagonal.
+    coefficients rounded to FP32 and ``c`` added to the diagonal, and the
+    end-of-schedule trace check falls back to the plain network.
     Returns ``(P, n_iter)``."""
     h = np.asarray(h, dtype=np.float32)
     n = h.shape[0]
@@ -94,6 +95,10 @@ def sp2_emulated(h, n_occ, mode, tol=1e-5, max_iter=100, stop_rule=1, stall_gate
         errs.append(abs(t1 - t2))
         if should_stop(k, errs, abs(t1 - n_occ), tol, stop_rule, stall_gate) or k == max_iter:
             break
+        if sched and k == len(sched) and not abs(t1 - n_occ) < 0.5:
+            # end-of-schedule check failed: the plain network from the start
+            return sp2_emulated(h, n_occ, mode, tol, max_iter, stop_rule, stall_gate, refine,
+                                (lo_b, hi_b))
         sq = square_emulated(s, mode).astype(np.float32)
         if k < len(sched):
             a, b, c = sched[k]

@@ -159,6 +159,7 @@ class SP2Record:
     refine: bool = False
     trivial: bool = False     # n_occ in {0, N}: P = 0 or I, independent of H
     coefs: list = field(default_factory=list)   # (a, b, c) per layer when not plain
+    fallback: bool = False    # an accelerated network failed its end-of-schedule check
 
     @property
     def n_iter(self):

@@ -158,23 +158,37 @@ def test_estimates_outside_the_spectrum_reduce_to_plain_sp2():
 
 
 @pytest.mark.parametrize("shift_into", ["occupied", "virtual"])
-def test_estimates_that_miss_the_gap_do_not_give_a_wrong_converged_p(shift_into):
-    """Estimates whose 'gap' lies inside the occupied (or virtual) band: the
-    schedule folds the wrong states or not, but the trace-driven tail and
-    the stop test's trace condition leave either the right P or a run that
-    does not converge -- never a wrong P reported as converged."""
+def test_estimates_that_miss_the_gap_fall_back_to_the_plain_network(shift_into):
+    """Estimates whose 'gap' lies inside the occupied band (below the 64-fold
+    degenerate HOMO level of this box) or the virtual band: the schedule
+    drives 20 or more states to the wrong side, the trace at its end is off,
+    and the plain network runs instead -- the same P and record as the
+    oracle's plain network with the same bounds."""
     hw = water_box_hamiltonian(32, seed=2)
     n_occ = 128
     p_ref, w, _ = oracle.density_matrix_eigh(hw, n_occ)
     if shift_into == "occupied":
-        homo, lumo = w[n_occ - 40], w[n_occ - 20]
+        homo, lumo = w[n_occ - 100], w[n_occ - 80]
+        assert lumo < w[n_occ - 65] < w[n_occ - 1] - 0.1
     else:
         homo, lumo = w[n_occ + 10], w[n_occ + 30]
     p, rec = acc.sp2_accelerated(hw, n_occ, homo, lumo, max_iter=100)
-    if rec.converged:
-        assert np.linalg.norm(p - p_ref) / np.sqrt(192) < 1e-8
-    else:
-        assert abs(np.trace(p) - n_occ) >= 0.5 or rec.err[-1] >= 1e-10
+    assert rec.fallback and rec.converged
+    p0, rec0 = oracle.sp2(hw, n_occ)
+    assert rec.branches == rec0.branches and np.array_equal(p, p0)
+    assert np.linalg.norm(p - p_ref) / np.sqrt(192) < 1e-8
+    ws = np.linalg.eigvalsh(hw)
+    x, rs = acc.sp2_accelerated_scalar(ws, n_occ, rec.eps_min, rec.eps_max, homo, lumo)
+    assert rs.fallback and rs.branches == rec0.branches
+
+
+def test_estimates_inside_the_gap_do_not_fall_back():
+    hw = water_box_hamiltonian(32, seed=2)
+    w = np.linalg.eigvalsh(hw)
+    for frac in (0.0, 0.2, 0.45):
+        g = w[128] - w[127]
+        _, rec = acc.sp2_accelerated(hw, 128, w[127] + frac * g, w[128] - frac * g)
+        assert rec.converged and not rec.fallback
 
 
 def test_derivatives_of_the_accelerated_network():
