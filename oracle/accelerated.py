@@ -24,9 +24,16 @@ picture of Section II.D:
   ``0 <= s <= 1/2``.  ``s = 0`` gives the plain SP2 layers ``x^2`` and
   ``2x - x^2``; every such map sends [0, 1] into [0, 1].
 * Schedule: ``+`` when the virtual interval is the wider one
-  (``l >= 1 - h``), else ``-``; the shift is half the width of the interval
-  being folded (``s = l/2`` for ``+``, ``(1 - h)/2`` for ``-``), which
-  minimises the folded interval's image.  The interval ends follow the
+  (``l >= 1 - h``), else ``-``; the shift is the fraction ``FOLD = 0.4`` of
+  the width of the interval being folded (``s = 0.4 l`` for ``+``,
+  ``0.4 (1 - h)`` for ``-``).  Half the width would minimise the folded
+  interval's image (fewest layers), but each shift also widens the other
+  side's distance from its target by ``1/(1 - s)``, which slows the growth
+  of the gap between the two intervals and so amplifies early rounding
+  more: in the FP32-storage emulation (water N = 1536 and a c2-type
+  N = 1024, Gershgorin and Lanczos bounds, FP16 pairs) 0.5 cost up to 1.7x
+  the plain network's error, 0.4 stayed within 0.8-1.4x of it at 15-24
+  layers instead of 23-42.  The interval ends follow the
   same maps exactly, so the whole schedule is fixed by ``(l, h)`` before
   the first product.  It runs while ``max(l, 1 - h) >= ACC_END``; after it
   the trace-driven branch rule of plain DNN-SP2 takes over.
@@ -37,7 +44,14 @@ picture of Section II.D:
   one (in finite precision they can no longer be told apart), so the
   iterate is dropped and the plain network runs from the start
   (``record.fallback``).
-* The stop test and refinement are those of ``sp2_oracle.sp2``.
+* The stop test and refinement are those of ``sp2_oracle.sp2``, with one
+  change for the stagnation rule (``e_k >= e_{k-2}`` taken as the rounding
+  floor): inside the schedule ``e_k`` can rise by itself (two layers of the
+  same sign, and each shift scales the other side's distance from its
+  target by up to ``1/(1 - s)``), so the comparison is allowed only from the
+  iterate whose tracked width ``max(l_k, 1 - h_k)`` is below the unit
+  roundoff ``u`` of the layer arithmetic (then only rounding moves ``e``),
+  or from the end of the schedule.
 
 Pins (tests/test_oracle_accelerated.py): agreement with the diagonalisation
 (``density_matrix_eigh``); the scalar recursion on the eigenvalues
@@ -60,6 +74,8 @@ from .sp2_oracle import (SP2Record, STALL_GATE, apply_layer, choose_branch, gers
 
 # The schedule stops once both mapped intervals are this close to 0 and 1.
 ACC_END = 1e-14
+# Shift of a layer as a fraction of the width of the interval it folds.
+FOLD = 0.4
 
 
 def mapped_interval(eps_min, eps_max, homo, lumo):
@@ -90,29 +106,45 @@ def acceleration_schedule(l, h, max_len=100, end=ACC_END):
         return out
     while len(out) < max_len and max(l, 1.0 - h) >= end:
         if l >= 1.0 - h:
-            s = 0.5 * l
+            s = FOLD * l
             d = 1.0 - s
-            q, r = s / d, (h - s) / d
+            q, r = max(s, l - s) / d, (h - s) / d
             l, h = q * q, r * r
             out.append((1, s, l, h))
         else:
-            s = 0.5 * (1.0 - h)
+            s = FOLD * (1.0 - h)
             d = 1.0 - s
-            q, r = (1.0 - l - s) / d, s / d
+            q, r = (1.0 - l - s) / d, max(s, 1.0 - h - s) / d
             l, h = 1.0 - q * q, 1.0 - r * r
             out.append((-1, s, l, h))
     return out
 
 
-def _schedule_coefs(rec, homo, lumo, max_iter):
+def stall_start(l, h, sched, u):
+    """First iterate index whose tracked width ``max(l_k, 1 - h_k)`` is below
+    ``u`` (``len(sched)`` if none is): from there the stagnation rule may
+    compare errors."""
+    w = max(l, 1.0 - h)
+    for k, (_, _, lk, hk) in enumerate(sched):
+        if w < u:
+            return k
+        w = max(lk, 1.0 - hk)
+    return len(sched)
+
+
+def _schedule(rec, homo, lumo, max_iter, u):
     l, h = mapped_interval(rec.eps_min, rec.eps_max, homo, lumo)
-    return [layer_polynomial(sg, s) for sg, s, _, _ in acceleration_schedule(l, h, max_iter)]
+    sched = acceleration_schedule(l, h, max_iter)
+    return ([layer_polynomial(sg, s) for sg, s, _, _ in sched],
+            stall_start(l, h, sched, u) if sched else 0)
 
 
 def sp2_accelerated(h, n_occ, homo, lumo, tol=1e-10, max_iter=100, stop_rule=0,
-                    stall_gate=STALL_GATE, bounds=None, refine=False, return_iterates=False):
+                    stall_gate=STALL_GATE, bounds=None, refine=False, return_iterates=False,
+                    unit_roundoff=2.0 ** -53):
     """DNN-SP2 whose first layers follow the accelerated schedule of the
     estimates ``homo < lumo`` (energies), then the trace-driven rule.
+    ``unit_roundoff``: ``u`` of the stagnation gating (FP64 here).
 
     Returns ``(D, record)``; ``record.coefs`` holds ``(a, b, c)`` of every
     applied layer (``record.branches`` its sign)."""
@@ -131,7 +163,7 @@ def sp2_accelerated(h, n_occ, homo, lumo, tol=1e-10, max_iter=100, stop_rule=0,
         return (d, rec, [d]) if return_iterates else (d, rec)
     if not eps_max > eps_min:
         raise ValueError("degenerate spectrum: no gap to place the step in")
-    sched = _schedule_coefs(rec, homo, lumo, max_iter)
+    sched, stall_from = _schedule(rec, homo, lumo, max_iter, unit_roundoff)
     s = input_layer(h, eps_min, eps_max)
     iterates = [s]
     for k in range(max_iter + 1):
@@ -140,7 +172,7 @@ def sp2_accelerated(h, n_occ, homo, lumo, tol=1e-10, max_iter=100, stop_rule=0,
         rec.t1.append(t1)
         rec.t2.append(t2)
         rec.err.append(abs(t1 - t2))
-        if should_stop(k, rec.err, abs(t1 - n_occ), tol, stop_rule, stall_gate):
+        if should_stop(k, rec.err, abs(t1 - n_occ), tol, stop_rule, stall_gate, stall_from):
             rec.converged = True
             break
         if k == max_iter:
@@ -166,20 +198,20 @@ def sp2_accelerated(h, n_occ, homo, lumo, tol=1e-10, max_iter=100, stop_rule=0,
 
 
 def sp2_accelerated_scalar(w, n_occ, eps_min, eps_max, homo, lumo, tol=1e-10, max_iter=100,
-                           stop_rule=0, stall_gate=STALL_GATE):
+                           stop_rule=0, stall_gate=STALL_GATE, unit_roundoff=2.0 ** -53):
     """The same network on the eigenvalues ``w`` of ``H`` (every layer is a
     polynomial of ``S_0``, which shares the eigenvectors of ``H``).
     Returns ``(p(x), record)``."""
     x = (eps_max - np.asarray(w, dtype=np.float64)) / (eps_max - eps_min)
     rec = SP2Record(eps_min=eps_min, eps_max=eps_max)
-    sched = _schedule_coefs(rec, homo, lumo, max_iter)
+    sched, stall_from = _schedule(rec, homo, lumo, max_iter, unit_roundoff)
     for k in range(max_iter + 1):
         t1 = float(np.sum(x))
         t2 = float(np.sum(x * x))
         rec.t1.append(t1)
         rec.t2.append(t2)
         rec.err.append(abs(t1 - t2))
-        if should_stop(k, rec.err, abs(t1 - n_occ), tol, stop_rule, stall_gate):
+        if should_stop(k, rec.err, abs(t1 - n_occ), tol, stop_rule, stall_gate, stall_from):
             rec.converged = True
             break
         if k == max_iter:

@@ -24,7 +24,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .accelerated import acceleration_schedule, layer_polynomial, mapped_interval
+from .accelerated import acceleration_schedule, layer_polynomial, mapped_interval, stall_start
 from .sp2_oracle import (FP16_SPLIT_SCALE_LOG2, STALL_GATE, choose_branch, gershgorin_bounds,
                          should_stop, split_bf16, split_fp16_scaled)
 
@@ -81,10 +81,13 @@ def sp2_emulated(h, n_occ, mode, tol=1e-5, max_iter=100, stop_rule=1, stall_gate
         stall_gate = automatic_stall_gate(n, mode)
     lo_b, hi_b = gershgorin_bounds(h.astype(np.float64)) if bounds is None else bounds
     s = ((hi_b * np.eye(n) - h.astype(np.float64)) / (hi_b - lo_b)).astype(np.float32)
-    sched = []
+    sched, stall_from = [], 0
     if homo is not None:
         l, hh = mapped_interval(lo_b, hi_b, homo, lumo)
-        sched = [layer_polynomial(sg, sh) for sg, sh, _, _ in acceleration_schedule(l, hh, max_iter)]
+        steps = acceleration_schedule(l, hh, max_iter)
+        sched = [layer_polynomial(sg, sh) for sg, sh, _, _ in steps]
+        if steps:
+            stall_from = stall_start(l, hh, steps, 2.0 ** (-OPERAND_BITS[mode]))
     diag = np.diag_indices(n)
     errs = []
     layers = 0
@@ -93,7 +96,8 @@ def sp2_emulated(h, n_occ, mode, tol=1e-5, max_iter=100, stop_rule=1, stall_gate
         t1 = float(np.trace(sd))
         t2 = float(np.sum(sd * sd))
         errs.append(abs(t1 - t2))
-        if should_stop(k, errs, abs(t1 - n_occ), tol, stop_rule, stall_gate) or k == max_iter:
+        if should_stop(k, errs, abs(t1 - n_occ), tol, stop_rule, stall_gate, stall_from) \
+                or k == max_iter:
             break
         if sched and k == len(sched) and not abs(t1 - n_occ) < 0.5:
             # end-of-schedule check failed: the plain network from the start

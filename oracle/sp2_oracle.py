@@ -117,7 +117,7 @@ def choose_branch(t1, t2, n_occ):
     return 1 if abs(t2 - n_occ) <= abs(2.0 * t1 - t2 - n_occ) else -1
 
 
-def should_stop(k, errs, trace_gap, tol, stop_rule, stall_gate):
+def should_stop(k, errs, trace_gap, tol, stop_rule, stall_gate, stall_from=0):
     """Convergence test on the idempotency estimate ``e_k = |Tr S_k - Tr S_k^2|``
     (Section II.E: idempotency estimated from traces).
 
@@ -129,13 +129,16 @@ def should_stop(k, errs, trace_gap, tol, stop_rule, stall_gate):
     the error, so rounding dominates), once ``e_k < stall_gate``.  With every
     eigenvalue in [0, 1], ``e_k < 3/16`` puts each within 1/4 of 0 or 1, where
     every layer pair contracts in exact arithmetic; together with the trace
-    gap this also fixes which eigenvalues sit near 1."""
+    gap this also fixes which eigenvalues sit near 1.  ``stall_from``: the
+    stagnation comparison uses only ``e_{k-2}`` with ``k - 2 >= stall_from``
+    (an accelerated schedule can raise ``e`` by itself before that, see
+    ``oracle.accelerated``)."""
     if not trace_gap < 0.5:
         return False
     e = errs[k]
     if e < tol:
         return True
-    if stop_rule == 1 and k >= 2 and e < stall_gate and e >= errs[k - 2]:
+    if stop_rule == 1 and k >= 2 and k - 2 >= stall_from and e < stall_gate and e >= errs[k - 2]:
         return True
     return False
 

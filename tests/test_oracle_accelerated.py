@@ -70,7 +70,7 @@ def test_schedule_branches_toward_the_wider_interval():
     l, h = 0.157, 0.212
     for sign, shift, l_after, h_after in sched:
         assert sign == (1 if l >= 1.0 - h else -1)
-        assert shift == pytest.approx(0.5 * (l if sign > 0 else 1.0 - h), rel=1e-15)
+        assert shift == pytest.approx(0.4 * (l if sign > 0 else 1.0 - h), rel=1e-15)
         l, h = l_after, h_after
 
 
@@ -80,8 +80,8 @@ def test_no_gap_gives_no_schedule():
 
 
 def test_fewer_layers_than_plain_sp2():
-    """The scalar probe of the c1 input and a water box: about 40% fewer
-    layers with exact estimates and Gershgorin bounds."""
+    """The c1 input and a water box: about a third fewer layers with exact
+    estimates and Gershgorin bounds."""
     h, q, e = random_orthogonal_hamiltonian(256, 128, seed=0, return_factors=True)
     _, rec = oracle.sp2(h, 128)
     p, rec_a = acc.sp2_accelerated(h, 128, e[:128].max(), e[128:].min())
