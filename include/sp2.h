@@ -71,6 +71,7 @@ typedef enum { SP2_REFINE_NONE = 0, SP2_REFINE_FP32 = 1, SP2_REFINE_SPLIT = 2 } 
 #define SP2_MAX_BOUND_STEPS 64
 #define SP2_FLAG_TIME_LAYERS 1
 #define SP2_FLAG_SPLIT_DERIVATIVES 2
+#define SP2_FLAG_ACCELERATE 4
 
 typedef struct {
   int32_t precision;        /* sp2_precision (default SP2_BF16X3) */
@@ -101,13 +102,37 @@ typedef struct {
                                FP32).  Below 3/16 every eigenvalue of S_n is within 1/4 of
                                0 or 1; n u / 16 stays above the rounding floor of e_n.
                                NaN is rejected */
+  double homo, lumo;        /* with SP2_FLAG_ACCELERATE: estimates of the highest occupied
+                               and the lowest unoccupied eigenvalue of H (energies, finite,
+                               homo < lumo; default 0).  Section II.E: such estimates allow an
+                               accelerated network with fewer layers.  With the bounds mapped
+                               to l = (eps_max - lumo)/(eps_max - eps_min) (top of the
+                               virtual eigenvalues) and h = (eps_max - homo)/(eps_max -
+                               eps_min) (bottom of the occupied ones), clipped to [0, 1], the
+                               first layers follow a schedule fixed by (l, h): while
+                               max(l, 1 - h) >= 1e-14 the wider interval is folded about
+                               0.4 of its width, S <- ((S - sI)/(1 - s))^2 with s = 0.4 l when
+                               l >= 1 - h, else S <- I - ((I - S - sI)/(1 - s))^2 with
+                               s = 0.4 (1 - h), the ends following the same maps; later layers
+                               take the trace-driven sign.  Inside the schedule the stagnation
+                               test of stop_rule 1 waits until the tracked width is below the
+                               unit roundoff of the layer operands (the schedule itself can
+                               raise e_n before that).  Estimates must bracket part of the
+                               true gap (homo >= HOMO, lumo <= LUMO).  At the end of the
+                               schedule every eigenvalue has reached its side, so
+                               |Tr S - n_occ| >= 1/2 there means the estimates were wrong: the
+                               scheduled iterate is dropped and the plain network runs from
+                               the start (sp2_info.fallback = 1; the schedule's layers are
+                               lost time).  sp2_homo_lumo computes estimates from a P */
 } sp2_options;
 
 typedef struct {
   int32_t n_iter;      /* layers applied (refinement not counted) */
   int32_t converged;   /* 1 if the stop test passed */
   int32_t status;      /* sp2_status of the call */
-  int32_t reserved;
+  int32_t fallback;    /* 1: SP2_FLAG_ACCELERATE was set but the trace check at the end of
+                          the schedule failed (the estimates do not bracket the HOMO-LUMO
+                          gap), so the plain network was run instead and produced P */
   double eps_min;      /* lower spectral bound used by the input layer, FP64 */
   double eps_max;      /* upper spectral bound */
   double trace;        /* Tr P of the returned P, FP64 sum of FP32 entries */
@@ -194,6 +219,29 @@ sp2_status sp2_jvp(void* workspace, size_t ws_bytes, const float* H1, int64_t ld
 sp2_status sp2_vjp(void* workspace, size_t ws_bytes, const float* W, int64_t ld, float* G,
                    void* stream);
 
+/* Estimates of the highest occupied and the lowest unoccupied eigenvalue of
+ * H from a density matrix P of it (for the accelerated network of Section
+ * II.E, SP2_FLAG_ACCELERATE; in molecular dynamics P comes from the previous
+ * step).  HOMO = largest eigenvalue of H on the range of P, LUMO = smallest
+ * on the range of I - P, each from `steps` (SP2_MIN_BOUND_STEPS ..
+ * SP2_MAX_BOUND_STEPS) steps of the Lanczos recurrence (FP64 vectors, full
+ * reorthogonalisation, as sp2_spectral_bounds) on v -> Q((H - s I) v),
+ * Q = P or I - P, started from Q u / |Q u| with the SplitMix64 vector u of
+ * `seed`; s = the Gershgorin eps_min (occupied side) or eps_max (virtual
+ * side), so that the complement's zero eigenvalue cannot be the extreme
+ * one.  Each extreme Ritz value is moved outwards by its residual norm
+ * |beta_k s_k| (HOMO up, LUMO down), then the interval between them is
+ * shrunk by margin (0 <= margin < 1/2) of its width on each side.  H and P:
+ * n x n FP32, leading dimension ld, DEVICE; P symmetric (not checked).
+ * Outputs are host doubles; blocks until done.  Reuses the workspace
+ * header and Lanczos area (drops a derivative tape).  Returns
+ * SP2_ERR_NONFINITE for NaN/Inf in H, SP2_ERR_NOT_CONVERGED when no gap
+ * separates the two estimates (P empty or full, or not a density matrix of
+ * H). */
+sp2_status sp2_homo_lumo(const float* H, const float* P, int64_t n, int64_t ld, int32_t steps,
+                         int32_t seed, double margin, double* homo, double* lumo, void* workspace,
+                         size_t ws_bytes, void* stream);
+
 /* Gershgorin enclosure of the spectrum of H (the linear map of the input
  * layer needs spectral bounds; Section II.D): eps_min = min_i(H_ii -
  * sum_{j!=i}|H_ij|), eps_max = max_i(H_ii + sum_{j!=i}|H_ij|), FP64 sums of
@@ -251,9 +299,14 @@ sp2_status sp2_layer(const float* X, int64_t n, int64_t ld, int32_t precision, i
  * NULL) receives n_iter + 1.  After a trivial occupation (n_occ in {0, n}),
  * a bound error, or another call that reuses the workspace (sp2_bounds,
  * sp2_spectral_bounds, sp2_layer), the history holds one meaningless entry.
+ * coef (may be NULL): 3 * min(cap, n_iter) doubles, the coefficients
+ * (a, b, c) of every applied layer S_{k+1} = a S_k^2 + b S_k + c I, in
+ * FP64 as recorded (the layer kernels apply them rounded to FP32): (1, 0, 0)
+ * and (-1, 2, 0) for plain layers, the scheduled ones with
+ * SP2_FLAG_ACCELERATE.
  * Blocks until the copy is done. */
 sp2_status sp2_history(void* workspace, size_t ws_bytes, int32_t cap, double* t1, double* t2,
-                       double* err, int32_t* count, void* stream);
+                       double* err, double* coef, int32_t* count, void* stream);
 
 /* ---- XL-BOMD kernel building block (Section III, Eq. 27-28) ----------------
  * Extended-Lagrangian dynamics propagates one net charge n_I per atom and

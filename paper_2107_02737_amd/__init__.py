@@ -11,5 +11,5 @@ from ._lib import (EXPORTED, PRECISIONS, SP2Error, allocate_workspace, load_libr
                    sp2_workspace_bytes, sp2_mulliken, sp2_xl_scratch_bytes, allocate_xl_scratch,
                    sp2_xl_response, sp2_xl_kernel, SP2_XL_MAX_RANK, nvt_params,
                    sp2_nvt_gamma_tc, sp2_nvt_first_half, sp2_nvt_second_half, sp2_history,
-                   sp2_density_noalloc)
-from .sp2 import SP2Density, density, jvp, vjp  # noqa: F401
+                   sp2_density_noalloc, sp2_homo_lumo)
+from .sp2 import SP2Density, density, homo_lumo, jvp, vjp  # noqa: F401

@@ -42,7 +42,7 @@ EXPORTED = ["sp2_default_options", "sp2_workspace_bytes", "sp2_density", "sp2_de
             "sp2_jvp", "sp2_vjp", "sp2_bounds", "sp2_spectral_bounds", "sp2_split", "sp2_layer",
             "sp2_mulliken", "sp2_xl_scratch_bytes", "sp2_xl_response", "sp2_xl_kernel",
             "sp2_nvt_gamma_tc", "sp2_nvt_first_half", "sp2_nvt_second_half", "sp2_last_error",
-            "sp2_history", "sp2_density_noalloc"]
+            "sp2_history", "sp2_density_noalloc", "sp2_homo_lumo"]
 SP2_XL_MAX_RANK = 32
 
 
@@ -50,12 +50,13 @@ class sp2_options(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("refine", c_int32), ("max_iter", c_int32),
                 ("stop_rule", c_int32), ("checkpoint_every", c_int32), ("flags", c_int32),
                 ("bound_steps", c_int32), ("bound_seed", c_int32),
-                ("tol", c_double), ("stall_gate", c_double)]
+                ("tol", c_double), ("stall_gate", c_double), ("homo", c_double),
+                ("lumo", c_double)]
 
 
 class sp2_info(ctypes.Structure):
     _fields_ = [("n_iter", c_int32), ("converged", c_int32), ("status", c_int32),
-                ("reserved", c_int32), ("eps_min", c_double), ("eps_max", c_double),
+                ("fallback", c_int32), ("eps_min", c_double), ("eps_max", c_double),
                 ("trace", c_double), ("idem_err", c_double), ("layer_ms", c_double),
                 ("refine_ms", c_double)]
 
@@ -112,6 +113,9 @@ def load_library(path=None):
                                         ctypes.POINTER(c_double), ctypes.POINTER(c_double), vp,
                                         c_size_t, vp]
     lib.sp2_spectral_bounds.restype = c_int32
+    lib.sp2_homo_lumo.argtypes = [vp, vp, c_int64, c_int64, c_int32, c_int32, c_double,
+                                  ctypes.POINTER(c_double), ctypes.POINTER(c_double), vp, c_size_t, vp]
+    lib.sp2_homo_lumo.restype = c_int32
     lib.sp2_split.argtypes = [vp, c_int64, c_int64, c_int32, vp, vp, vp]
     lib.sp2_split.restype = c_int32
     lib.sp2_layer.argtypes = [vp, c_int64, c_int64, c_int32, c_int32, vp, vp, c_size_t, vp]
@@ -132,7 +136,7 @@ def load_library(path=None):
     lib.sp2_nvt_first_half.restype = c_int32
     lib.sp2_nvt_second_half.argtypes = [vp, vp, vp, c_int64, ctypes.POINTER(sp2_nvt_params), vp]
     lib.sp2_nvt_second_half.restype = c_int32
-    lib.sp2_history.argtypes = [vp, c_size_t, c_int32, vp, vp, vp, ctypes.POINTER(c_int32), vp]
+    lib.sp2_history.argtypes = [vp, c_size_t, c_int32, vp, vp, vp, vp, ctypes.POINTER(c_int32), vp]
     lib.sp2_history.restype = c_int32
     lib.sp2_last_error.argtypes = []
     lib.sp2_last_error.restype = ctypes.c_char_p
@@ -163,12 +167,15 @@ def _stream(device):
 
 SP2_FLAG_TIME_LAYERS = 1
 SP2_FLAG_SPLIT_DERIVATIVES = 2
+SP2_FLAG_ACCELERATE = 4
 
 
 def make_options(precision="bf16x3", refine="fp32", max_iter=100, stop_rule=1,
                  checkpoint_every=0, tol=1e-5, stall_gate=-1.0, time_layers=False,
-                 bound_steps=0, bound_seed=0, split_derivatives=False):
-    """sp2_options; ``stall_gate`` < 0 selects the library's automatic gate."""
+                 bound_steps=0, bound_seed=0, split_derivatives=False, homo=None, lumo=None):
+    """sp2_options; ``stall_gate`` < 0 selects the library's automatic gate.
+    ``homo`` and ``lumo`` (both or neither) select the accelerated network
+    (SP2_FLAG_ACCELERATE) with these eigenvalue estimates."""
     lib = load_library()
     o = sp2_options()
     lib.sp2_default_options(ctypes.byref(o))
@@ -183,6 +190,12 @@ def make_options(precision="bf16x3", refine="fp32", max_iter=100, stop_rule=1,
         (SP2_FLAG_SPLIT_DERIVATIVES if split_derivatives else 0)
     o.bound_steps = int(bound_steps)
     o.bound_seed = int(bound_seed)
+    if (homo is None) != (lumo is None):
+        raise ValueError("give both homo and lumo, or neither")
+    if homo is not None:
+        o.flags |= SP2_FLAG_ACCELERATE
+        o.homo = float(homo)
+        o.lumo = float(lumo)
     return o
 
 
@@ -309,16 +322,34 @@ def sp2_layer(X, precision, sign, Y, workspace):
 
 
 def sp2_history(workspace, cap=SP2_MAX_ITER + 1):
-    """Per-layer traces of the last solve on ``workspace``: a dict of lists
+    """Per-layer record of the last solve on ``workspace``: a dict of lists
     ``t1`` (Tr S_k), ``t2`` (||S_k||_F^2) and ``err`` (|t1 - t2|) for
-    k = 0 .. n_iter."""
+    k = 0 .. n_iter, and ``coef``, the ``(a, b, c)`` of every applied layer
+    ``S_{k+1} = a S_k^2 + b S_k + c I``."""
     lib = load_library()
     t1, t2, err = (c_double * cap)(), (c_double * cap)(), (c_double * cap)()
+    coef = (c_double * (3 * cap))()
     cnt = c_int32(0)
     _check(lib.sp2_history(c_void_p(workspace.data_ptr()), workspace.numel(), int(cap), t1, t2,
-                           err, ctypes.byref(cnt), _stream(workspace.device)))
+                           err, coef, ctypes.byref(cnt), _stream(workspace.device)))
     m = min(cnt.value, cap)
-    return {"t1": list(t1[:m]), "t2": list(t2[:m]), "err": list(err[:m])}
+    nl = min(cnt.value - 1, cap)
+    return {"t1": list(t1[:m]), "t2": list(t2[:m]), "err": list(err[:m]),
+            "coef": [tuple(coef[3 * k:3 * k + 3]) for k in range(max(nl, 0))]}
+
+
+def sp2_homo_lumo(H, P, workspace, steps=24, seed=0, margin=0.05):
+    """Estimates ``(homo, lumo)`` of the highest occupied and lowest
+    unoccupied eigenvalue of ``H`` from its density matrix ``P``."""
+    lib = load_library()
+    if P.stride(0) != H.stride(0) or P.shape != H.shape:
+        raise ValueError("H and P must have the same shape and leading dimension")
+    homo, lumo = c_double(), c_double()
+    _check(lib.sp2_homo_lumo(_dev_ptr(H, name="H"), _dev_ptr(P, name="P"), H.shape[0], H.stride(0),
+                             int(steps), int(seed), float(margin), ctypes.byref(homo),
+                             ctypes.byref(lumo), c_void_p(workspace.data_ptr()), workspace.numel(),
+                             _stream(H.device)))
+    return homo.value, lumo.value
 
 
 def sp2_last_error():

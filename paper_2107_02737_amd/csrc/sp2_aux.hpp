@@ -107,6 +107,9 @@ __global__ __launch_bounds__(256) void k_bounds_final(const double* __restrict__
     ctrl->nonfinite = nonfinite;
     ctrl->degenerate = degenerate;
     ctrl->n_iter = 0;
+    ctrl->acc_len = 0;
+    ctrl->acc_failed = 0;
+    ctrl->stall_from = 0;
     ctrl->converged = (trivial && !nonfinite) ? 1 : 0;
     ctrl->stopped = (nonfinite || degenerate || trivial) ? 1 : 0;
     ctrl->final_t1 = 0.0;
@@ -368,7 +371,8 @@ __global__ __launch_bounds__(256) void k_finish_loop(Ctrl* ctrl, Hist* hist,
   if (threadIdx.x == 0) {
     const int n = max_iter;
     const double e = fabs(t1 - t2);
-    const bool stop = stop_test(t1, e, n, hist->err, n_occ, tol, stop_rule, stall_gate);
+    const bool stop = stop_test(t1, e, n, hist->err, n_occ, tol, stop_rule, stall_gate,
+                                ctrl->stall_from);
     hist->t1[n] = t1;
     hist->t2[n] = t2;
     hist->err[n] = e;
@@ -376,6 +380,75 @@ __global__ __launch_bounds__(256) void k_finish_loop(Ctrl* ctrl, Hist* hist,
     ctrl->converged = stop ? 1 : 0;
     ctrl->stopped = 1;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Accelerated schedule (Section II.E: with estimates of the HOMO and the
+// LUMO the network needs fewer layers).  The mapped interval ends
+// l = (eps_max - lumo)/(eps_max - eps_min) (top of the virtual eigenvalues)
+// and h = (eps_max - homo)/(eps_max - eps_min) (bottom of the occupied ones)
+// fix the whole schedule: while max(l, 1 - h) >= kAccEnd, the wider of the
+// two intervals is folded about kAccFold of its width, s = kAccFold l with
+// the layer ((x - s)/(1 - s))^2 when l >= 1 - h, else s = kAccFold (1 - h)
+// with 1 - ((1 - x - s)/(1 - s))^2, and the ends follow the same maps (the
+// folded end to the larger of the images of its two ends).  A fold of 0.4
+// rather than 1/2 (the smallest folded image) keeps the gap between the two
+// intervals growing fast enough that early rounding is not amplified beyond
+// the plain network's.  The stagnation test may compare errors from the
+// first iterate whose tracked width is below u, the unit roundoff of the
+// layer operands (before that the schedule itself can raise e), or from
+// the end of the schedule.  One thread, FP64, every operation rounded as
+// written (no contraction), so the coefficients are those of the same
+// recursion evaluated anywhere else in IEEE double.  Layers past the
+// schedule use the trace-driven sign.
+// ---------------------------------------------------------------------------
+constexpr double kAccEnd = 1e-14;
+constexpr double kAccFold = 0.4;
+
+__global__ void k_acc_schedule(Ctrl* ctrl, Hist* hist, double homo, double lumo, int max_len,
+                               double u) {
+#pragma clang fp contract(off)
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  ctrl->acc_len = 0;
+  ctrl->stall_from = 0;
+  if (ctrl->stopped) return;   // NaN/Inf, no spread, or a trivial occupation
+  const double r = ctrl->eps_max - ctrl->eps_min;
+  double l = fmin(fmax((ctrl->eps_max - lumo) / r, 0.0), 1.0);
+  double h = fmin(fmax((ctrl->eps_max - homo) / r, 0.0), 1.0);
+  int n = 0, quiet = -1;
+  if (l < h) {
+    while (n < max_len && fmax(l, 1.0 - h) >= kAccEnd) {
+      if (quiet < 0 && fmax(l, 1.0 - h) < u) quiet = n;
+      double a, b, c;
+      int sign;
+      if (l >= 1.0 - h) {
+        const double s = kAccFold * l, d = 1.0 - s;
+        const double q = fmax(s, l - s) / d, t = (h - s) / d;
+        l = q * q;
+        h = t * t;
+        a = 1.0 / (d * d);
+        b = -2.0 * s / (d * d);
+        c = s * s / (d * d);
+        sign = 1;
+      } else {
+        const double s = kAccFold * (1.0 - h), d = 1.0 - s;
+        const double q = (1.0 - l - s) / d, t = fmax(s, 1.0 - h - s) / d;
+        l = 1.0 - q * q;
+        h = 1.0 - t * t;
+        a = -1.0 / (d * d);
+        b = 2.0 / d;
+        c = 0.0;
+        sign = -1;
+      }
+      hist->coef[n][0] = a;
+      hist->coef[n][1] = b;
+      hist->coef[n][2] = c;
+      hist->branch[n] = sign;
+      ++n;
+    }
+  }
+  ctrl->acc_len = n;
+  ctrl->stall_from = n == 0 ? 0 : (quiet >= 0 ? quiet : n);
 }
 
 // One work-group: sum (Tr, ||.||_F^2) partials of the returned P into ctrl.

@@ -11,6 +11,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <atomic>
 #include <string>
 #include <vector>
@@ -266,7 +267,9 @@ bool options_ok(const sp2_options& o) {
          o.refine <= SP2_REFINE_SPLIT && o.max_iter >= 1 && o.max_iter <= SP2_MAX_ITER &&
          (o.stop_rule == 0 || o.stop_rule == 1) && o.checkpoint_every >= 0 &&
          o.checkpoint_every <= SP2_MAX_ITER && o.tol >= 0.0 && o.stall_gate == o.stall_gate &&
-         (o.flags & ~(SP2_FLAG_TIME_LAYERS | SP2_FLAG_SPLIT_DERIVATIVES)) == 0 &&
+         (o.flags & ~(SP2_FLAG_TIME_LAYERS | SP2_FLAG_SPLIT_DERIVATIVES | SP2_FLAG_ACCELERATE)) == 0 &&
+         (!(o.flags & SP2_FLAG_ACCELERATE) ||
+          (std::isfinite(o.homo) && std::isfinite(o.lumo) && o.homo < o.lumo)) &&
          (o.bound_steps == 0 ||
           (o.bound_steps >= SP2_MIN_BOUND_STEPS && o.bound_steps <= SP2_MAX_BOUND_STEPS));
 }
@@ -276,13 +279,18 @@ bool options_ok(const sp2_options& o) {
 // Below 3/16 every eigenvalue of S_n lies within 1/4 of 0 or 1; the second
 // term keeps the gate above the rounding floor of the error estimate, which
 // grows with n u.
+// Unit roundoff of the layer operands: 8 significant bits for single
+// BF16, 16 for the BF16 pair, 22 for the scaled FP16 pair, 24 for FP32.
+double unit_roundoff_of(int precision) {
+  return precision == SP2_BF16X1   ? 0x1p-8
+         : precision == SP2_BF16X3 ? 0x1p-16
+         : precision == SP2_FP16X3 ? 0x1p-22
+                                   : 0x1p-24;
+}
+
 double stall_gate_of(const sp2_options& o, int precision, int64_t n) {
   if (o.stall_gate >= 0.0) return o.stall_gate;
-  const double u = precision == SP2_BF16X1   ? 0x1p-8
-                   : precision == SP2_BF16X3 ? 0x1p-16
-                   : precision == SP2_FP16X3 ? 0x1p-22
-                                             : 0x1p-24;
-  return std::max(3.0 / 16.0, static_cast<double>(n) * u / 16.0);
+  return std::max(3.0 / 16.0, static_cast<double>(n) * unit_roundoff_of(precision) / 16.0);
 }
 
 int split_kind_of(int precision) {
@@ -312,6 +320,7 @@ struct HostMirror {
   Meta meta;
   XlState xl;
   int xl_stop;
+  double ritz[4];
 };
 thread_local HostMirror* g_host = nullptr;
 
@@ -502,7 +511,7 @@ float* s_f32(const WS& w, int precision, int n) {
 }
 
 // One forward layer S_n -> S_{n+1}.  mode 1: device decision; mode 2: replay
-// the recorded branch.  src/dst FP32 buffers may alias (split modes only).
+// the recorded layer.  src/dst FP32 buffers may alias (split modes only).
 sp2_status launch_layer(const WS& w, int precision, int n, int mode, const float* src, float* dst,
                         int pair_in, int pair_out, double* parts_out, hipStream_t st,
                         const sp2_options* o, int64_t n_occ, bool full_out = true) {
@@ -519,6 +528,7 @@ sp2_status launch_layer(const WS& w, int precision, int n, int mode, const float
   e.c = src;
   e.out = dst;
   e.parts_out = parts_out;
+  e.n_diag = static_cast<int>(w.L.n);   // the c I term of a shifted layer: real rows only
   if (precision == SP2_FP32) {
     const float* A[1] = {src};
     return launch_f32(w, 1, A, A, e, d, st);
@@ -814,6 +824,11 @@ sp2_status density_impl(const float* H, int64_t n, int64_t ld, int64_t n_occ, co
   LAUNCH_TRY();
   if (!trivial && o.bound_steps > 0)
     if ((s = refine_bounds(w, H, n, ld, o.bound_steps, o.bound_seed, st))) return s;
+  if (!trivial && (o.flags & SP2_FLAG_ACCELERATE)) {
+    k_acc_schedule<<<1, 1, 0, st>>>(w.ctrl, w.hist, o.homo, o.lumo, o.max_iter,
+                                    unit_roundoff_of(prec));
+    LAUNCH_TRY();
+  }
 
   int n_iter = 0;
   bool n_iter_even_for_refine = false;
@@ -908,6 +923,16 @@ sp2_status density_impl(const float* H, int64_t n, int64_t ld, int64_t n_occ, co
   // The freshest control block: the loop has drained, read it again.
   if ((s = read_back(w, hm, false, st))) return s;
   if (hm->ctrl[0].nonfinite) return fail(SP2_ERR_NONFINITE, "H holds NaN or Inf");
+  if (hm->ctrl[0].acc_failed) {
+    // The estimates did not bracket the gap (trace check at the end of the
+    // schedule): run the plain network from the start.
+    sp2_options plain = o;
+    plain.flags &= ~SP2_FLAG_ACCELERATE;
+    const sp2_status r = density_impl(H, n, ld, n_occ, plain, L, P, info, branches, branches_cap,
+                                      workspace, st, hm, pinned);
+    if (info) info->fallback = 1;
+    return r;
+  }
   if (!hm->ctrl[0].stopped) {
     k_finish_loop<<<1, 256, 0, st>>>(w.ctrl, w.hist, w.parts[o.max_iter & 1],
                                      nparts_of_layer(w, prec, o.max_iter), o.max_iter,
@@ -963,7 +988,7 @@ sp2_status density_impl(const float* H, int64_t n, int64_t ld, int64_t n_occ, co
     info->eps_max = c.eps_max;
     info->trace = t1;
     info->idem_err = fabs(t1 - t2);
-    info->reserved = 0;
+    info->fallback = 0;
     info->layer_ms = timer.on ? timer.sum(0, nit) : 0.0;
     info->refine_ms = (timer.on && refined) ? timer.sum(refine_ev, refine_ev + 1) : 0.0;
   }
@@ -1058,6 +1083,87 @@ sp2_status sp2_spectral_bounds(const float* H, int64_t n, int64_t ld, int32_t st
   return SP2_OK;
 }
 
+sp2_status sp2_homo_lumo(const float* H, const float* P, int64_t n, int64_t ld, int32_t steps,
+                         int32_t seed, double margin, double* homo, double* lumo, void* workspace,
+                         size_t ws_bytes, void* stream) {
+  g_err.clear();
+  if (!H || !P || !homo || !lumo) return fail(SP2_ERR_INVALID_ARG, "NULL argument");
+  if (n <= 0 || ld < n) return fail(SP2_ERR_INVALID_ARG, "need n > 0 and ld >= n");
+  if (steps < SP2_MIN_BOUND_STEPS || steps > SP2_MAX_BOUND_STEPS)
+    return fail(SP2_ERR_INVALID_ARG, "steps must lie in [%d, %d]", SP2_MIN_BOUND_STEPS,
+                SP2_MAX_BOUND_STEPS);
+  if (!(margin >= 0.0 && margin < 0.5)) return fail(SP2_ERR_INVALID_ARG, "margin must lie in [0, 1/2)");
+  sp2_options o;
+  sp2_default_options(&o);
+  Layout L;
+  if (!make_layout(n, o, L)) return fail(SP2_ERR_INVALID_ARG, "matrix order out of range");
+  if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 || ws_bytes < L.off_slot0)
+    return fail(SP2_ERR_WORKSPACE, "workspace missing, misaligned or too small");
+  HostMirror* hm;
+  if (sp2_status s = host_mirror(&hm)) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  WS w;
+  bind(w, workspace, L);
+  k_drop_tape<<<1, 1, 0, st>>>(w.meta);
+  LAUNCH_TRY();
+  k_gershgorin_rows<<<L.gersh_blocks, kRowThreads, 0, st>>>(H, n, ld, w.gersh);
+  LAUNCH_TRY();
+  k_bounds_final<<<1, 256, 0, st>>>(w.gersh, L.gersh_blocks, w.ctrl, 1);
+  LAUNCH_TRY();
+  const int nb = L.lz_blocks, nc = L.lz_chunks;
+  const int k = static_cast<int>(std::min<int64_t>(steps, n));
+  double* V = w.lzv;
+  double* wv = w.lzv + int64_t(kLzMaxSteps + 1) * n;   // w
+  double* yv = w.lzv + int64_t(kLzMaxSteps + 2) * n;   // (H - shift) v_j
+  double* p1 = w.lzpart;
+  double* p2 = p1 + size_t(nb) * kLzCoef;
+  double* pn = p2 + size_t(nc) * kLzCoef;
+  double* pc = pn + nc;
+  for (int side = 0; side < 2; ++side) {
+    const int qmode = side == 0 ? 1 : 2;   // Q = P, or I - P
+    // Gershgorin shifts read on the device: the kernels take them from ctrl
+    k_lz_start<<<1, kLzThreads, 0, st>>>(V, n, static_cast<uint64_t>(static_cast<uint32_t>(seed)), w.lz);
+    LAUNCH_TRY();
+    k_hl_matvec<<<nb, kLzMvThreads, 0, st>>>(P, n, ld, V, wv, qmode, 0.0, V, 0, nullptr, w.lz);
+    LAUNCH_TRY();
+    k_hl_norm_parts<<<nc, kLzChunk, 0, st>>>(wv, n, pn, w.lz);
+    LAUNCH_TRY();
+    k_hl_next<<<nc, kLzChunk, 0, st>>>(V, wv, n, 0, pn, nc, w.lz);
+    LAUNCH_TRY();
+    for (int j = 0; j < k; ++j) {
+      k_hl_shifted_matvec<<<nb, kLzMvThreads, 0, st>>>(H, n, ld, V + int64_t(j) * n, yv, side, w.ctrl,
+                                                       w.lz);
+      LAUNCH_TRY();
+      k_hl_matvec<<<nb, kLzMvThreads, 0, st>>>(P, n, ld, yv, wv, qmode, 0.0, V, j, p1, w.lz);
+      LAUNCH_TRY();
+      k_lz_coef<<<j + 1, kLzChunk, 0, st>>>(p1, nb, pc, w.lz);
+      LAUNCH_TRY();
+      k_lz_apply<<<nc, kLzChunk, 0, st>>>(V, wv, n, j, pc, nullptr, 0, p2, w.lz, 0);
+      LAUNCH_TRY();
+      k_lz_apply<<<nc, kLzChunk, 0, st>>>(V, wv, n, j, nullptr, p2, nc, pn, w.lz, 1);
+      LAUNCH_TRY();
+      k_hl_next<<<nc, kLzChunk, 0, st>>>(V, wv, n, j + 1, pn, nc, w.lz);
+      LAUNCH_TRY();
+    }
+    k_hl_ritz<<<1, kWave, 0, st>>>(w.lz, side);
+    LAUNCH_TRY();
+  }
+  HIP_TRY(hipMemcpyAsync(hm->ritz, w.lz->ritz, sizeof(hm->ritz), hipMemcpyDeviceToHost, st));
+  if (sp2_status s = read_back(w, hm, false, st)) return s;
+  const Ctrl& c = hm->ctrl[0];
+  if (c.nonfinite) return fail(SP2_ERR_NONFINITE, "H holds NaN or Inf");
+  if (c.degenerate) return fail(SP2_ERR_NOT_CONVERGED, "degenerate spectrum (eps_max == eps_min): no gap");
+  const double h_est = hm->ritz[0] + c.eps_min + hm->ritz[1];
+  const double l_est = hm->ritz[2] + c.eps_max - hm->ritz[3];
+  const double gap = l_est - h_est;
+  if (!(gap > 0.0))
+    return fail(SP2_ERR_NOT_CONVERGED, "no gap between the estimates (HOMO %.6g, LUMO %.6g)", h_est,
+                l_est);
+  *homo = h_est + margin * gap;
+  *lumo = l_est - margin * gap;
+  return SP2_OK;
+}
+
 sp2_status sp2_split(const float* X, int64_t n, int64_t ld, int32_t precision, uint16_t* hi,
                      uint16_t* lo, void* stream) {
   g_err.clear();
@@ -1118,9 +1224,10 @@ sp2_status sp2_layer(const float* X, int64_t n, int64_t ld, int32_t precision, i
 }
 
 sp2_status sp2_history(void* workspace, size_t ws_bytes, int32_t cap, double* t1, double* t2,
-                       double* err, int32_t* count, void* stream) {
+                       double* err, double* coef, int32_t* count, void* stream) {
   g_err.clear();
-  if (cap < 0 || (cap > 0 && !t1 && !t2 && !err)) return fail(SP2_ERR_INVALID_ARG, "bad cap or outputs");
+  if (cap < 0 || (cap > 0 && !t1 && !t2 && !err && !coef))
+    return fail(SP2_ERR_INVALID_ARG, "bad cap or outputs");
   sp2_options d;
   sp2_default_options(&d);
   Layout L0;
@@ -1139,6 +1246,10 @@ sp2_status sp2_history(void* workspace, size_t ws_bytes, int32_t cap, double* t1
     if (t2) t2[k] = hm->hist.t2[k];
     if (err) err[k] = hm->hist.err[k];
   }
+  if (coef)
+    for (int32_t k = 0; k < std::min(nk - 1, cap); ++k)
+      for (int q = 0; q < 3; ++q)
+        coef[3 * k + q] = hm->hist.coef[k][q];
   if (count) *count = nk;
   return SP2_OK;
 }
@@ -1201,7 +1312,7 @@ uint16_t* dhi(const WS& w, int i) { return reinterpret_cast<uint16_t*>(w.work(2 
 uint16_t* dlo(const WS& w, int i) { return dhi(w, i) + w.L.np * w.L.np; }
 
 // Split form of sym_pair: out = alpha (X Y + Y X) + beta C from the planes
-// of X and Y (branch coefficients of layer `layer` in mode 2), with the
+// of X and Y (in mode 3 the recorded a, b of layer `layer`), with the
 // planes of out written to pair `op` of the derivative planes.
 sp2_status sym_pair_split(const WS& w, const uint16_t* xh, const uint16_t* xl, int yp,
                           const float* C, float* out, int op, int mode, int layer,
@@ -1337,9 +1448,9 @@ sp2_status jvp_run(const WS& w, const HostMirror* hm, const sp2_options& o, cons
     const float* S = s_f32(w, prec, k);
     if (sd)
       s = sym_pair_split(w, w.hi(k & 1), w.lo(k & 1), k & 1, w.work(k & 1), w.work((k + 1) & 1),
-                         (k + 1) & 1, 2, k, st);
+                         (k + 1) & 1, 3, k, st);
     else
-      s = sym_pair(w, S, w.work(k & 1), w.work(k & 1), w.work((k + 1) & 1), 1.0f, 0.0f, 2, k, st);
+      s = sym_pair(w, S, w.work(k & 1), w.work(k & 1), w.work((k + 1) & 1), 1.0f, 0.0f, 3, k, st);
     if (s) return s;
     if (k + 1 < nl || o.refine != SP2_REFINE_NONE)
       if ((s = launch_layer(w, prec, k, 2, S, s_f32(w, prec, k + 1), k & 1, (k + 1) & 1, nullptr, st,
@@ -1440,10 +1551,10 @@ sp2_status sp2_vjp(void* workspace, size_t ws_bytes, const float* W, int64_t ld,
         k_split_tiled<<<L.init_blocks, kEwThreads, 0, st>>>(w.seg(nn - c), L.np, L.np, L.np, w.hi(0),
                                                             w.lo(0), split_code_of(SP2_BF16X3));
         LAUNCH_TRY();
-        s = sym_pair_split(w, w.hi(0), w.lo(0), cur, w.work(cur), w.work(1 - cur), 1 - cur, 2, nn,
+        s = sym_pair_split(w, w.hi(0), w.lo(0), cur, w.work(cur), w.work(1 - cur), 1 - cur, 3, nn,
                            st);
       } else {
-        s = sym_pair(w, w.seg(nn - c), w.work(cur), w.work(cur), w.work(1 - cur), 1.0f, 0.0f, 2, nn,
+        s = sym_pair(w, w.seg(nn - c), w.work(cur), w.work(cur), w.work(1 - cur), 1.0f, 0.0f, 3, nn,
                      st);
       }
       if (s) return s;

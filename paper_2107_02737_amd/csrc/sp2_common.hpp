@@ -31,17 +31,43 @@ struct Ctrl {
   int32_t stopped;           // stop test passed (or nothing to iterate)
   int32_t n_iter;            // layers applied when stopped
   int32_t converged;
-  int32_t pad[7];
+  int32_t acc_len;           // layers 0 .. acc_len-1 follow the accelerated schedule
+  int32_t acc_failed;        // the trace check at the end of the schedule failed
+  int32_t stall_from;        // the stagnation test compares e_n with e_{n-2} only for n-2 >= this
+  int32_t pad[4];
 };
 
-// Per-layer history: traces of every examined approximation S_k and the
-// sign of every applied layer (+1: S^2, -1: 2S - S^2).
+// Per-layer history: traces of every examined approximation S_k, the sign
+// of every applied layer (+1: the S^2 family, -1: the 2S - S^2 family) and
+// its coefficients (a, b, c): S_{k+1} = a S_k^2 + b S_k + c I.
 struct Hist {
   double t1[kMaxIter + 1];
   double t2[kMaxIter + 1];
   double err[kMaxIter + 1];
+  double coef[kMaxIter][3];
   int32_t branch[kMaxIter];
 };
+
+// Coefficients of one layer S_{n+1} = a S_n^2 + b S_n + c I: the DNN layer
+// of Eq. 19 with W_n = a I and B_n = b S_n + c I.  Plain SP2 layers are
+// (1, 0, 0) and (-1, 2, 0); the accelerated ones shift and scale them.
+// sign 0: the network has stopped.
+struct LayerCoef {
+  int sign;
+  float a, b, c;
+};
+
+__device__ __forceinline__ LayerCoef plain_coef(int sign) {
+  return sign > 0 ? LayerCoef{1, 1.0f, 0.0f, 0.0f} : LayerCoef{-1, -1.0f, 2.0f, 0.0f};
+}
+
+// Recorded coefficients of layer n; with_c = false drops c (the derivative
+// of the layer map is dS -> a (S dS + dS S) + b dS).
+__device__ __forceinline__ LayerCoef hist_coef(const Hist* h, int n, bool with_c) {
+  const double a = h->coef[n][0];
+  return LayerCoef{a > 0.0 ? 1 : -1, static_cast<float>(a), static_cast<float>(h->coef[n][1]),
+                   with_c ? static_cast<float>(h->coef[n][2]) : 0.0f};
+}
 
 // Parameters of the trace-driven stop / branch decision (Section II.D-E).
 struct Decide {
@@ -50,7 +76,8 @@ struct Decide {
   const double* parts_in;   // (Tr, ||.||_F^2) partial pairs of S_n
   int nparts_in;
   int layer;                // n: this launch turns S_n into S_{n+1}
-  int mode;                 // 0: fixed coefficients, 1: decide, 2: replay hist->branch
+  int mode;                 // 0: fixed coefficients, 1: decide, 2: replay the recorded
+                            // layer (a, b, c), 3: its derivative map (a, b, 0)
   double n_occ, tol, stall_gate;
   int stop_rule;
   int quiet;                // 1: decide without recording (a second kernel of the same layer)
@@ -105,8 +132,9 @@ __device__ __forceinline__ void block_sum2(double& a, double& b, double* red) {
 
 // ---------------------------------------------------------------------------
 // Branch and stop decision, taken redundantly (and identically) by every
-// work-group of a layer launch before it multiplies.  Returns +1 (S^2), -1
-// (2S - S^2), or 0 when the network has stopped.
+// work-group of a layer launch before it multiplies.  Returns the layer's
+// coefficients, sign 0 when the network has stopped.  Mode 0 returns sign 1
+// and leaves the coefficients to the launch.
 // ---------------------------------------------------------------------------
 
 // Stop test on the traces of S_n (Section II.E: idempotency estimated from
@@ -114,26 +142,29 @@ __device__ __forceinline__ void block_sum2(double& a, double& b, double* red) {
 // yet hold n_occ eigenvalues near 1 (an occupied eigenvalue can pass close to
 // 0 on the way, which makes e small long before convergence).  Then rule 0:
 // e < tol; rule 1 also stops once e < stall_gate and e >= e_{n-2} (two
-// layers brought no reduction, so rounding dominates).
+// layers brought no reduction, so rounding dominates), comparing only from
+// n - 2 >= stall_from (inside an accelerated schedule e can rise by itself
+// until the tracked interval width falls below the unit roundoff).
 __device__ __forceinline__ bool stop_test(double t1, double e, int n, const double* err_hist,
                                           double n_occ, double tol, int stop_rule,
-                                          double stall_gate) {
+                                          double stall_gate, int stall_from) {
   if (!(fabs(t1 - n_occ) < 0.5)) return false;
   if (e < tol) return true;
-  return stop_rule == 1 && n >= 2 && e < stall_gate && e >= err_hist[n - 2];
+  return stop_rule == 1 && n >= 2 && n - 2 >= stall_from && e < stall_gate &&
+         e >= err_hist[n - 2];
 }
 
 template <int NT>
-__device__ __forceinline__ int decide_layer(const Decide& d, double* red) {
-  if (d.mode == 2) return d.hist->branch[d.layer];
-  if (d.mode != 1) return 1;
+__device__ __forceinline__ LayerCoef decide_layer(const Decide& d, double* red) {
+  if (d.mode == 2 || d.mode == 3) return hist_coef(d.hist, d.layer, d.mode == 2);
+  if (d.mode != 1) return LayerCoef{1, 1.0f, 0.0f, 0.0f};
   // One read of the stop flag per work-group, shared through LDS, so that
   // all of its waves take the same exit -- before the partial sums, so that
   // launches queued after the stop leave at once.
   __shared__ int s_stopped;
   if (threadIdx.x == 0) s_stopped = __atomic_load_n(&d.ctrl->stopped, __ATOMIC_RELAXED);
   __syncthreads();
-  if (s_stopped) return 0;
+  if (s_stopped) return LayerCoef{0, 0.0f, 0.0f, 0.0f};
   double t1 = 0.0, t2 = 0.0;
   for (int i = threadIdx.x; i < d.nparts_in; i += NT) {
     t1 += d.parts_in[2 * i];
@@ -142,31 +173,46 @@ __device__ __forceinline__ int decide_layer(const Decide& d, double* red) {
   block_sum2<NT>(t1, t2, red);
   const int n = d.layer;
   const double e = fabs(t1 - t2);
-  const bool stop = stop_test(t1, e, n, d.hist->err, d.n_occ, d.tol, d.stop_rule, d.stall_gate);
-  // Trace-closest sign: Tr(S^2) = t2 versus Tr(2S - S^2) = 2 t1 - t2; ties take S^2.
+  const bool stop = stop_test(t1, e, n, d.hist->err, d.n_occ, d.tol, d.stop_rule, d.stall_gate,
+                              d.ctrl->stall_from);
+  // Layers of the accelerated schedule (written before the first layer)
+  // take their recorded coefficients; the others the trace-closest sign:
+  // Tr(S^2) = t2 versus Tr(2S - S^2) = 2 t1 - t2; ties take S^2.  At the
+  // end of a schedule every eigenvalue sits on its side, so a trace more
+  // than 1/2 from n_occ means the estimates were wrong: the network ends
+  // unconverged (acc_failed) and the host runs the plain network instead.
+  const int acc_len = d.ctrl->acc_len;
+  const bool scheduled = n < acc_len;
+  const bool failed = !stop && acc_len > 0 && n == acc_len && !(fabs(t1 - d.n_occ) < 0.5);
   const int sign = (fabs(t2 - d.n_occ) <= fabs(2.0 * t1 - t2 - d.n_occ)) ? 1 : -1;
   if (!d.quiet && blockIdx.x == 0 && threadIdx.x == 0) {
     d.hist->t1[n] = t1;
     d.hist->t2[n] = t2;
     d.hist->err[n] = e;
-    if (stop) {
+    if (stop || failed) {
       d.ctrl->n_iter = n;
-      d.ctrl->converged = 1;
+      d.ctrl->converged = stop ? 1 : 0;
+      d.ctrl->acc_failed = failed ? 1 : 0;
       __atomic_store_n(&d.ctrl->stopped, 1, __ATOMIC_RELAXED);
-    } else {
+    } else if (!scheduled) {
       d.hist->branch[n] = sign;
+      d.hist->coef[n][0] = sign > 0 ? 1.0 : -1.0;
+      d.hist->coef[n][1] = sign > 0 ? 0.0 : 2.0;
+      d.hist->coef[n][2] = 0.0;
     }
   }
-  return stop ? 0 : sign;
+  if (stop || failed) return LayerCoef{0, 0.0f, 0.0f, 0.0f};
+  return scheduled ? hist_coef(d.hist, n, true) : plain_coef(sign);
 }
 
-// The decision of a layer as recorded by that layer's product launch, for a
-// kernel that follows it on the stream: 0 once the network has stopped.
-__device__ __forceinline__ int recorded_branch(const Decide& d) {
-  if (d.mode == 2) return d.hist->branch[d.layer];
-  if (d.mode != 1) return 1;
-  if (__atomic_load_n(&d.ctrl->stopped, __ATOMIC_RELAXED)) return 0;
-  return d.hist->branch[d.layer];
+// The coefficients of a layer as recorded by that layer's product launch,
+// for a kernel that follows it on the stream: sign 0 once the network has
+// stopped.
+__device__ __forceinline__ LayerCoef recorded_coef(const Decide& d) {
+  if (d.mode == 2 || d.mode == 3) return hist_coef(d.hist, d.layer, d.mode == 2);
+  if (d.mode != 1) return LayerCoef{1, 1.0f, 0.0f, 0.0f};
+  if (__atomic_load_n(&d.ctrl->stopped, __ATOMIC_RELAXED)) return LayerCoef{0, 0.0f, 0.0f, 0.0f};
+  return hist_coef(d.hist, d.layer, true);
 }
 
 // ---------------------------------------------------------------------------

@@ -10,8 +10,9 @@
 //   k_sym_f32    FP32 32x32x2 MFMA over up to four K segments
 //                sum_s A_s B_s^T (plain FP32 layers, refinement, JVP/VJP).
 //
-// Both end in the same fused epilogue: out = alpha*acc + beta*C with the
-// coefficients given by the layer's branch (S^2 or 2S - S^2) or fixed, the
+// Both end in the same fused epilogue: out = alpha*acc + beta*C (+ gamma on
+// the diagonal) with the coefficients of the layer (S^2, 2S - S^2 or their
+// shifted and scaled forms, S_{n+1} = a S_n^2 + b S_n + c I) or fixed, the
 // mirror write, optional re-split of the result into hi/lo planes for the
 // next layer, and FP64 (Tr, ||.||_F^2) partials of the result for the next
 // branch/stop decision.
@@ -37,6 +38,8 @@ struct Epi {
   float oscale;          // scale of the raw accumulator (2^-28 for scaled fp16)
   int np;
   int mirror_out;        // 1: FP32 result in both triangles; 0: upper triangle only
+  int n_diag;            // the layer's c I term reaches diagonal entries < n_diag
+                         // (the real rows: padding stays exactly 0)
 };
 
 // Work decomposition of one product launch.  Work-groups [0, nfull) each
@@ -148,11 +151,13 @@ __device__ __forceinline__ void store_planes8(const Epi& p, int64_t o, const flo
 }
 
 // The four passes over an image of H rows of one 256 x 256 tile (tile rows
-// hr .. hr+H-1), 256 threads.  as = alpha * output scale.  Adds the trace
-// contributions of the upper elements to (t1, t2).
+// hr .. hr+H-1), 256 threads.  as = alpha * output scale; gamma is added to
+// diagonal entries below p.n_diag.  Adds the trace contributions of the
+// upper elements to (t1, t2).
 template <int H>
-__device__ __forceinline__ void epilogue_passes(const Epi& p, float as, float beta, int ti, int tj,
-                                                int hr, float* img, double& t1, double& t2) {
+__device__ __forceinline__ void epilogue_passes(const Epi& p, float as, float beta, float gamma,
+                                                int ti, int tj, int hr, float* img, double& t1,
+                                                double& t2) {
   static_assert(H == 16 || H == 32 || H == 128, "image height");
   constexpr int BM = 256, S = kEpiLd, G = BM / H;
   const int64_t np = p.np;
@@ -160,7 +165,8 @@ __device__ __forceinline__ void epilogue_passes(const Epi& p, float as, float be
   const int t = threadIdx.x, w = t / kWave, lane = t & (kWave - 1);
   const int64_t R0 = int64_t(ti) * BM, C0 = int64_t(tj) * BM;   // tile origin
   const int64_t nv = p.n_valid;
-  // Pass A, upper elements: v = alpha acc + beta C, FP32 result, traces;
+  // Pass A, upper elements: v = alpha acc + beta C (+ gamma on the real
+  // diagonal), FP32 result, traces;
   // v goes back into the image for the other passes (C is symmetric, so
   // the mirrored element takes the same v).  Lane = column (4 of them),
   // wave = every 4th row, 4 rows per step: every access is 64 consecutive
@@ -194,9 +200,10 @@ __device__ __forceinline__ void epilogue_passes(const Epi& p, float as, float be
 #pragma clang loop unroll(full)
       for (int j = 0; j < 4; ++j) {
         const int c = lane + 64 * j;
-        img[rh * S + c] = v[i][j];
         const bool up = !diag || c >= rl;   // below the diagonal: mirrored from above
         const bool on = diag && c == rl;
+        if (on && row < p.n_diag) v[i][j] += gamma;
+        img[rh * S + c] = v[i][j];
         const double d = up ? static_cast<double>(v[i][j]) : 0.0;
         t1 += on ? d : 0.0;
         t2 += (on ? 1.0 : 2.0) * d * d;     // each unordered pair counted once
@@ -271,8 +278,8 @@ __device__ __forceinline__ void epilogue_passes(const Epi& p, float as, float be
 // accumulators into the [128][257] image, then epilogue_passes finish it.
 template <int NT, int MI, int NI>
 __device__ __forceinline__ void sym_epilogue_lds(const f32x16 (&acc)[MI][NI], const Epi& p, float alpha,
-                                                 float beta, int ti, int tj, int wm, int wn, int lane,
-                                                 double* red, int tile, float* img) {
+                                                 float beta, float gamma, int ti, int tj, int wm,
+                                                 int wn, int lane, double* red, int tile, float* img) {
   static_assert(NT == 256, "four waves");
   constexpr int TM = 128, TN = 128, S = kEpiLd;
   const float as = alpha * p.oscale;   // exact: oscale is a power of two
@@ -293,7 +300,7 @@ __device__ __forceinline__ void sym_epilogue_lds(const f32x16 (&acc)[MI][NI], co
         }
     }
     __syncthreads();
-    epilogue_passes<TM>(p, as, beta, ti, tj, half * TM, img, t1, t2);
+    epilogue_passes<TM>(p, as, beta, gamma, ti, tj, half * TM, img, t1, t2);
   }
   if (p.parts_out) {
     block_sum2<NT>(t1, t2, red);
@@ -382,12 +389,13 @@ void k_sym_split(SplitArgs p) {
   __shared__ __attribute__((aligned(1024))) uint16_t lds[128 * kEpiLd * 2];
   __shared__ double red[2 * (NT / kWave)];
 
-  const int sign = decide_layer<NT>(p.dec, red);
-  if (sign == 0) return;
-  float alpha = p.epi.alpha, beta = p.epi.beta;
+  const LayerCoef cf = decide_layer<NT>(p.dec, red);
+  if (cf.sign == 0) return;
+  float alpha = p.epi.alpha, beta = p.epi.beta, gamma = 0.0f;
   if (p.dec.mode != 0) {
-    alpha = sign > 0 ? 1.0f : -1.0f;
-    beta = sign > 0 ? 0.0f : 2.0f;
+    alpha = cf.a;
+    beta = cf.b;
+    gamma = cf.c;
   }
   const int64_t np = p.epi.np;
   const int KT = static_cast<int>(np / BK);
@@ -561,7 +569,7 @@ void k_sym_split(SplitArgs p) {
     store_piece<NT, MI, NI>(acc, p.dc, tail, piece);
     return;
   }
-  sym_epilogue_lds<NT, MI, NI>(acc, p.epi, alpha, beta, ti, tj, wm, wn, lane, red, tile,
+  sym_epilogue_lds<NT, MI, NI>(acc, p.epi, alpha, beta, gamma, ti, tj, wm, wn, lane, red, tile,
                                reinterpret_cast<float*>(lds));
 }
 
@@ -579,12 +587,13 @@ __global__ __launch_bounds__(256) void k_split_tail(SplitArgs p) {
   constexpr int NT = 256, H = 16, S = kEpiLd, NI = 4;
   __shared__ float img[H * S];
   __shared__ double red[2 * (NT / kWave)];
-  const int sign = recorded_branch(p.dec);
-  if (sign == 0) return;
-  float alpha = p.epi.alpha, beta = p.epi.beta;
+  const LayerCoef cf = recorded_coef(p.dec);
+  if (cf.sign == 0) return;
+  float alpha = p.epi.alpha, beta = p.epi.beta, gamma = 0.0f;
   if (p.dec.mode != 0) {
-    alpha = sign > 0 ? 1.0f : -1.0f;
-    beta = sign > 0 ? 0.0f : 2.0f;
+    alpha = cf.a;
+    beta = cf.b;
+    gamma = cf.c;
   }
   const Decomp& dc = p.dc;
   const int tail = blockIdx.x / kTailStrips, s = blockIdx.x % kTailStrips;
@@ -625,7 +634,7 @@ __global__ __launch_bounds__(256) void k_split_tail(SplitArgs p) {
   }
   __syncthreads();
   double t1 = 0.0, t2 = 0.0;
-  epilogue_passes<H>(p.epi, alpha * p.epi.oscale, beta, ti, tj, H * s, img, t1, t2);
+  epilogue_passes<H>(p.epi, alpha * p.epi.oscale, beta, gamma, ti, tj, H * s, img, t1, t2);
   if (p.epi.parts_out) {
     block_sum2<NT>(t1, t2, red);
     if (threadIdx.x == 0) {
@@ -659,12 +668,13 @@ void k_sym_f32(F32Args p) {
   __shared__ __attribute__((aligned(1024))) float lds[128 * kEpiLd];
   __shared__ double red[2 * (NT / kWave)];
 
-  const int sign = decide_layer<NT>(p.dec, red);
-  if (sign == 0) return;
-  float alpha = p.epi.alpha, beta = p.epi.beta;
+  const LayerCoef cf = decide_layer<NT>(p.dec, red);
+  if (cf.sign == 0) return;
+  float alpha = p.epi.alpha, beta = p.epi.beta, gamma = 0.0f;
   if (p.dec.mode != 0) {
-    alpha = sign > 0 ? 1.0f : -1.0f;
-    beta = sign > 0 ? 0.0f : 2.0f;
+    alpha = cf.a;
+    beta = cf.b;
+    gamma = cf.c;
   }
   const int64_t np = p.epi.np;
   const int KT = static_cast<int>(np / BK);
@@ -785,7 +795,7 @@ void k_sym_f32(F32Args p) {
     store_piece<NT, MI, NI>(acc, p.dc, tail, piece);
     return;
   }
-  sym_epilogue_lds<NT, MI, NI>(acc, p.epi, alpha, beta, ti, tj, wm, wn, lane, red, tile, lds);
+  sym_epilogue_lds<NT, MI, NI>(acc, p.epi, alpha, beta, gamma, ti, tj, wm, wn, lane, red, tile, lds);
 }
 
 }  // namespace sp2

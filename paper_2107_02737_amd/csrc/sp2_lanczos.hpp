@@ -30,6 +30,8 @@ struct LzState {
   int32_t steps;    // recorded alpha values
   int32_t broke;    // beta vanished: invariant subspace, later steps skipped
   int32_t pad[2];
+  double ritz[4];   // HOMO/LUMO estimator: (th_max, r_max) of the occupied run,
+                    // (th_min, r_min) of the virtual run
 };
 
 __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t i) {
@@ -456,6 +458,191 @@ __global__ __launch_bounds__(2 * kWave) void k_lz_bounds(LzState* st, Ctrl* ctrl
     ctrl->eps_min = e_lo;
     ctrl->eps_max = e_hi;
     ctrl->inv_range = 1.0 / (e_hi - e_lo);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// HOMO/LUMO estimates from a density matrix P (input of the accelerated
+// network, Section II.E): the same Lanczos recurrence on the projected
+// operator v -> Q ((H - shift I) v), Q = P (occupied side) or I - P (virtual
+// side), started from Q u / |Q u|.  For a projector commuting with H the
+// vectors stay in the range of Q, where the operator is H - shift I on the
+// occupied (virtual) eigenstates; the shift (eps_min, resp. eps_max) keeps
+// the zero eigenvalue of the complement on the inner side.  Each step:
+// y = (H - shift) v_j (k_hl_matvec, mode 0), w = Q y with the first
+// Gram-Schmidt dot partials (mode 1 or 2), the two Gram-Schmidt passes of
+// the bound refinement (k_lz_coef, k_lz_apply), then v_{j+1} = w / |w|
+// (k_hl_next).
+// ---------------------------------------------------------------------------
+
+// out = M x (mode 0: minus shift * x; mode 1: as is; mode 2: x - M x), M an
+// FP32 n x n matrix (leading dimension ld), FP64 vectors, 2 rows per wave.
+// With dot_part (modes 1, 2): partial dots of out with V rows 0 .. j per
+// work-group, dot_part[block * kLzCoef + i].
+__device__ __forceinline__ void k_hl_matvec_body(const float* __restrict__ M, int64_t n, int64_t ld,
+                                                 const double* __restrict__ x,
+                                                 double* __restrict__ out, int mode, double shift,
+                                                 const double* __restrict__ V, int j,
+                                                 double* __restrict__ dot_part, const LzState* st) {
+  __shared__ double dred[kLzMvThreads / kWave][kWave];
+  if (st->broke) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = threadIdx.x / kWave;
+  const int64_t r0 = int64_t(blockIdx.x) * kLzRowsPerBlock + wv * kLzRowsPerWave;
+  double acc[kLzRowsPerWave];
+#pragma unroll
+  for (int rr = 0; rr < kLzRowsPerWave; ++rr) acc[rr] = 0.0;
+  const bool vec = (ld % 4 == 0) && ((reinterpret_cast<uintptr_t>(M) & 15) == 0);
+  int64_t c_done = 0;
+  if (vec) {
+    const int64_t n4 = n & ~int64_t(3);
+#pragma unroll 2
+    for (int64_t c = 4 * lane; c < n4; c += 4 * kWave) {
+      const double x0 = x[c], x1 = x[c + 1], x2 = x[c + 2], x3 = x[c + 3];
+#pragma unroll
+      for (int rr = 0; rr < kLzRowsPerWave; ++rr) {
+        const int64_t row = r0 + rr;
+        if (row < n) {
+          const f32x4 h = *reinterpret_cast<const f32x4*>(M + row * ld + c);
+          double a = acc[rr];
+          a = fma(static_cast<double>(h[0]), x0, a);
+          a = fma(static_cast<double>(h[1]), x1, a);
+          a = fma(static_cast<double>(h[2]), x2, a);
+          a = fma(static_cast<double>(h[3]), x3, a);
+          acc[rr] = a;
+        }
+      }
+    }
+    c_done = n4;
+  }
+  for (int64_t c = c_done + lane; c < n; c += kWave) {
+    const double xc = x[c];
+#pragma unroll
+    for (int rr = 0; rr < kLzRowsPerWave; ++rr) {
+      const int64_t row = r0 + rr;
+      if (row < n) acc[rr] = fma(static_cast<double>(M[row * ld + c]), xc, acc[rr]);
+    }
+  }
+  double ws[kLzRowsPerWave];
+#pragma unroll
+  for (int rr = 0; rr < kLzRowsPerWave; ++rr) {
+    const double sum = wave_sum(acc[rr]);
+    const int64_t row = r0 + rr;
+    double v = 0.0;
+    if (row < n) v = mode == 0 ? sum - shift * x[row] : (mode == 1 ? sum : x[row] - sum);
+    ws[rr] = v;
+    if (lane == 0 && row < n) out[row] = v;
+  }
+  if (!dot_part) return;
+  double d = 0.0;
+  if (lane <= j) {
+#pragma unroll
+    for (int rr = 0; rr < kLzRowsPerWave; ++rr) {
+      const int64_t row = r0 + rr;
+      if (row < n) d = fma(V[int64_t(lane) * n + row], ws[rr], d);
+    }
+  }
+  dred[wv][lane] = d;
+  __syncthreads();
+  if (threadIdx.x <= j) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < kLzMvThreads / kWave; ++q) t += dred[q][threadIdx.x];
+    dot_part[int64_t(blockIdx.x) * kLzCoef + threadIdx.x] = t;
+  }
+}
+
+__global__ __launch_bounds__(kLzMvThreads) void k_hl_matvec(const float* __restrict__ M, int64_t n,
+                                                   int64_t ld, const double* __restrict__ x,
+                                                   double* __restrict__ out, int mode, double shift,
+                                                   const double* __restrict__ V, int j,
+                                                   double* __restrict__ dot_part, const LzState* st) {
+  k_hl_matvec_body(M, n, ld, x, out, mode, shift, V, j, dot_part, st);
+}
+
+// y = (H - shift I) v with shift = eps_min (side 0) or eps_max (side 1)
+// from the control block (the spectral bounds of H).
+__global__ __launch_bounds__(kLzMvThreads) void k_hl_shifted_matvec(const float* __restrict__ H,
+                                                           int64_t n, int64_t ld,
+                                                           const double* __restrict__ v,
+                                                           double* __restrict__ y, int side,
+                                                           const Ctrl* ctrl, const LzState* st) {
+  const double shift = side == 0 ? ctrl->eps_min : ctrl->eps_max;
+  k_hl_matvec_body(H, n, ld, v, y, 0, shift, nullptr, 0, nullptr, st);
+}
+
+// Squared-norm partials of w per chunk of 256 rows.
+__global__ __launch_bounds__(kLzChunk) void k_hl_norm_parts(const double* __restrict__ w, int64_t n,
+                                                          double* __restrict__ part,
+                                                          const LzState* st) {
+  __shared__ double red[kLzChunk / kWave];
+  if (st->broke) return;
+  const int64_t row = int64_t(blockIdx.x) * kLzChunk + threadIdx.x;
+  const double v = row < n ? w[row] : 0.0;
+  const double s = block_sum1<kLzChunk>(v * v, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// v_row = w / |w| with |w|^2 the ordered sum of the chunk partials; records
+// beta[row - 1] for row >= 1.  A vanishing norm ends the recurrence (broke;
+// with row 0, no step is recorded).  Every work-group sums the partials
+// identically.
+__global__ __launch_bounds__(kLzChunk) void k_hl_next(double* __restrict__ V, const double* __restrict__ w,
+                                                    int64_t n, int row, const double* __restrict__ part,
+                                                    int nchunks, LzState* st) {
+  __shared__ double sbuf[256];
+  __shared__ double snorm;
+  if (st->broke) return;
+  ordered_sums(part, nchunks, 1, 1, sbuf, 256, &snorm);
+  const double nrm = sqrt(snorm);
+  if (!(nrm > 1e-300)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (row > 0) st->beta[row - 1] = nrm;
+      st->broke = 1;
+    }
+    return;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && row > 0) st->beta[row - 1] = nrm;
+  const int64_t i = int64_t(blockIdx.x) * kLzChunk + threadIdx.x;
+  if (i < n) V[int64_t(row) * n + i] = w[i] * (1.0 / nrm);
+}
+
+// Extreme Ritz value of the recorded tridiagonal matrix and its residual
+// norm |beta_k s_k|: the largest (side 0, into ritz[0..1]) or the smallest
+// (side 1, into ritz[2..3]).  One wave.  NaN when no step was recorded.
+__global__ __launch_bounds__(kWave) void k_hl_ritz(LzState* st, int side) {
+  __shared__ double x[kLzMaxSteps], dl[kLzMaxSteps], dd[kLzMaxSteps], du[kLzMaxSteps],
+      du2[kLzMaxSteps], sa[kLzMaxSteps], sb[kLzMaxSteps];
+  __shared__ int swp[kLzMaxSteps];
+  const int k = st->steps;
+  if (k <= 0) {
+    if (threadIdx.x == 0) st->ritz[2 * side] = st->ritz[2 * side + 1] = NAN;
+    return;
+  }
+  for (int i = threadIdx.x; i < k; i += kWave) {
+    sa[i] = st->alpha[i];
+    sb[i] = st->beta[i];
+  }
+  __syncthreads();
+  // an early breakdown leaves beta[k - 1] = 0: the Ritz pair is exact
+  double lo = INFINITY, hi = -INFINITY, scale = 0.0;
+  for (int i = 0; i < k; ++i) {
+    const double off = (i > 0 ? fabs(sb[i - 1]) : 0.0) + (i + 1 < k ? fabs(sb[i]) : 0.0);
+    lo = fmin(lo, sa[i] - off);
+    hi = fmax(hi, sa[i] + off);
+    scale = fmax(scale, fabs(sa[i]) + off);
+  }
+  scale = fmax(scale, 1e-300);
+  const double pivmin = 1e-280 * fmax(1.0, scale * scale);
+  const double pad = 1e-14 * (hi - lo) + 1e-14 * scale;
+  const double th = tridiag_eig(sa, sb, k, side == 0 ? k - 1 : 0, lo - pad, hi + pad, pivmin);
+  if (threadIdx.x == 0) {
+    const double tiny = 1e-13 * scale;
+    const double bk = st->broke ? 0.0 : sb[k - 1];
+    st->ritz[2 * side] = th;
+    st->ritz[2 * side + 1] =
+        fabs(bk) * tridiag_last_component(sa, sb, k, side == 0 ? th + tiny : th - tiny, tiny, x, dl,
+                                          dd, du, du2, swp);
   }
 }
 

@@ -29,14 +29,17 @@ def _as_matrix(H, symmetrize):
 def density(H, n_occ, tol=1e-5, precision="bf16x3", refine="fp32", max_iter=100, stop_rule=1,
             stall_gate=-1.0, checkpoint_every=0, symmetrize=False, return_info=False,
             workspace=None, time_layers=False, bound_steps=0, bound_seed=0,
-            split_derivatives=False, allow_unconverged=False):
+            split_derivatives=False, allow_unconverged=False, homo=None, lumo=None):
     """Density matrix of the symmetric ``H`` with ``n_occ`` occupied states.
 
     Returns ``P`` (FP32, same device), or ``(P, info)`` with ``info`` holding
     ``n_iter``, ``converged``, ``eps_min``, ``eps_max``, ``trace``,
     ``idem_err``, ``status`` and the ``branches`` string (1 = S^2).
     ``split_derivatives`` (BF16X3 with a tape) runs the JVP/VJP layer
-    products in BF16X3 instead of FP32.
+    products in BF16X3 instead of FP32.  ``homo``/``lumo``: estimates of the
+    highest occupied and lowest unoccupied eigenvalue (e.g. ``homo_lumo`` of
+    a previous solve) select the accelerated network, which needs fewer
+    layers (Section II.E).
 
     A solve that does not meet the stop test raises ``SP2Error``
     (``SP2_ERR_NOT_CONVERGED``) unless ``allow_unconverged``; then the last
@@ -45,7 +48,8 @@ def density(H, n_occ, tol=1e-5, precision="bf16x3", refine="fp32", max_iter=100,
     H = _as_matrix(H, symmetrize)
     n = H.shape[0]
     opt = _lib.make_options(precision, refine, max_iter, stop_rule, checkpoint_every, tol,
-                            stall_gate, time_layers, bound_steps, bound_seed, split_derivatives)
+                            stall_gate, time_layers, bound_steps, bound_seed, split_derivatives,
+                            homo, lumo)
     if workspace is None:
         workspace = _lib.allocate_workspace(n, opt, H.device)
     P = torch.empty_like(H)
@@ -113,3 +117,16 @@ def vjp(H, n_occ, W, **opts):
     G = torch.empty_like(W)
     _lib.sp2_vjp(info["workspace"], W, G)
     return P, G
+
+
+def homo_lumo(H, P, steps=24, margin=0.05, seed=0, workspace=None):
+    """Estimates ``(homo, lumo)`` of the highest occupied and lowest
+    unoccupied eigenvalue of ``H`` from its density matrix ``P`` (Lanczos on
+    the occupied and virtual projections), for ``density(..., homo=, lumo=)``
+    of a nearby Hamiltonian.  Raises ``SP2Error`` when no gap is found."""
+    H = _as_matrix(H, False)
+    P = P.detach().to(torch.float32).contiguous()
+    if workspace is None:
+        workspace = _lib.allocate_workspace(H.shape[0], None, H.device)
+    return _lib.sp2_homo_lumo(H, P, workspace, steps, seed, margin)
+

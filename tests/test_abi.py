@@ -39,7 +39,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 def test_struct_layouts_match_header():
     from paper_2107_02737_amd import _lib
-    assert ctypes.sizeof(_lib.sp2_options) == 8 * 4 + 2 * 8
+    assert ctypes.sizeof(_lib.sp2_options) == 8 * 4 + 4 * 8
     assert ctypes.sizeof(_lib.sp2_info) == 4 * 4 + 6 * 8
 
 
@@ -49,6 +49,7 @@ def test_default_options(lib):
     assert (o.precision, o.refine, o.max_iter, o.stop_rule, o.checkpoint_every) == (2, 1, 100, 1, 0)
     assert o.tol == 1e-5 and o.stall_gate == -1.0
     assert (o.bound_steps, o.bound_seed, o.flags) == (0, 0, 0)
+    assert (o.homo, o.lumo) == (0.0, 0.0)
 
 
 def test_workspace_bytes(lib):
@@ -130,15 +131,17 @@ def test_history_rejects_bad_arguments(lib):
     buf = (ctypes.c_double * 4)()
     cnt = ctypes.c_int32(0)
     ws = ctypes.c_void_p(0x100000)
-    assert lib.sp2_history(ws, 1 << 30, -1, buf, None, None, ctypes.byref(cnt), None) == \
+    assert lib.sp2_history(ws, 1 << 30, -1, buf, None, None, None, ctypes.byref(cnt), None) == \
         _lib.SP2_ERR_INVALID_ARG
-    assert lib.sp2_history(ws, 1 << 30, 4, None, None, None, ctypes.byref(cnt), None) == \
+    assert lib.sp2_history(ws, 1 << 30, 4, None, None, None, None, ctypes.byref(cnt), None) == \
         _lib.SP2_ERR_INVALID_ARG
-    assert lib.sp2_history(None, 1 << 30, 4, buf, None, None, ctypes.byref(cnt), None) == \
+    assert lib.sp2_history(None, 1 << 30, 4, buf, None, None, None, ctypes.byref(cnt), None) == \
         _lib.SP2_ERR_WORKSPACE
-    assert lib.sp2_history(ctypes.c_void_p(0x100010), 1 << 30, 4, buf, None, None, None, None) == \
-        _lib.SP2_ERR_WORKSPACE
-    assert lib.sp2_history(ws, 64, 4, buf, None, None, None, None) == _lib.SP2_ERR_WORKSPACE
+    assert lib.sp2_history(None, 1 << 30, 4, None, None, None, buf, ctypes.byref(cnt), None) == \
+        _lib.SP2_ERR_WORKSPACE       # coefficients alone are a valid request
+    assert lib.sp2_history(ctypes.c_void_p(0x100010), 1 << 30, 4, buf, None, None, None, None,
+                           None) == _lib.SP2_ERR_WORKSPACE
+    assert lib.sp2_history(ws, 64, 4, buf, None, None, None, None, None) == _lib.SP2_ERR_WORKSPACE
 
 
 def test_xl_entry_points_reject_bad_arguments(lib):
@@ -223,4 +226,37 @@ def test_noalloc_limits_rejected_before_device_work(lib):
     assert call(256, o) == _lib.SP2_ERR_INVALID_ARG
     o = _lib.sp2_default_options()
     assert call(0, o) == _lib.SP2_ERR_INVALID_ARG
+
+
+def test_accelerate_option_checks(lib):
+    """SP2_FLAG_ACCELERATE needs finite estimates with homo < lumo."""
+    from paper_2107_02737_amd import _lib
+    o = _lib.make_options("fp16x3", "split", homo=-0.5, lumo=-0.2)
+    assert o.flags & _lib.SP2_FLAG_ACCELERATE
+    assert _lib.sp2_workspace_bytes(512, o) > 0
+    for h, l in ((-0.2, -0.5), (0.1, 0.1), (float("nan"), 0.0), (-float("inf"), 0.0)):
+        o.homo, o.lumo = h, l
+        assert _lib.sp2_workspace_bytes(512, o) == 0
+    with pytest.raises(ValueError):
+        _lib.make_options(homo=-0.5)
+
+
+def test_homo_lumo_argument_checks(lib):
+    """sp2_homo_lumo rejects bad arguments before any device work."""
+    from paper_2107_02737_amd import _lib
+    a, b = ctypes.c_double(), ctypes.c_double()
+    dummy = ctypes.c_void_p(256)
+    ws = ctypes.c_void_p(1 << 20)
+
+    def call(n, ld, steps, margin):
+        return lib.sp2_homo_lumo(dummy, dummy, n, ld, steps, 0, margin, ctypes.byref(a),
+                                 ctypes.byref(b), ws, 1 << 40, None)
+    assert call(0, 0, 16, 0.0) == _lib.SP2_ERR_INVALID_ARG
+    assert call(64, 32, 16, 0.0) == _lib.SP2_ERR_INVALID_ARG
+    assert call(64, 64, 7, 0.0) == _lib.SP2_ERR_INVALID_ARG
+    assert call(64, 64, 65, 0.0) == _lib.SP2_ERR_INVALID_ARG
+    assert call(64, 64, 16, 0.5) == _lib.SP2_ERR_INVALID_ARG
+    assert call(64, 64, 16, -0.1) == _lib.SP2_ERR_INVALID_ARG
+    assert lib.sp2_homo_lumo(None, dummy, 64, 64, 16, 0, 0.0, ctypes.byref(a), ctypes.byref(b), ws,
+                             1 << 40, None) == _lib.SP2_ERR_INVALID_ARG
 

@@ -98,3 +98,30 @@ def test_lanczos_bounds_enclose_the_spectrum(setup):
         assert float(gold["eps_min"]) <= lo <= w[0]
         assert w[-1] <= hi <= float(gold["eps_max"])
         assert np.isclose(w[0], float(gold["lam_min"]), rtol=1e-12)
+
+
+def test_accelerated_fp32_equivalent_mode(setup):
+    """The accelerated network at full size, with HOMO/LUMO estimates from
+    the previous solve's P (sp2_homo_lumo), as the benchmark's accelerated
+    leg runs it: every entry within the stated 1e-6, far fewer layers."""
+    import torch
+    pk, gold, H, p_ref, w = setup
+    n, n_occ = int(gold["n"]), int(gold["n_occ"])
+    banner(f"accelerated water N={n} fp16x3 refine=split bound_steps=32")
+    P0, info0 = pk.density(H, n_occ, precision="fp16x3", refine="split", bound_steps=32,
+                           return_info=True)
+    homo, lumo = pk.homo_lumo(H, P0)
+    assert w[n_occ - 1] <= homo < lumo <= w[n_occ]
+    P, info = pk.density(H, n_occ, precision="fp16x3", refine="split", bound_steps=32, homo=homo,
+                         lumo=lumo, return_info=True)
+    d = P.double().cpu().numpy() - p_ref
+    fro = float(np.linalg.norm(d)) / math.sqrt(n)
+    mabs = float(np.max(np.abs(d)))
+    print(f"  estimates ({homo:.5f}, {lumo:.5f}) vs ({w[n_occ - 1]:.5f}, {w[n_occ]:.5f}); "
+          f"n_iter={info['n_iter']} (plain {info0['n_iter']}) fro={fro:.3e} max={mabs:.3e}",
+          flush=True)
+    assert info["converged"] == 1
+    assert info["n_iter"] <= info0["n_iter"] - 5
+    assert torch.equal(P, P.T)
+    assert fro <= FP32_EQUIVALENT_TOL
+    assert mabs <= MAX_ABS_FACTOR * FP32_EQUIVALENT_TOL

@@ -133,3 +133,37 @@ def test_trajectory_drift(setup):
         del P, H
     assert max(abs(x) for x in traces) < 0.1
     assert max(idems) < 1e-4
+
+
+def test_trajectory_accelerated_with_earlier_estimates(setup):
+    """The molecular-dynamics use of the accelerated network: HOMO/LUMO
+    estimates from the density matrix of step 0 (sp2_homo_lumo) drive the
+    solve of step 99, whose H differs by 0.01 sin(9.9) H_p.  P against the
+    stored exact samples, far fewer layers than the plain network, and the
+    adjoint of the accelerated network against perturbation theory."""
+    import torch
+    pk, g, H0, Hp, W = setup
+    n, n_occ = int(g["n"]), int(g["n_occ"])
+    banner(f"trajectory N={n}: estimates from t=0, accelerated t=99 bf16x3")
+    H = hamiltonian_at(H0, Hp, 0)
+    P0, info0 = pk.density(H, n_occ, precision="bf16x3", refine="fp32", return_info=True)
+    homo, lumo = pk.homo_lumo(H, P0, workspace=info0["workspace"])
+    del P0, H
+    H = hamiltonian_at(H0, Hp, 99)
+    P, info = pk.density(H, n_occ, precision="bf16x3", refine="fp32", homo=homo, lumo=lumo,
+                         checkpoint_every=4, return_info=True)
+    err, _ = _sampled_err(P, g, "t99_p")
+    idem = _idempotency(P)
+    print(f"  estimates ({homo:.5f}, {lumo:.5f}); n_iter={info['n_iter']} (plain "
+          f"{info0['n_iter']}) fallback={info['fallback']} P err~{err:.2e} idem={idem:.2e}",
+          flush=True)
+    assert info["converged"] == 1 and info["fallback"] == 0
+    assert info["n_iter"] <= info0["n_iter"] - 6
+    assert err <= P_TOL and idem < 1e-4 and abs(info["trace"] - n_occ) < 0.1
+    G = torch.empty_like(P)
+    pk.sp2_vjp(info["workspace"], W, G)
+    torch.cuda.synchronize()
+    _, g_rel = _sampled_err(G, g, "t99_g")
+    print(f"  adjoint rel (sampled)={g_rel:.2e}", flush=True)
+    assert g_rel <= G_TOL
+    assert torch.equal(G, G.T)
