@@ -97,6 +97,62 @@ __device__ __forceinline__ void ordered_sums(const double* __restrict__ part, in
   __syncthreads();
 }
 
+// Partial products of kLzRowsPerWave rows of an FP32 matrix (row pointers
+// mrow) with an FP64 vector x scaled by xs, over this lane's columns c = 4
+// lane + 256 k.  Four 256-column chunks per step with every load issued
+// before the arithmetic, then a chunk at a time; each row's FMA chain runs
+// over its columns in increasing order whatever the chunking.
+__device__ __forceinline__ void rows_dot(const float* const (&mrow)[kLzRowsPerWave],
+                                         const double* __restrict__ x, double xs, int64_t n,
+                                         int64_t ld, bool vec, int lane,
+                                         double (&acc)[kLzRowsPerWave]) {
+  constexpr int U = 4, R = kLzRowsPerWave;
+  int64_t c_done = 0;
+  if (vec) {
+    const int64_t n4 = n & ~int64_t(3);
+    int64_t c = 4 * lane;
+    for (; c + (U - 1) * 4 * kWave < n4; c += U * 4 * kWave) {
+      f32x4 h[U][R];
+      double xv[U][4];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr)
+          h[u][rr] = *reinterpret_cast<const f32x4*>(mrow[rr] + c + u * 4 * kWave);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) xv[u][e] = x[c + u * 4 * kWave + e];
+      // every load above is issued before any of the arithmetic below
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            acc[rr] = fma(static_cast<double>(h[u][rr][e]), xv[u][e] * xs, acc[rr]);
+    }
+    for (; c < n4; c += 4 * kWave) {
+      double xv[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) xv[e] = x[c + e] * xs;
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr) {
+        const f32x4 h = *reinterpret_cast<const f32x4*>(mrow[rr] + c);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[rr] = fma(static_cast<double>(h[e]), xv[e], acc[rr]);
+      }
+    }
+    c_done = n4;
+  }
+  for (int64_t c = c_done + lane; c < n; c += kWave) {
+    const double xc = x[c] * xs;
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr) acc[rr] = fma(static_cast<double>(mrow[rr][c]), xc, acc[rr]);
+  }
+}
+
 // V_0 = u / |u|, u_i = (z_i >> 11) 2^-53 - 1/2; state reset.  V holds the
 // Lanczos vectors as consecutive rows of n doubles.
 __global__ __launch_bounds__(kLzThreads) void k_lz_start(double* __restrict__ V, int64_t n,
@@ -152,42 +208,19 @@ __global__ __launch_bounds__(kLzMvThreads) void k_lz_matvec(const float* __restr
     v = win;
   }
   const int lane = threadIdx.x & (kWave - 1);
-  const int wv = threadIdx.x / kWave;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int64_t r0 = int64_t(blockIdx.x) * kLzRowsPerBlock + wv * kLzRowsPerWave;
   double acc[kLzRowsPerWave];
+  const float* hrow[kLzRowsPerWave];
+  // rows past n read row 0 instead (in bounds; their sums are discarded),
+  // so the column loop carries no per-row branch and its loads overlap
 #pragma unroll
-  for (int rr = 0; rr < kLzRowsPerWave; ++rr) acc[rr] = 0.0;
+  for (int rr = 0; rr < kLzRowsPerWave; ++rr) {
+    acc[rr] = 0.0;
+    hrow[rr] = H + (r0 + rr < n ? r0 + rr : 0) * ld;
+  }
   const bool vec = (ld % 4 == 0) && ((reinterpret_cast<uintptr_t>(H) & 15) == 0);
-  int64_t c_done = 0;
-  if (vec) {
-    const int64_t n4 = n & ~int64_t(3);
-#pragma unroll 2
-    for (int64_t c = 4 * lane; c < n4; c += 4 * kWave) {
-      const double v0 = v[c] * inv, v1 = v[c + 1] * inv, v2 = v[c + 2] * inv, v3 = v[c + 3] * inv;
-#pragma unroll
-      for (int rr = 0; rr < kLzRowsPerWave; ++rr) {
-        const int64_t row = r0 + rr;
-        if (row < n) {
-          const f32x4 h = *reinterpret_cast<const f32x4*>(H + row * ld + c);
-          double a = acc[rr];
-          a = fma(static_cast<double>(h[0]), v0, a);
-          a = fma(static_cast<double>(h[1]), v1, a);
-          a = fma(static_cast<double>(h[2]), v2, a);
-          a = fma(static_cast<double>(h[3]), v3, a);
-          acc[rr] = a;
-        }
-      }
-    }
-    c_done = n4;
-  }
-  for (int64_t c = c_done + lane; c < n; c += kWave) {
-    const double vc = v[c] * inv;
-#pragma unroll
-    for (int rr = 0; rr < kLzRowsPerWave; ++rr) {
-      const int64_t row = r0 + rr;
-      if (row < n) acc[rr] = fma(static_cast<double>(H[row * ld + c]), vc, acc[rr]);
-    }
-  }
+  rows_dot(hrow, v, inv, n, ld, vec, lane, acc);
   double ws[kLzRowsPerWave];
 #pragma unroll
   for (int rr = 0; rr < kLzRowsPerWave; ++rr) {
@@ -487,42 +520,18 @@ __device__ __forceinline__ void k_hl_matvec_body(const float* __restrict__ M, in
   __shared__ double dred[kLzMvThreads / kWave][kWave];
   if (st->broke) return;
   const int lane = threadIdx.x & (kWave - 1);
-  const int wv = threadIdx.x / kWave;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int64_t r0 = int64_t(blockIdx.x) * kLzRowsPerBlock + wv * kLzRowsPerWave;
   double acc[kLzRowsPerWave];
+  const float* mrow[kLzRowsPerWave];
+  // rows past n read row 0 instead (in bounds; their sums are discarded)
 #pragma unroll
-  for (int rr = 0; rr < kLzRowsPerWave; ++rr) acc[rr] = 0.0;
+  for (int rr = 0; rr < kLzRowsPerWave; ++rr) {
+    acc[rr] = 0.0;
+    mrow[rr] = M + (r0 + rr < n ? r0 + rr : 0) * ld;
+  }
   const bool vec = (ld % 4 == 0) && ((reinterpret_cast<uintptr_t>(M) & 15) == 0);
-  int64_t c_done = 0;
-  if (vec) {
-    const int64_t n4 = n & ~int64_t(3);
-#pragma unroll 2
-    for (int64_t c = 4 * lane; c < n4; c += 4 * kWave) {
-      const double x0 = x[c], x1 = x[c + 1], x2 = x[c + 2], x3 = x[c + 3];
-#pragma unroll
-      for (int rr = 0; rr < kLzRowsPerWave; ++rr) {
-        const int64_t row = r0 + rr;
-        if (row < n) {
-          const f32x4 h = *reinterpret_cast<const f32x4*>(M + row * ld + c);
-          double a = acc[rr];
-          a = fma(static_cast<double>(h[0]), x0, a);
-          a = fma(static_cast<double>(h[1]), x1, a);
-          a = fma(static_cast<double>(h[2]), x2, a);
-          a = fma(static_cast<double>(h[3]), x3, a);
-          acc[rr] = a;
-        }
-      }
-    }
-    c_done = n4;
-  }
-  for (int64_t c = c_done + lane; c < n; c += kWave) {
-    const double xc = x[c];
-#pragma unroll
-    for (int rr = 0; rr < kLzRowsPerWave; ++rr) {
-      const int64_t row = r0 + rr;
-      if (row < n) acc[rr] = fma(static_cast<double>(M[row * ld + c]), xc, acc[rr]);
-    }
-  }
+  rows_dot(mrow, x, 1.0, n, ld, vec, lane, acc);
   double ws[kLzRowsPerWave];
 #pragma unroll
   for (int rr = 0; rr < kLzRowsPerWave; ++rr) {
