@@ -78,8 +78,11 @@ typedef struct {
   int32_t refine;           /* sp2_refine (default SP2_REFINE_FP32) */
   int32_t max_iter;         /* layer cap, 1..SP2_MAX_ITER (default 100) */
   int32_t stop_rule;        /* 0: stop when e_n < tol; 1 (default): also stop when
-                               e_n < stall_gate and e_n >= e_{n-2} (rounding floor).
-                               Either rule stops only while |Tr S_n - n_occ| < 1/2 */
+                               e_n < stall_gate and e_n >= min(e_{n-2}, 16 e_{n-2}^2): two
+                               more layers no longer reduced e_n as exact arithmetic would
+                               (there e_n <= (64/9) e_{n-2}^2 below the gate), so rounding
+                               dominates.  Either rule stops only while
+                               |Tr S_n - n_occ| < 1/2 */
   int32_t checkpoint_every; /* 0 (default): no tape.  k > 0: keep S_0 and every k-th
                                iterate in the workspace for sp2_jvp / sp2_vjp */
   int32_t flags;            /* bit SP2_FLAG_TIME_LAYERS: time every layer launch with HIP
@@ -115,9 +118,8 @@ typedef struct {
                                l >= 1 - h, else S <- I - ((I - S - sI)/(1 - s))^2 with
                                s = 0.4 (1 - h), the ends following the same maps; later layers
                                take the trace-driven sign.  Inside the schedule the stagnation
-                               test of stop_rule 1 waits until the tracked width is below the
-                               unit roundoff of the layer operands (the schedule itself can
-                               raise e_n before that).  Estimates must bracket part of the
+                               test of stop_rule 1 waits until the tracked width is below
+                               1e-4 (the schedule itself can raise e_n before that).  Estimates must bracket part of the
                                true gap (homo >= HOMO, lumo <= LUMO).  At the end of the
                                schedule every eigenvalue has reached its side, so
                                |Tr S - n_occ| >= 1/2 there means the estimates were wrong: the

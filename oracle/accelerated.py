@@ -45,13 +45,13 @@ picture of Section II.D:
   iterate is dropped and the plain network runs from the start
   (``record.fallback``).
 * The stop test and refinement are those of ``sp2_oracle.sp2``, with one
-  change for the stagnation rule (``e_k >= e_{k-2}`` taken as the rounding
-  floor): inside the schedule ``e_k`` can rise by itself (two layers of the
-  same sign, and each shift scales the other side's distance from its
-  target by up to ``1/(1 - s)``), so the comparison is allowed only from the
-  iterate whose tracked width ``max(l_k, 1 - h_k)`` is below the unit
-  roundoff ``u`` of the layer arithmetic (then only rounding moves ``e``),
-  or from the end of the schedule.
+  change for rule 1 (comparisons of ``e_k`` with ``e_{k-2}``): inside the
+  schedule ``e_k`` can rise by itself, or fall less than quadratically (two
+  layers of the same sign, and each shift scales the other side's distance
+  from its target by up to ``1/(1 - s)``), so the comparisons are allowed
+  only from the iterate whose tracked width ``max(l_k, 1 - h_k)`` is below
+  ``STALL_WIDTH`` (the remaining shifts are then below ``0.4 STALL_WIDTH``
+  and the layers act as plain ones), or from the end of the schedule.
 
 Pins (tests/test_oracle_accelerated.py): agreement with the diagonalisation
 (``density_matrix_eigh``); the scalar recursion on the eigenvalues
@@ -76,6 +76,8 @@ from .sp2_oracle import (SP2Record, STALL_GATE, apply_layer, choose_branch, gers
 ACC_END = 1e-14
 # Shift of a layer as a fraction of the width of the interval it folds.
 FOLD = 0.4
+# Tracked width below which the stop rule may compare errors two layers apart.
+STALL_WIDTH = 1e-4
 
 
 def mapped_interval(eps_min, eps_max, homo, lumo):
@@ -120,31 +122,29 @@ def acceleration_schedule(l, h, max_len=100, end=ACC_END):
     return out
 
 
-def stall_start(l, h, sched, u):
+def stall_start(l, h, sched, width=STALL_WIDTH):
     """First iterate index whose tracked width ``max(l_k, 1 - h_k)`` is below
-    ``u`` (``len(sched)`` if none is): from there the stagnation rule may
+    ``width`` (``len(sched)`` if none is): from there the stagnation rule may
     compare errors."""
     w = max(l, 1.0 - h)
     for k, (_, _, lk, hk) in enumerate(sched):
-        if w < u:
+        if w < width:
             return k
         w = max(lk, 1.0 - hk)
     return len(sched)
 
 
-def _schedule(rec, homo, lumo, max_iter, u):
+def _schedule(rec, homo, lumo, max_iter):
     l, h = mapped_interval(rec.eps_min, rec.eps_max, homo, lumo)
     sched = acceleration_schedule(l, h, max_iter)
     return ([layer_polynomial(sg, s) for sg, s, _, _ in sched],
-            stall_start(l, h, sched, u) if sched else 0)
+            stall_start(l, h, sched) if sched else 0)
 
 
 def sp2_accelerated(h, n_occ, homo, lumo, tol=1e-10, max_iter=100, stop_rule=0,
-                    stall_gate=STALL_GATE, bounds=None, refine=False, return_iterates=False,
-                    unit_roundoff=2.0 ** -53):
+                    stall_gate=STALL_GATE, bounds=None, refine=False, return_iterates=False):
     """DNN-SP2 whose first layers follow the accelerated schedule of the
     estimates ``homo < lumo`` (energies), then the trace-driven rule.
-    ``unit_roundoff``: ``u`` of the stagnation gating (FP64 here).
 
     Returns ``(D, record)``; ``record.coefs`` holds ``(a, b, c)`` of every
     applied layer (``record.branches`` its sign)."""
@@ -163,7 +163,7 @@ def sp2_accelerated(h, n_occ, homo, lumo, tol=1e-10, max_iter=100, stop_rule=0,
         return (d, rec, [d]) if return_iterates else (d, rec)
     if not eps_max > eps_min:
         raise ValueError("degenerate spectrum: no gap to place the step in")
-    sched, stall_from = _schedule(rec, homo, lumo, max_iter, unit_roundoff)
+    sched, stall_from = _schedule(rec, homo, lumo, max_iter)
     s = input_layer(h, eps_min, eps_max)
     iterates = [s]
     for k in range(max_iter + 1):
@@ -198,13 +198,13 @@ def sp2_accelerated(h, n_occ, homo, lumo, tol=1e-10, max_iter=100, stop_rule=0,
 
 
 def sp2_accelerated_scalar(w, n_occ, eps_min, eps_max, homo, lumo, tol=1e-10, max_iter=100,
-                           stop_rule=0, stall_gate=STALL_GATE, unit_roundoff=2.0 ** -53):
+                           stop_rule=0, stall_gate=STALL_GATE):
     """The same network on the eigenvalues ``w`` of ``H`` (every layer is a
     polynomial of ``S_0``, which shares the eigenvectors of ``H``).
     Returns ``(p(x), record)``."""
     x = (eps_max - np.asarray(w, dtype=np.float64)) / (eps_max - eps_min)
     rec = SP2Record(eps_min=eps_min, eps_max=eps_max)
-    sched, stall_from = _schedule(rec, homo, lumo, max_iter, unit_roundoff)
+    sched, stall_from = _schedule(rec, homo, lumo, max_iter)
     for k in range(max_iter + 1):
         t1 = float(np.sum(x))
         t2 = float(np.sum(x * x))

@@ -2,8 +2,9 @@
 
 Runs the same DNN-SP2 network as ``sp2_oracle.sp2`` but stores every iterate
 in FP32 and forms each square from the dual 16-bit representation of
-Eq. (20)-(22) (or plain FP32), with FP32 accumulation (NumPy ``float32``
-matmul).  Used only to predict the error floor each precision mode reaches
+Eq. (20)-(22) of the centred iterate ``S - I/2`` (or plain FP32), with FP32
+accumulation (NumPy ``float32`` matmul), restoring the square in FP32
+(``layer_emulated``).  Used only to predict the error floor each precision mode reaches
 against the exact density matrix, from which the end-to-end test
 tolerances are derived.  The accumulation order differs from the GPU's
 MFMA, so agreement with the GPU is statistical, not bitwise
@@ -12,7 +13,9 @@ MFMA, so agreement with the GPU is statistical, not bitwise
 Pins (tests/test_oracle_emulation.py): on operands exactly representable in
 each mode, ``square_emulated`` equals the exact FP64 sum of the products of
 Eq. (22) (with the 2^-28 rescale for the scaled FP16 pair; X0 X0 alone for the
-single pass); ``automatic_stall_gate`` against closed forms;
+single pass); ``layer_emulated`` equals the exact layer ``a S^2 + b S + c I``
+on iterates whose centred matrix and products are exact in every mode;
+``automatic_stall_gate`` against closed forms;
 ``sp2_emulated("fp32")`` bitwise against a plain FP32 loop written out in
 the test (plain and accelerated); every mode's error against the exact
 density matrix within [1/64, 2] of its operand roundoff times the
@@ -29,6 +32,12 @@ from .sp2_oracle import (FP16_SPLIT_SCALE_LOG2, STALL_GATE, choose_branch, gersh
                          should_stop, split_bf16, split_fp16_scaled)
 
 MODES = ("fp32", "bf16x1", "bf16x3", "fp16x3")
+
+# The split modes represent a network iterate S by the planes of S - cI,
+# c = PLANE_CENTRE: its eigenvalues lie in [-1/2, 1/2] and its diagonal
+# entries (near 0 or 1 for S near a density matrix) shrink, and with them
+# the FP32 partial sums of each product and the 16-bit roundings.
+PLANE_CENTRE = 0.5
 
 
 def square_emulated(x, mode):
@@ -47,6 +56,27 @@ def square_emulated(x, mode):
         hi, lo = split_fp16_scaled(x)
         return (hi @ hi + (hi @ lo + lo @ hi)) * np.float32(2.0 ** (-2 * FP16_SPLIT_SCALE_LOG2))
     raise ValueError(mode)
+
+
+def layer_emulated(s, mode, a, b, c):
+    """One layer ``a S^2 + b S + c I`` of an FP32 symmetric iterate in the
+    given arithmetic, FP32 result.  The split modes square the centred
+    matrix ``T = S - PLANE_CENTRE I`` (rounded to FP32, then to its planes)
+    and restore ``S^2 = T^2 + 2c S - c^2 I`` (c = PLANE_CENTRE) in FP32:
+    ``a T^2 + (b + 2c a) S + (c' - c^2 a) I``."""
+    s = np.asarray(s, dtype=np.float32)
+    diag = np.diag_indices(s.shape[0])
+    if mode == "fp32":
+        out = np.float32(a) * square_emulated(s, mode).astype(np.float32) + np.float32(b) * s
+        if c != 0.0:
+            out[diag] += np.float32(c)
+        return out
+    t = s.copy()
+    t[diag] -= np.float32(PLANE_CENTRE)
+    sq = square_emulated(t, mode).astype(np.float32)
+    out = np.float32(a) * sq + np.float32(b + 2.0 * PLANE_CENTRE * a) * s
+    out[diag] += np.float32(c - PLANE_CENTRE * PLANE_CENTRE * a)
+    return out
 
 
 # Significant bits of the layer operands in each mode: a BF16 value carries 8,
@@ -87,7 +117,7 @@ def sp2_emulated(h, n_occ, mode, tol=1e-5, max_iter=100, stop_rule=1, stall_gate
         steps = acceleration_schedule(l, hh, max_iter)
         sched = [layer_polynomial(sg, sh) for sg, sh, _, _ in steps]
         if steps:
-            stall_from = stall_start(l, hh, steps, 2.0 ** (-OPERAND_BITS[mode]))
+            stall_from = stall_start(l, hh, steps)
     diag = np.diag_indices(n)
     errs = []
     layers = 0
@@ -103,14 +133,11 @@ def sp2_emulated(h, n_occ, mode, tol=1e-5, max_iter=100, stop_rule=1, stall_gate
             # end-of-schedule check failed: the plain network from the start
             return sp2_emulated(h, n_occ, mode, tol, max_iter, stop_rule, stall_gate, refine,
                                 (lo_b, hi_b))
-        sq = square_emulated(s, mode).astype(np.float32)
         if k < len(sched):
             a, b, c = sched[k]
-            s = np.float32(a) * sq + np.float32(b) * s
-            s[diag] += np.float32(c)
         else:
-            sign = choose_branch(t1, t2, n_occ)
-            s = sq if sign > 0 else np.float32(2.0) * s - sq
+            a, b, c = (1.0, 0.0, 0.0) if choose_branch(t1, t2, n_occ) > 0 else (-1.0, 2.0, 0.0)
+        s = layer_emulated(s, mode, a, b, c)
         s = np.triu(s) + np.triu(s, 1).T          # upper triangle mirrored, as computed
         layers += 1
     if refine:

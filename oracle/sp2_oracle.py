@@ -46,6 +46,7 @@ __all__ = [
     "choose_branch",
     "should_stop",
     "STALL_GATE",
+    "QUAD_FACTOR",
     "sp2",
     "sp2_scalar",
     "mcweeny",
@@ -125,25 +126,37 @@ def should_stop(k, errs, trace_gap, tol, stop_rule, stall_gate, stall_from=0):
     does not yet hold ``n_occ`` eigenvalues near 1 (an occupied eigenvalue can
     be driven close to 0 on the way, which makes ``e_k`` small long before
     convergence).  Otherwise rule 0 stops when ``e_k < tol``; rule 1 also
-    stops on stagnation, ``e_k >= e_{k-2}`` (two more layers did not reduce
-    the error, so rounding dominates), once ``e_k < stall_gate``.  With every
-    eigenvalue in [0, 1], ``e_k < 3/16`` puts each within 1/4 of 0 or 1, where
-    every layer pair contracts in exact arithmetic; together with the trace
-    gap this also fixes which eigenvalues sit near 1.  ``stall_from``: the
-    stagnation comparison uses only ``e_{k-2}`` with ``k - 2 >= stall_from``
-    (an accelerated schedule can raise ``e`` by itself before that, see
-    ``oracle.accelerated``)."""
+    stops once ``e_k < stall_gate`` when the last two layers no longer
+    reduced the error as exact arithmetic would: ``e_k >= e_{k-2}`` or
+    ``e_k >= QUAD_FACTOR e_{k-2}^2``.  With every eigenvalue in [0, 1],
+    ``e_k < 3/16`` puts each within 1/4 of 0 or 1; together with the trace
+    gap this also fixes which eigenvalues sit near 1.  There, with
+    ``m = x (1 - x)`` an eigenvalue's share of ``e`` and its deviation from
+    0 or 1 at most 1/4, a pair of layers of opposite sign maps ``m`` to at
+    most ``(64/9) m^2`` (``4 m^2`` in the limit: ``2 d^2`` for a deviation
+    ``d`` from 0 after ``+ -``, ``4 d^2`` after ``- +``, the mirror for
+    deviations from 1), and the trace-closest rule squares the deviations of
+    the side that dominates the trace, so ``e_k <= (64/9) e_{k-2}^2``: an
+    ``e_k`` of ``16 e_{k-2}^2`` or more is mostly rounding, and the layers
+    after it would only add more.
+    ``stall_from``: the comparisons use only ``e_{k-2}`` with
+    ``k - 2 >= stall_from`` (an accelerated schedule can raise ``e`` by
+    itself before that, see ``oracle.accelerated``)."""
     if not trace_gap < 0.5:
         return False
     e = errs[k]
     if e < tol:
         return True
-    if stop_rule == 1 and k >= 2 and k - 2 >= stall_from and e < stall_gate and e >= errs[k - 2]:
-        return True
+    if stop_rule == 1 and k >= 2 and k - 2 >= stall_from and e < stall_gate:
+        ep = errs[k - 2]
+        return e >= min(ep, QUAD_FACTOR * ep * ep)
     return False
 
 
 STALL_GATE = 3.0 / 16.0
+# Rule 1 stops when e_k >= QUAD_FACTOR e_{k-2}^2: above the exact-arithmetic bound
+# e_k <= (64/9) e_{k-2}^2 below the gate (4 e_{k-2}^2 in the limit; see should_stop).
+QUAD_FACTOR = 16.0
 
 
 @dataclass

@@ -171,6 +171,7 @@ __global__ __launch_bounds__(kEwThreads) void k_input_layer(const float* __restr
                                                             float* __restrict__ S,
                                                             uint16_t* __restrict__ hi,
                                                             uint16_t* __restrict__ lo, int split,
+                                                            float centre,
                                                             double* __restrict__ parts) {
   static_assert(kEwThreads == 256, "tile mapping");
   __shared__ __attribute__((aligned(16))) float tile[kInRows * kInLd];
@@ -217,6 +218,10 @@ __global__ __launch_bounds__(kEwThreads) void k_input_layer(const float* __restr
         if (i == j) t1 += xd;
       }
       *reinterpret_cast<f32x4*>(S + i * np + j0) = f32x4{v[0], v[1], v[2], v[3]};
+      // the planes hold S_0 - centre I (real diagonal)
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (i < n && i == j0 + c) v[c] -= centre;
       *reinterpret_cast<f32x4*>(tile + r * kInLd + 4 * q) = f32x4{v[0], v[1], v[2], v[3]};
     }
     if (split) {
@@ -256,14 +261,17 @@ __global__ __launch_bounds__(kEwThreads) void k_split(const float* __restrict__ 
   }
 }
 
-// Dual representation of an n x n FP32 matrix (leading dimension ld) into
-// the K-tiled hi/lo planes of an np x np matrix (np a multiple of 256; rows
-// and columns in [n, np) are zero): work-groups stride over 32 x 256 tiles,
-// read a row at a time and written as planes from LDS (tile_planes).
+// Dual representation of X - centre I for an n x n FP32 matrix X (leading
+// dimension ld; the centre is taken off the first nd diagonal entries, the
+// real ones of a padded matrix) into the K-tiled hi/lo planes of an np x np
+// matrix (np a multiple of 256; rows and columns in [n, np) are zero):
+// work-groups stride over 32 x 256 tiles, read a row at a time and written
+// as planes from LDS (tile_planes).
 __global__ __launch_bounds__(kEwThreads) void k_split_tiled(const float* __restrict__ X, int64_t n,
                                                             int64_t ld, int64_t np,
                                                             uint16_t* __restrict__ hi,
-                                                            uint16_t* __restrict__ lo, int split) {
+                                                            uint16_t* __restrict__ lo, int split,
+                                                            float centre, int64_t nd) {
   __shared__ __attribute__((aligned(16))) float tile[kInRows * kInLd];
   const bool vec = (ld % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
   const int64_t tiles_c = np / kInCols, ntiles = (np / kInRows) * tiles_c;
@@ -284,6 +292,9 @@ __global__ __launch_bounds__(kEwThreads) void k_split_tiled(const float* __restr
           for (int c = 0; c < 4; ++c)
             if (j0 + c < n) v[c] = X[i * ld + j0 + c];
         }
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          if (i == j0 + c && i < nd) v[c] -= centre;
       }
       *reinterpret_cast<f32x4*>(tile + r * kInLd + 4 * q) = v;
     }
@@ -395,18 +406,19 @@ __global__ __launch_bounds__(256) void k_finish_loop(Ctrl* ctrl, Hist* hist,
 // rather than 1/2 (the smallest folded image) keeps the gap between the two
 // intervals growing fast enough that early rounding is not amplified beyond
 // the plain network's.  The stagnation test may compare errors from the
-// first iterate whose tracked width is below u, the unit roundoff of the
-// layer operands (before that the schedule itself can raise e), or from
-// the end of the schedule.  One thread, FP64, every operation rounded as
+// first iterate whose tracked width is below kStallWidth (the remaining
+// shifts are then below 0.4 kStallWidth and the layers act as plain ones;
+// before that the schedule itself can raise e), or from the end of the
+// schedule.  One thread, FP64, every operation rounded as
 // written (no contraction), so the coefficients are those of the same
 // recursion evaluated anywhere else in IEEE double.  Layers past the
 // schedule use the trace-driven sign.
 // ---------------------------------------------------------------------------
 constexpr double kAccEnd = 1e-14;
 constexpr double kAccFold = 0.4;
+constexpr double kStallWidth = 1e-4;
 
-__global__ void k_acc_schedule(Ctrl* ctrl, Hist* hist, double homo, double lumo, int max_len,
-                               double u) {
+__global__ void k_acc_schedule(Ctrl* ctrl, Hist* hist, double homo, double lumo, int max_len) {
 #pragma clang fp contract(off)
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   ctrl->acc_len = 0;
@@ -418,7 +430,7 @@ __global__ void k_acc_schedule(Ctrl* ctrl, Hist* hist, double homo, double lumo,
   int n = 0, quiet = -1;
   if (l < h) {
     while (n < max_len && fmax(l, 1.0 - h) >= kAccEnd) {
-      if (quiet < 0 && fmax(l, 1.0 - h) < u) quiet = n;
+      if (quiet < 0 && fmax(l, 1.0 - h) < kStallWidth) quiet = n;
       double a, b, c;
       int sign;
       if (l >= 1.0 - h) {

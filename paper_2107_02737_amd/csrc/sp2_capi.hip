@@ -536,6 +536,9 @@ sp2_status launch_layer(const WS& w, int precision, int n, int mode, const float
   e.split_out = split_code_of(precision);
   e.hi_out = w.hi(pair_out);
   e.lo_out = w.lo(pair_out);
+  // Planes of S_n - I/2 in, planes of S_{n+1} - I/2 out (kPlaneCentre):
+  // S^2 = (S - I/2)^2 + S - I/4, so every layer reads C = S_n.
+  e.centring = kCentredSquare | kCentredOut;
   // The next split layer reads only the planes and the upper triangle of C.
   e.mirror_out = full_out ? 1 : 0;
   return launch_split(w, precision, w.hi(pair_in), w.lo(pair_in), w.hi(pair_in), w.lo(pair_in), e,
@@ -660,17 +663,29 @@ sp2_status refine(const WS& w, int precision, int refine_mode, int n_iter, const
     if ((s = launch_f32(w, 1, A, B, e2, d0, st))) return s;
     return SP2_OK;
   }
-  // FP16X3 split refinement: planes of S (pair p) and of S^2 (pair 1-p).
+  // FP16X3 split refinement with S's planes centred (c = kPlaneCentre, pair
+  // p): Q = S^2 = (S - cI)^2 + 2c S - c^2 I, its plain planes in pair 1-p,
+  // then P = 3Q - 2SQ = -2 (S - cI) Q + (3 - 2c) Q.
+  constexpr float c = kPlaneCentre;
   const int p = precision == SP2_FP32 ? 0 : (n_iter & 1);
   if (precision != SP2_FP16X3) {
-    k_split_tiled<<<L.init_blocks, kEwThreads, 0, st>>>(S, L.np, L.np, L.np, w.hi(p), w.lo(p), 2);
+    k_split_tiled<<<L.init_blocks, kEwThreads, 0, st>>>(S, L.np, L.np, L.np, w.hi(p), w.lo(p), 2,
+                                                        c, L.n);
     LAUNCH_TRY();
   }
-  e1.split_out = 2;
-  e1.hi_out = w.hi(1 - p);
-  e1.lo_out = w.lo(1 - p);
-  if ((s = launch_split(w, SP2_FP16X3, w.hi(p), w.lo(p), w.hi(p), w.lo(p), e1, d0, st))) return s;
-  return launch_split(w, SP2_FP16X3, w.hi(p), w.lo(p), w.hi(1 - p), w.lo(1 - p), e2, d0, st);
+  Epi f1 = e1;
+  f1.c = S;
+  f1.beta = 2.0f * c;
+  f1.gamma = -c * c;
+  f1.n_diag = static_cast<int>(L.n);
+  f1.mirror_out = 0;   // the second product reads only the upper triangle of Q
+  f1.split_out = 2;
+  f1.hi_out = w.hi(1 - p);
+  f1.lo_out = w.lo(1 - p);
+  if ((s = launch_split(w, SP2_FP16X3, w.hi(p), w.lo(p), w.hi(p), w.lo(p), f1, d0, st))) return s;
+  Epi f2 = e2;
+  f2.beta = 3.0f - 2.0f * c;
+  return launch_split(w, SP2_FP16X3, w.hi(p), w.lo(p), w.hi(1 - p), w.lo(1 - p), f2, d0, st);
 }
 
 sp2_status read_back(const WS& w, HostMirror* hm, bool with_hist, hipStream_t st) {
@@ -825,8 +840,7 @@ sp2_status density_impl(const float* H, int64_t n, int64_t ld, int64_t n_occ, co
   if (!trivial && o.bound_steps > 0)
     if ((s = refine_bounds(w, H, n, ld, o.bound_steps, o.bound_seed, st))) return s;
   if (!trivial && (o.flags & SP2_FLAG_ACCELERATE)) {
-    k_acc_schedule<<<1, 1, 0, st>>>(w.ctrl, w.hist, o.homo, o.lumo, o.max_iter,
-                                    unit_roundoff_of(prec));
+    k_acc_schedule<<<1, 1, 0, st>>>(w.ctrl, w.hist, o.homo, o.lumo, o.max_iter);
     LAUNCH_TRY();
   }
 
@@ -855,7 +869,8 @@ sp2_status density_impl(const float* H, int64_t n, int64_t ld, int64_t n_occ, co
 
   // Input layer S_0 with its split planes (pair 0) and trace partials.
   k_input_layer<<<L.init_blocks, kEwThreads, 0, st>>>(H, n, ld, L.np, w.ctrl, w.slotf(0), w.hi(0),
-                                                      w.lo(0), split_code_of(prec), w.parts[0]);
+                                                      w.lo(0), split_code_of(prec), kPlaneCentre,
+                                                      w.parts[0]);
   LAUNCH_TRY();
   if (o.checkpoint_every > 0) HIP_TRY(hipMemcpyAsync(w.tape(0), w.slotf(0), L.slot_bytes, hipMemcpyDeviceToDevice, st));
 
@@ -1213,9 +1228,13 @@ sp2_status sp2_layer(const float* X, int64_t n, int64_t ld, int32_t precision, i
     const float* A[1] = {Xp};
     s = launch_f32(w, 1, A, A, e, d0, st);
   } else {
+    // as in the network: the planes hold X - cI, X^2 = (X - cI)^2 + 2c X - c^2 I
     k_split_tiled<<<L.init_blocks, kEwThreads, 0, st>>>(Xp, L.np, L.np, L.np, w.hi(0), w.lo(0),
-                                                        split_code_of(precision));
+                                                        split_code_of(precision), kPlaneCentre, L.n);
     LAUNCH_TRY();
+    e.beta += 2.0f * kPlaneCentre * e.alpha;
+    e.gamma = -kPlaneCentre * kPlaneCentre * e.alpha;
+    e.n_diag = static_cast<int>(n);
     s = launch_split(w, precision, w.hi(0), w.lo(0), w.hi(0), w.lo(0), e, d0, st);
   }
   if (s) return s;
@@ -1323,13 +1342,16 @@ sp2_status sym_pair_split(const WS& w, const uint16_t* xh, const uint16_t* xl, i
   e.split_out = split_code_of(SP2_BF16X3);
   e.hi_out = dhi(w, op);
   e.lo_out = dlo(w, op);
+  // X's planes are centred: (X - cI) Y + Y (X - cI) = X Y + Y X - 2c Y
+  e.centring = kCentredPair;
   return launch_split_pair(w, xh, xl, dhi(w, yp), dlo(w, yp), e, make_decide(w, mode, layer), st);
 }
 
 // BF16X3 planes of an FP32 derivative iterate (np x np) into pair `op`.
 sp2_status split_derivative(const WS& w, const float* X, int op, hipStream_t st) {
   k_split_tiled<<<w.L.init_blocks, kEwThreads, 0, st>>>(X, w.L.np, w.L.np, w.L.np, dhi(w, op),
-                                                        dlo(w, op), split_code_of(SP2_BF16X3));
+                                                        dlo(w, op), split_code_of(SP2_BF16X3), 0.0f,
+                                                        0);
   LAUNCH_TRY();
   return SP2_OK;
 }
@@ -1363,12 +1385,16 @@ sp2_status refine_derivative(const WS& w, const float* S, const float* D, float*
 }
 
 // The same map in BF16X3 products (split derivatives): S given by its
-// planes in forward pair ps, D by its planes in derivative pair qd (its FP32
-// copy in work(qd) is overwritten).  Four products: M = SD + DS (planes in
-// derivative pair 1 - qd), S^2 (planes in forward pair 1 - ps),
-// T = 3M - (S^2 D + D S^2) into work(qd), out = T - (SM + MS).
-sp2_status refine_derivative_split(const WS& w, int ps, int qd, float* out, int64_t ld, int64_t n,
-                                   bool vec_ok, hipStream_t st) {
+// centred planes (S - cI, c = kPlaneCentre) in forward pair ps and its FP32
+// value S32, D by its planes in derivative pair qd and its FP32 copy in
+// work(qd) (overwritten).  Four products: M = SD + DS = [(S - cI) D +
+// D (S - cI)] + 2c D (planes in derivative pair 1 - qd), S^2 = (S - cI)^2 +
+// 2c S - c^2 I (plain planes in forward pair 1 - ps), T = (3 - 2c) M -
+// (S^2 D + D S^2) into work(qd), out = T - [(S - cI) M + M (S - cI)]
+// (= 3M - (SM + MS) - (S^2 D + D S^2)).
+sp2_status refine_derivative_split(const WS& w, int ps, int qd, const float* S32, float* out,
+                                   int64_t ld, int64_t n, bool vec_ok, hipStream_t st) {
+  constexpr float c = kPlaneCentre;
   const int bf = split_code_of(SP2_BF16X3);
   const Decide d0 = make_decide(w, 0, 0);
   float* M = w.work(1 - qd);
@@ -1376,6 +1402,8 @@ sp2_status refine_derivative_split(const WS& w, int ps, int qd, float* out, int6
   sp2_status s;
   {
     Epi e = make_epi(w.L);
+    e.c = w.work(qd);
+    e.beta = 2.0f * c;
     e.out = M;
     e.split_out = bf;
     e.hi_out = dhi(w, 1 - qd);
@@ -1384,6 +1412,10 @@ sp2_status refine_derivative_split(const WS& w, int ps, int qd, float* out, int6
   }
   {
     Epi e = make_epi(w.L);
+    e.c = S32;
+    e.beta = 2.0f * c;
+    e.gamma = -c * c;
+    e.n_diag = static_cast<int>(w.L.n);
     e.out = w.slotf(3);
     e.split_out = bf;
     e.hi_out = w.hi(1 - ps);
@@ -1395,7 +1427,7 @@ sp2_status refine_derivative_split(const WS& w, int ps, int qd, float* out, int6
     e.c = M;
     e.out = T;
     e.alpha = -1.0f;
-    e.beta = 3.0f;
+    e.beta = 3.0f - 2.0f * c;
     if ((s = launch_split_pair(w, w.hi(1 - ps), w.lo(1 - ps), dhi(w, qd), dlo(w, qd), e, d0, st)))
       return s;
   }
@@ -1416,7 +1448,8 @@ sp2_status load_checkpoint(const WS& w, int prec, int slot, float* dst, hipStrea
   HIP_TRY(hipMemcpyAsync(dst, w.tape(slot), w.L.slot_bytes, hipMemcpyDeviceToDevice, st));
   if (prec != SP2_FP32) {
     k_split_tiled<<<w.L.init_blocks, kEwThreads, 0, st>>>(dst, w.L.np, w.L.np, w.L.np, w.hi(0),
-                                                          w.lo(0), split_code_of(prec));
+                                                          w.lo(0), split_code_of(prec), kPlaneCentre,
+                                                          w.L.n);
     LAUNCH_TRY();
   }
   return SP2_OK;
@@ -1461,7 +1494,7 @@ sp2_status jvp_run(const WS& w, const HostMirror* hm, const sp2_options& o, cons
   if (o.refine != SP2_REFINE_NONE) {
     // S_nl's planes are in forward pair nl & 1, Y's in derivative pair nl & 1
     if (sd)
-      s = refine_derivative_split(w, nl & 1, nl & 1, P1, ld, n, vec_ok, st);
+      s = refine_derivative_split(w, nl & 1, nl & 1, s_f32(w, prec, nl), P1, ld, n, vec_ok, st);
     else
       s = refine_derivative(w, s_f32(w, prec, nl), Y, P1, ld, n, vec_ok, st);
     if (s) return s;
@@ -1529,7 +1562,8 @@ sp2_status sp2_vjp(void* workspace, size_t ws_bytes, const float* W, int64_t ld,
     if (sd) {
       // S_L's planes are in forward pair (nl - c) & 1; G's go to derivative pair 0
       if ((s = split_derivative(w, w.work(0), 0, st))) return s;
-      s = refine_derivative_split(w, (nl - c) & 1, 0, w.work(1), L.np, L.np, true, st);
+      s = refine_derivative_split(w, (nl - c) & 1, 0, s_f32(w, prec, nl), w.work(1), L.np, L.np,
+                                  true, st);
     } else {
       s = refine_derivative(w, s_f32(w, prec, nl), w.work(0), w.work(1), L.np, L.np, true, st);
     }
@@ -1549,7 +1583,8 @@ sp2_status sp2_vjp(void* workspace, size_t ws_bytes, const float* W, int64_t ld,
       if (sd) {
         // planes of S_nn into pair 0 (the recomputation has moved on)
         k_split_tiled<<<L.init_blocks, kEwThreads, 0, st>>>(w.seg(nn - c), L.np, L.np, L.np, w.hi(0),
-                                                            w.lo(0), split_code_of(SP2_BF16X3));
+                                                            w.lo(0), split_code_of(SP2_BF16X3),
+                                                            kPlaneCentre, L.n);
         LAUNCH_TRY();
         s = sym_pair_split(w, w.hi(0), w.lo(0), cur, w.work(cur), w.work(1 - cur), 1 - cur, 3, nn,
                            st);

@@ -19,6 +19,13 @@ typedef __attribute__((ext_vector_type(2))) uint32_t u32x2;
 constexpr int kWave = 64;
 constexpr int kMaxIter = SP2_MAX_ITER;
 constexpr int kFp16ScaleLog2 = 14;   // 2^14 X keeps the FP16 residual normal
+// The split planes of a network iterate S hold S - kPlaneCentre I.  Every
+// eigenvalue of S lies in [0, 1], so the centred matrix has eigenvalues in
+// [-1/2, 1/2] and much smaller diagonal entries (those of a density matrix
+// sit near 0 or 1): the FP32 partial sums of the MFMA K loop and the 16-bit
+// roundings of the operands shrink with them, and the layer restores
+// S^2 = (S - I/2)^2 + S - I/4 exactly in its epilogue.
+constexpr float kPlaneCentre = 0.5f;
 
 // Device control block: one per workspace.  Written by the bound pass, the
 // layer kernels (work-group 0 only) and the one-work-group control kernels.
@@ -141,17 +148,27 @@ __device__ __forceinline__ void block_sum2(double& a, double& b, double* red) {
 // traces), e = |t1 - t2|.  No stop while |t1 - n_occ| >= 1/2: S_n does not
 // yet hold n_occ eigenvalues near 1 (an occupied eigenvalue can pass close to
 // 0 on the way, which makes e small long before convergence).  Then rule 0:
-// e < tol; rule 1 also stops once e < stall_gate and e >= e_{n-2} (two
-// layers brought no reduction, so rounding dominates), comparing only from
-// n - 2 >= stall_from (inside an accelerated schedule e can rise by itself
-// until the tracked interval width falls below the unit roundoff).
+// e < tol; rule 1 also stops once e < stall_gate and the last two layers did
+// not reduce e as exact arithmetic would: e >= e_{n-2}, or
+// e >= kQuadFactor e_{n-2}^2.  Below the gate (every eigenvalue within 1/4
+// of 0 or 1) a pair of layers of opposite sign maps each eigenvalue's share
+// x(1 - x) of e to at most 64/9 times its square (4 times in the limit), and
+// the trace-closest sign squares the side that dominates the trace, so
+// e_n <= (64/9) e_{n-2}^2 in exact arithmetic: an e_n of 16 e_{n-2}^2 or
+// more is mostly rounding.  The
+// comparisons start at n - 2 >= stall_from (inside an accelerated schedule e
+// can rise, or fall less than quadratically, by itself until the tracked
+// interval width is small).
+constexpr double kQuadFactor = 16.0;
+
 __device__ __forceinline__ bool stop_test(double t1, double e, int n, const double* err_hist,
                                           double n_occ, double tol, int stop_rule,
                                           double stall_gate, int stall_from) {
   if (!(fabs(t1 - n_occ) < 0.5)) return false;
   if (e < tol) return true;
-  return stop_rule == 1 && n >= 2 && n - 2 >= stall_from && e < stall_gate &&
-         e >= err_hist[n - 2];
+  if (!(stop_rule == 1 && n >= 2 && n - 2 >= stall_from && e < stall_gate)) return false;
+  const double ep = err_hist[n - 2];
+  return e >= fmin(ep, kQuadFactor * ep * ep);
 }
 
 template <int NT>

@@ -24,6 +24,16 @@ namespace sp2 {
 
 enum SplitKind { kBF16X3 = 0, kBF16X1 = 1, kFP16X3 = 2 };
 
+// Centred operands (c = kPlaneCentre): the split planes of a symmetric X
+// hold X - cI, so the raw product of a square is X^2 - 2c X + c^2 I and that
+// of a pair (X Y + Y X) is X Y + Y X - 2c Y.  With a branch coefficient
+// (a, b, c') a launch flagged kCentredSquare uses beta = b + 2c a and
+// gamma = c' - c^2 a, one flagged kCentredPair beta = b + 2c a; without a
+// branch the host folds the same terms into alpha, beta and gamma.
+// kCentredOut: the planes written for the result hold v - cI (real
+// diagonal), as the next layer expects.
+constexpr int kCentredSquare = 1, kCentredPair = 2, kCentredOut = 4;
+
 struct Epi {
   const float* c;        // addend C (ld = np); read only where needed
   float* out;            // result, leading dimension ld_out
@@ -35,6 +45,8 @@ struct Epi {
   int split_out;         // 0 none, 1 bf16, 2 fp16 scaled
   double* parts_out;     // optional (Tr, ||.||_F^2) pair per work-group
   float alpha, beta;     // used when the launch has no branch
+  float gamma;           // diagonal term of a launch without branch
+  int centring;          // kCentredSquare / kCentredPair / kCentredOut bits
   float oscale;          // scale of the raw accumulator (2^-28 for scaled fp16)
   int np;
   int mirror_out;        // 1: FP32 result in both triangles; 0: upper triangle only
@@ -193,6 +205,7 @@ __device__ __forceinline__ void epilogue_passes(const Epi& p, float as, float be
 #pragma clang loop unroll(full)
         for (int j = 0; j < 4; ++j) v[i][j] = as * v[i][j];
     }
+    const float oc = (p.centring & kCentredOut) ? kPlaneCentre : 0.0f;
 #pragma clang loop unroll(full)
     for (int i = 0; i < 4; ++i) {
       const int rh = w + 4 * (rb + i), rl = hr + rh;
@@ -202,8 +215,11 @@ __device__ __forceinline__ void epilogue_passes(const Epi& p, float as, float be
         const int c = lane + 64 * j;
         const bool up = !diag || c >= rl;   // below the diagonal: mirrored from above
         const bool on = diag && c == rl;
-        if (on && row < p.n_diag) v[i][j] += gamma;
-        img[rh * S + c] = v[i][j];
+        const bool real_on = on && row < p.n_diag;
+        if (real_on) v[i][j] += gamma;
+        // the image feeds the plane passes (centred) and the mirrored FP32
+        // pass (off the diagonal only, where the two agree)
+        img[rh * S + c] = real_on ? v[i][j] - oc : v[i][j];
         const double d = up ? static_cast<double>(v[i][j]) : 0.0;
         t1 += on ? d : 0.0;
         t2 += (on ? 1.0 : 2.0) * d * d;     // each unordered pair counted once
@@ -391,11 +407,12 @@ void k_sym_split(SplitArgs p) {
 
   const LayerCoef cf = decide_layer<NT>(p.dec, red);
   if (cf.sign == 0) return;
-  float alpha = p.epi.alpha, beta = p.epi.beta, gamma = 0.0f;
+  float alpha = p.epi.alpha, beta = p.epi.beta, gamma = p.epi.gamma;
   if (p.dec.mode != 0) {
+    const int cn = p.epi.centring;
     alpha = cf.a;
-    beta = cf.b;
-    gamma = cf.c;
+    beta = (cn & (kCentredSquare | kCentredPair)) ? cf.b + 2.0f * kPlaneCentre * cf.a : cf.b;
+    gamma = (cn & kCentredSquare) ? cf.c - kPlaneCentre * kPlaneCentre * cf.a : cf.c;
   }
   const int64_t np = p.epi.np;
   const int KT = static_cast<int>(np / BK);
@@ -589,11 +606,12 @@ __global__ __launch_bounds__(256) void k_split_tail(SplitArgs p) {
   __shared__ double red[2 * (NT / kWave)];
   const LayerCoef cf = recorded_coef(p.dec);
   if (cf.sign == 0) return;
-  float alpha = p.epi.alpha, beta = p.epi.beta, gamma = 0.0f;
+  float alpha = p.epi.alpha, beta = p.epi.beta, gamma = p.epi.gamma;
   if (p.dec.mode != 0) {
+    const int cn = p.epi.centring;
     alpha = cf.a;
-    beta = cf.b;
-    gamma = cf.c;
+    beta = (cn & (kCentredSquare | kCentredPair)) ? cf.b + 2.0f * kPlaneCentre * cf.a : cf.b;
+    gamma = (cn & kCentredSquare) ? cf.c - kPlaneCentre * kPlaneCentre * cf.a : cf.c;
   }
   const Decomp& dc = p.dc;
   const int tail = blockIdx.x / kTailStrips, s = blockIdx.x % kTailStrips;
@@ -670,11 +688,12 @@ void k_sym_f32(F32Args p) {
 
   const LayerCoef cf = decide_layer<NT>(p.dec, red);
   if (cf.sign == 0) return;
-  float alpha = p.epi.alpha, beta = p.epi.beta, gamma = 0.0f;
+  float alpha = p.epi.alpha, beta = p.epi.beta, gamma = p.epi.gamma;
   if (p.dec.mode != 0) {
+    const int cn = p.epi.centring;
     alpha = cf.a;
-    beta = cf.b;
-    gamma = cf.c;
+    beta = (cn & (kCentredSquare | kCentredPair)) ? cf.b + 2.0f * kPlaneCentre * cf.a : cf.b;
+    gamma = (cn & kCentredSquare) ? cf.c - kPlaneCentre * kPlaneCentre * cf.a : cf.c;
   }
   const int64_t np = p.epi.np;
   const int KT = static_cast<int>(np / BK);

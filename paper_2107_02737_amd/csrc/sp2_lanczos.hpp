@@ -259,11 +259,23 @@ __global__ __launch_bounds__(kLzMvThreads) void k_lz_matvec(const float* __restr
 // part[chunk * kLzCoef + i].
 __device__ __forceinline__ void chunk_dots(const double* V, double wr, int64_t row, int64_t n, int j,
                                            double* part, double* red) {
-  constexpr int NW = kLzChunk / kWave;
-  for (int i = 0; i <= j; ++i) {
-    const double p = row < n ? V[int64_t(i) * n + row] * wr : 0.0;
-    const double s = wave_sum(p);
-    if ((threadIdx.x & (kWave - 1)) == 0) red[(threadIdx.x / kWave) * kLzCoef + i] = s;
+  constexpr int NW = kLzChunk / kWave, B = 8;
+  // eight wave reductions side by side (each the butterfly of wave_sum)
+  for (int i0 = 0; i0 <= j; i0 += B) {
+    double p[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int i = i0 + b;
+      p[b] = (row < n && i <= j) ? V[int64_t(i) * n + row] * wr : 0.0;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+      for (int b = 0; b < B; ++b) p[b] += __shfl_xor(p[b], off, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0)
+#pragma unroll
+      for (int b = 0; b < B; ++b)
+        if (i0 + b <= j) red[(threadIdx.x / kWave) * kLzCoef + i0 + b] = p[b];
   }
   __syncthreads();
   for (int i = threadIdx.x; i <= j; i += kLzChunk) {

@@ -79,36 +79,46 @@ def test_split_bit_exact(pk, precision):
 
 
 def _layer_reference(x32, precision, sign):
-    """FP64 product of exactly the operands the kernel multiplies, and the
-    elementwise FP32-accumulation error bound gamma * (|A||B| summed)."""
+    """FP64 value of exactly what the kernel computes, and the elementwise
+    FP32-accumulation error bound gamma * (|A||B| summed) plus the FP32
+    roundings of the epilogue.  FP32: X^2 (or 2X - X^2) of the FP32 operand.
+    Split modes square the centred matrix T = X - I/2 (rounded to FP32, then
+    split; the operands are its planes) and restore the layer as
+    a T^2 + (b + a) X + (-a/4) I, with (a, b) = (1, 0) or (-1, 2)."""
     x = x32.astype(np.float64)
     n = x.shape[0]
+    a, b = (1.0, 0.0) if sign > 0 else (-1.0, 2.0)
     if precision == "fp32":
         r = x @ x
-        a = np.abs(x) @ np.abs(x)
+        acc = np.abs(x) @ np.abs(x)
+        nterms = n
+        y = a * r + b * x
+        bound = (nterms + 4) * U32 * acc + 2 * U32 * np.abs(r)
+        if sign < 0:
+            bound = bound + 4 * U32 * np.abs(x) + 2 * U32 * np.abs(y)
+        return y, bound
+    t32 = x32.copy()
+    t32[np.diag_indices(n)] -= np.float32(0.5)
+    if precision == "fp16x3":
+        hi, lo = oracle.split_fp16_scaled(t32)
+        s = 2.0 ** (-2 * oracle.FP16_SPLIT_SCALE_LOG2)
+    else:
+        hi, lo = oracle.split_bf16(t32)
+        s = 1.0
+    hi = hi.astype(np.float64)
+    lo = lo.astype(np.float64)
+    if precision == "bf16x1":
+        r = hi @ hi
+        acc = np.abs(hi) @ np.abs(hi)
         nterms = n
     else:
-        if precision == "fp16x3":
-            hi, lo = oracle.split_fp16_scaled(x32)
-            s = 2.0 ** (-2 * oracle.FP16_SPLIT_SCALE_LOG2)
-        else:
-            hi, lo = oracle.split_bf16(x32)
-            s = 1.0
-        hi = hi.astype(np.float64)
-        lo = lo.astype(np.float64)
-        if precision == "bf16x1":
-            r = hi @ hi
-            a = np.abs(hi) @ np.abs(hi)
-            nterms = n
-        else:
-            r = (hi @ hi + hi @ lo + lo @ hi) * s
-            a = (np.abs(hi) @ np.abs(hi) + np.abs(hi) @ np.abs(lo) + np.abs(lo) @ np.abs(hi)) * s
-            nterms = 3 * n
-    bound = (nterms + 4) * U32 * a + 2 * U32 * np.abs(r)
-    if sign < 0:
-        r = 2.0 * x - r
-        bound = bound + 4 * U32 * np.abs(x) + 2 * U32 * np.abs(r)
-    return r, bound
+        r = (hi @ hi + hi @ lo + lo @ hi) * s
+        acc = (np.abs(hi) @ np.abs(hi) + np.abs(hi) @ np.abs(lo) + np.abs(lo) @ np.abs(hi)) * s
+        nterms = 3 * n
+    y = a * r + (b + a) * x - 0.25 * a * np.eye(n)
+    bound = ((nterms + 4) * U32 * acc + 2 * U32 * np.abs(r) + 4 * U32 * np.abs(x)
+             + 4 * U32 * np.abs(y))
+    return y, bound
 
 
 # (n, ld, split-K): at these sizes the 256x256 tiles do not fill the machine,

@@ -7,9 +7,10 @@ machine runs at once, so a launch mixes whole-tile work-groups with tiles
 split along K whose pieces are summed by a second kernel.  Every output
 entry at N = 6144, and whole sampled rows at N = 16384 (every tile row that
 holds a split tile among them), are compared with the FP64 product of exactly
-the operands the kernel multiplies (the oracle's 16-bit rounding), within
-the FP32 accumulation bound (3n + 4) u sum|a||b| (plus the rounding of the
-epilogue for 2X - X^2)."""
+the operands the kernel multiplies (the oracle's 16-bit rounding of the
+centred matrix X - I/2), within the FP32 accumulation bound
+(3n + 4) u sum|a||b| plus the rounding of the epilogue that restores the
+layer."""
 
 import numpy as np
 import pytest
@@ -30,11 +31,14 @@ def pk():
 
 
 def _operands(x32, precision):
-    """Hi/lo operands (FP64) and the scale of their products."""
+    """Hi/lo operands (FP64) of the centred matrix X - I/2 (rounded to FP32,
+    then split, as the kernel's planes) and the scale of their products."""
+    t32 = x32.copy()
+    t32[np.diag_indices(t32.shape[0])] -= np.float32(0.5)
     if precision == "fp16x3":
-        hi, lo = oracle.split_fp16_scaled(x32)
+        hi, lo = oracle.split_fp16_scaled(t32)
         return hi.astype(np.float64), lo.astype(np.float64), 2.0 ** (-2 * oracle.FP16_SPLIT_SCALE_LOG2)
-    hi, lo = oracle.split_bf16(x32)
+    hi, lo = oracle.split_bf16(t32)
     return hi.astype(np.float64), lo.astype(np.float64), 1.0
 
 
@@ -49,13 +53,14 @@ def _rows_reference(x32, rows, precision):
     return r, (3 * n + 4) * U32 * a + 2 * U32 * np.abs(r)
 
 
-def _check(y_rows, x_rows, r, bound, sign):
+def _check(y_rows, x_rows, rows, r, bound, sign):
+    """The layer restored from the centred square: a T^2 + (b + a) X - (a/4) I
+    with (a, b) = (1, 0) for X^2 and (-1, 2) for 2X - X^2."""
     x = x_rows.astype(np.float64)
-    if sign < 0:
-        ref = 2.0 * x - r
-        bnd = bound + 4 * U32 * np.abs(x) + 2 * U32 * np.abs(ref)
-    else:
-        ref, bnd = r, bound
+    a, b = (1.0, 0.0) if sign > 0 else (-1.0, 2.0)
+    ref = a * r + (b + a) * x
+    ref[np.arange(len(rows)), rows] -= 0.25 * a
+    bnd = bound + 4 * U32 * np.abs(x) + 4 * U32 * np.abs(ref)
     err = np.abs(y_rows - ref)
     worst = float(np.max(err / bnd))
     print(f"  sign={sign:+d} max|err| {err.max():.3e}  max err/bound {worst:.3f}", flush=True)
@@ -92,7 +97,7 @@ def test_layer_every_entry_n6144(pk, water6144, precision):
         pk.sp2_layer(X, precision, sign, Y, ws)
         y = to_host(Y)
         assert np.array_equal(y, y.T)
-        _check(y, x32, r, bound, sign)
+        _check(y, x32, rows, r, bound, sign)
 
 
 def _tile_rows_of_tail(n, cus=256, band=4):
@@ -136,5 +141,5 @@ def test_layer_sampled_rows_n16384(pk):
             y_rows = Y.index_select(0, ri).double().cpu().numpy()
             yt_rows = Y.index_select(1, ri).t().double().cpu().numpy()
             assert np.array_equal(y_rows, yt_rows)          # the mirror write is exact
-            _check(y_rows, x32[rows], r, bound, sign)
+            _check(y_rows, x32[rows], rows, r, bound, sign)
             del Y

@@ -221,6 +221,92 @@ def test_single_layer_rise_does_not_stop_the_network():
     assert r1.converged and r1.err[-1] < 1e-12
 
 
+def test_quadratic_stall_threshold():
+    """Rule 1 compares e_k with min(e_{k-2}, 16 e_{k-2}^2): at e_{k-2} = 0.01
+    the threshold is 1.6e-3 (not 1e-2, the plain comparison, nor 4e-4);
+    above e_{k-2} = 1/16 the plain comparison is the smaller one; the gate,
+    the trace guard and stall_from still apply."""
+    g = oracle.STALL_GATE
+    assert oracle.QUAD_FACTOR == 16.0
+    stop = lambda errs, gap=0.0, sf=0: oracle.should_stop(len(errs) - 1, errs, gap, 0.0, 1, g, sf)
+    assert stop([0.01, 0.5, 1.6e-3])
+    assert not stop([0.01, 0.5, 1.59e-3])
+    assert not stop([0.01, 0.5, 1.6e-3], gap=0.5)
+    assert not stop([0.5, 0.01, 0.5, 1.6e-3], sf=2)
+    assert stop([0.5, 0.01, 0.5, 1.6e-3], sf=1)
+    assert stop([0.1, 0.5, 0.1]) and not stop([0.1, 0.5, 0.0999])      # min is e_{k-2}
+    assert not stop([0.1, 0.5, 0.1], gap=0.6)
+    assert not stop([0.3, 0.5, 0.2])                                   # above the gate
+    assert not oracle.should_stop(2, [0.01, 0.5, 1.0], 0.0, 0.0, 0, g)  # rule 0
+
+
+def _random_spectrum(rng, trial):
+    n = int(rng.integers(3, 300))
+    kind = trial % 4
+    if kind == 0:
+        w = rng.normal(size=n)
+    elif kind == 1:
+        w = rng.uniform(-1.0, 1.0, size=n)
+    elif kind == 2:
+        w = np.concatenate([rng.normal(-1.0, 0.3, n // 2), rng.normal(1.0, 0.3, n - n // 2)])
+    else:
+        w = np.round(rng.normal(size=n), 1)       # many degenerate levels
+    w = np.sort(w)
+    n_occ = int(rng.integers(1, n))
+    lo = w[0] - rng.uniform(0.0, 0.5) * (w[-1] - w[0]) - 1e-3
+    hi = w[-1] + rng.uniform(0.0, 0.5) * (w[-1] - w[0]) + 1e-3
+    return w, n_occ, lo, hi
+
+
+def test_quadratic_stall_rule_never_stops_an_exact_network_early():
+    """In exact (FP64 scalar) arithmetic rule 1 with tol = 0 runs every plain
+    and accelerated network on random spectra (normal, uniform, two bands,
+    degenerate levels; occupations 1 .. N-1; loose and tight bounds) until
+    e_k < 1e-6 with every eigenvalue within 1e-6 of its side.  (The bound
+    e_k <= 4 e_{k-2}^2 can fail by itself only once e is tiny and carried by
+    one or two eigenvalues: over 2232 such runs the earliest stop was at
+    2.9e-7.)  A comparison that fired on a quadratically falling e (a
+    smaller factor, the wrong lag, or no stall_from in the schedule) stops
+    with e_k of order 1e-2 .. 1e-1 on some of them."""
+    rng = np.random.default_rng(7)
+    runs = 0
+    for trial in range(160):
+        w, n_occ, lo, hi = _random_spectrum(rng, trial)
+        gap = w[n_occ] - w[n_occ - 1]
+        if gap < 1e-3 * (hi - lo):
+            continue
+        target = np.arange(w.size) < n_occ
+        x, rec = oracle.sp2_scalar(w, n_occ, lo, hi, tol=0.0, max_iter=200, stop_rule=1)
+        nets = [(x, rec)]
+        for m in (0.0, 0.3):
+            nets.append(oracle.accelerated.sp2_accelerated_scalar(
+                w, n_occ, lo, hi, w[n_occ - 1] + m * gap, w[n_occ] - m * gap, tol=0.0,
+                max_iter=200, stop_rule=1))
+        for x, rec in nets:
+            runs += 1
+            assert rec.converged
+            assert rec.err[-1] < 1e-6, (trial, rec.err[-4:])
+            assert np.max(np.abs(x - target)) < 1e-6, trial
+    assert runs > 250
+
+
+def test_quadratic_stall_rule_ends_a_slowly_falling_floor():
+    """A rounding floor that still drifts down by 1% per layer: the plain
+    comparison e_k >= e_{k-2} never fires on it, the quadratic one fires as
+    soon as e_k is mostly floor (the exact part below a tenth of it), and
+    never while e_{k-2} is still large."""
+    w = np.concatenate([np.linspace(-2.0, -0.5, 40), np.linspace(0.5, 2.0, 60)])
+    _, rec = oracle.sp2_scalar(w, 40, -3.0, 3.0, tol=1e-12, max_iter=80, stop_rule=0)
+    floor = 2e-3 * 0.99 ** np.arange(len(rec.err))
+    errs = list(np.array(rec.err) + floor)
+    first = next(k for k in range(len(errs)) if rec.err[k] < 0.1 * floor[k])
+    fired = [k for k in range(2, len(errs))
+             if oracle.should_stop(k, errs, 0.0, 0.0, 1, oracle.STALL_GATE)]
+    assert fired and first <= fired[0] <= first + 2
+    assert all(rec.err[k - 2] < 1e-2 for k in fired)
+    assert not any(errs[k] >= errs[k - 2] for k in range(first, len(errs)))
+
+
 def test_vjp_of_nonsymmetric_weight_is_the_symmetric_gradient():
     """The gradient of Tr(W P) over symmetric perturbations of H is symmetric
     and depends on W only through sym(W)."""

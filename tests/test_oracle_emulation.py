@@ -81,6 +81,31 @@ def test_fp32_mode_is_the_plain_product():
     assert np.array_equal(got.astype(np.float64), x @ x)          # integer sums: exact
 
 
+@pytest.mark.parametrize("mode", emu.MODES)
+@pytest.mark.parametrize("abc", [(1.0, 0.0, 0.0), (-1.0, 2.0, 0.0), (1.5625, -0.625, 0.0625),
+                                 (-1.5625, 2.5, 0.0)])
+def test_centred_layer_is_the_exact_layer(mode, abc):
+    """An iterate with entries k/64 (|k| <= 32): its centred matrix S - I/2
+    is exact in every 16-bit format, every product of two entries is
+    exact and the sums stay far inside FP32, so the emulated layer (split
+    modes: square of the centred matrix plus the FP32 restoration) equals
+    the exact a S^2 + b S + c I for the plain layers and shifted ones
+    (coefficients with few bits).  A wrong restoration (b + a, c - a/4 as
+    other multiples of the centre) fails."""
+    a, b, c = abc
+    rng = np.random.default_rng(12)
+    s = _sym(rng.integers(-32, 33, (32, 32)).astype(np.float64)) / 64.0
+    s = np.triu(s) + np.triu(s, 1).T
+    exact = a * (s @ s) + b * s + c * np.eye(32)
+    got = emu.layer_emulated(s.astype(np.float32), mode, a, b, c)
+    assert got.dtype == np.float32
+    if mode == "bf16x1":        # one plane: the square of the rounded centred matrix
+        t = s - 0.5 * np.eye(32)
+        hi, _ = orc.split_bf16(t.astype(np.float32))
+        assert np.array_equal(hi.astype(np.float64), t)   # representable: no rounding
+    assert np.array_equal(got.astype(np.float64), exact)
+
+
 def test_unknown_mode_is_refused():
     with pytest.raises(ValueError):
         emu.square_emulated(np.eye(2, dtype=np.float32), "fp8")
@@ -168,7 +193,7 @@ def test_emulation_with_estimates_outside_the_spectrum_is_the_plain_network():
 
 @pytest.mark.parametrize("mode,bits", [("fp32", 24), ("fp16x3", 22), ("bf16x3", 16), ("bf16x1", 8)])
 def test_accelerated_emulated_error_follows_operand_precision(mode, bits):
-    """The accelerated network lands in the same band, [1/64, 2] of u times
+    """The accelerated network lands in the same band, [1/256, 2] of u times
     the Gershgorin width, with fewer layers."""
     for seed in (6, 7):
         h, q, e = random_orthogonal_hamiltonian(96, 48, seed=seed, return_factors=True)
@@ -180,7 +205,7 @@ def test_accelerated_emulated_error_follows_operand_precision(mode, bits):
         _, nl0 = emu.sp2_emulated(h, 48, mode, tol=1e-7)
         err = oracle.error_metrics(p, p_ref)["fro_over_sqrt_n"]
         scale = 2.0 ** -bits * (hi_b - lo_b)
-        assert scale / 64 < err < 2 * scale
+        assert scale / 256 < err < 2 * scale
         assert nl < nl0
 
 
@@ -188,9 +213,10 @@ def test_accelerated_emulated_error_follows_operand_precision(mode, bits):
 def test_emulated_error_follows_operand_precision(mode, bits):
     """Against the exact density matrix each mode lands near its operand
     roundoff ``u`` times the width of the Gershgorin interval (the inverse of
-    the mapped gap, the levels being at least 0.5 from mu): measured 0.05-0.55
-    of ``u * width`` for every mode.  A dropped lo term or a missing rescale
-    moves a mode by orders of magnitude."""
+    the mapped gap, the levels being at least 0.5 from mu): measured
+    0.007-0.55 of ``u * width`` for every mode (the centred planes of the
+    split modes keep them at the low end).  A dropped lo term or a missing
+    rescale moves a mode by orders of magnitude."""
     for seed in (6, 7):
         h = random_orthogonal_hamiltonian(96, 48, seed=seed).astype(np.float32)
         p_ref = oracle.density_matrix_eigh(h.astype(np.float64), 48)[0]
@@ -198,16 +224,20 @@ def test_emulated_error_follows_operand_precision(mode, bits):
         p, _ = emu.sp2_emulated(h, 48, mode, tol=1e-7)
         err = oracle.error_metrics(p, p_ref)["fro_over_sqrt_n"]
         scale = 2.0 ** -bits * (hi_b - lo_b)
-        assert scale / 64 < err < 2 * scale
+        assert scale / 256 < err < 2 * scale
 
 
 def test_single_pass_bf16_is_worse_than_the_pairs():
+    """Operand bits set the order: BF16 (8) far behind the BF16 pair (16),
+    which trails the FP16 pair (22); the last gap is narrower than 2^6
+    because the FP16 pair's error already sits near the FP32 accumulation
+    and storage level."""
     h = random_orthogonal_hamiltonian(96, 48, seed=7).astype(np.float32)
     p_ref = oracle.density_matrix_eigh(h.astype(np.float64), 48)[0]
     errs = {m: oracle.error_metrics(emu.sp2_emulated(h, 48, m)[0], p_ref)["fro_over_sqrt_n"]
             for m in ("bf16x1", "bf16x3", "fp16x3")}
     assert errs["bf16x1"] > 100 * errs["bf16x3"]
-    assert errs["bf16x3"] > 10 * errs["fp16x3"]
+    assert errs["bf16x3"] > 4 * errs["fp16x3"]
 
 
 # --------------------------------------------------------------------------
