@@ -3,15 +3,17 @@
 One step = one full ``sp2_density_ex`` call on a device-resident FP32
 Hamiltonian in the FP32-equivalent mode: Gershgorin discs tightened by 16
 Lanczos steps, the input layer, every SP2 layer as an FP16 hi/lo split
-product on MFMA (Eq. 20-22; FP64 trace-driven branch and stop decided on
-the device) and the McWeeny refinement in the same FP16 hi/lo arithmetic,
-ending with P in a caller buffer.  This mode meets the stated
-||P - P_ref||_F / sqrt(N) <= 1e-6 over every entry (an FP32 refinement
-does not: on this GPU its FP32 MFMA products round more coarsely than the
-FP16 pair).  The stop tolerance is 1e-3 on e_n = |Tr S - ||S||_F^2|: the
+product of the centred iterate S - I/2 on MFMA (Eq. 20-22; FP64
+trace-driven branch and stop decided on the device) and the McWeeny
+refinement in the same FP16 hi/lo arithmetic, ending with P in a caller
+buffer.  This mode meets the stated ||P - P_ref||_F / sqrt(N) <= 1e-6 over
+every entry with a margin (an FP32 refinement meets it too, closer to the
+bound: on this GPU its FP32 MFMA products round more coarsely than the FP16
+pair).  The stop tolerance is 2e-3 on e_n = |Tr S - ||S||_F^2|: the
 refinement maps an eigenvalue's deviation d from 0 or 1 to 3d^2 - 2d^3, so
-the layers that would drive e_n further down to its rounding floor only
-add rounding.
+what is left is at most 3 tol^2 / sqrt(N) = 1.5e-7 in ||P - P_ref||_F /
+sqrt(N), and the layers that would drive e_n further down to its rounding
+floor only add rounding.
 
 Workload: seeded tight-binding water box, 1024 molecules, N = 6144,
 n_occ = 4096, H in FP32 (synthetic stand-in for the paper's SCC-DFTB water).
@@ -63,17 +65,20 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="fp16x3", choices=list(PRODUCTS))
     ap.add_argument("--refine", default="split", choices=["none", "fp32", "split"])
-    ap.add_argument("--tol", type=float, default=1e-3,
+    ap.add_argument("--tol", type=float, default=2e-3,
                     help="stop tolerance on e_n = |Tr S - ||S||_F^2| (every configuration here "
                          "refines: one McWeeny step maps an eigenvalue's deviation d to "
-                         "3d^2 - 2d^3, so e_n < 1e-3 is as good as driving e_n to its floor)")
+                         "3d^2 - 2d^3, which leaves at most 3 tol^2 / sqrt(N) = 1.5e-7 in "
+                         "||P - P_ref||_F / sqrt(N) at N = 6144, 15%% of the 1e-6 budget)")
     ap.add_argument("--bound-steps", type=int, default=16,
                     help="Lanczos steps tightening the Gershgorin bounds (0: Gershgorin only)")
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the side legs in other arithmetics")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--est-steps", type=int, default=24,
-                    help="Lanczos steps per side of the HOMO/LUMO estimator (accelerated leg)")
+    ap.add_argument("--est-steps", type=int, default=8,
+                    help="Lanczos steps per side of the HOMO/LUMO estimator (accelerated leg and "
+                         "trajectory); on the water box 8 give the same accelerated layer count "
+                         "as 24 at a third of the cost")
     ap.add_argument("--no-accelerated", action="store_true",
                     help="skip the accelerated leg (HOMO/LUMO estimates from the previous solve)")
     ap.add_argument("--cpu-layers", type=int, default=4,
@@ -135,7 +140,7 @@ def measured_traffic(precision, profile=None, sources=KERNEL_SOURCES,
     return float(fields[key])
 
 
-def trajectory(steps, precision, refine, accelerate=False):
+def trajectory(steps, precision, refine, accelerate=False, est_steps=8):
     """Trajectory workload: water box of 2730 molecules zero-padded to
     N = 16384, n_occ = 10920; H(t) = H0 + fl32(a_t H_p), a_t = 0.01 sin(0.1 t),
     formed on the device; every step an independent split-precision solve,
@@ -178,7 +183,7 @@ def trajectory(steps, precision, refine, accelerate=False):
         fallbacks += info.fallback
         if accelerate and not last:
             ev0.record()
-            est = pk.sp2_homo_lumo(H, P, ws)
+            est = pk.sp2_homo_lumo(H, P, ws, steps=est_steps)
             ev1.record()
             torch.cuda.synchronize()
             est_times.append(ev0.elapsed_time(ev1))
@@ -223,6 +228,7 @@ def trajectory(steps, precision, refine, accelerate=False):
         "solve_ms_last_step_with_tape": float(tt[-1]),
         "accelerated": accelerate,
         "estimator_ms_mean": float(np.mean(est_times)) if est_times else None,
+        "estimator_steps": est_steps if accelerate else None,
         "ms_per_md_step_mean": float(tt[1:].mean() + np.mean(est_times)) if est_times else None,
         "fallbacks": fallbacks}), flush=True)
 
@@ -491,7 +497,8 @@ def main():
         copy_calibration()
         return
     if args.trajectory:
-        trajectory(args.trajectory, args.traj_precision, args.traj_refine, args.traj_accelerate)
+        trajectory(args.trajectory, args.traj_precision, args.traj_refine, args.traj_accelerate,
+                   args.est_steps)
         return
     import torch
 

@@ -129,22 +129,23 @@ def test_accelerated_fp32_equivalent_mode(setup):
 
 def test_benchmark_configuration(setup):
     """The benchmark's configuration: FP32-equivalent mode with the stop
-    tolerance 1e-3 (the McWeeny refinement that follows maps a deviation d
-    of an eigenvalue from 0 or 1 to 3d^2 - 2d^3, so e_n < 1e-3 leaves at
-    most ~3e-6 per eigenvalue, ~4e-8 in ||P - P_ref||_F / sqrt(N); the layers
+    tolerance 2e-3 (the McWeeny refinement that follows maps a deviation d
+    of an eigenvalue from 0 or 1 to 3d^2 - 2d^3, so e_n < 2e-3 leaves at
+    most 3 tol^2 / sqrt(N) = 1.5e-7 in ||P - P_ref||_F / sqrt(N); the layers
     that would drive e_n down to its rounding floor only add rounding),
-    plain and accelerated: every entry within the stated 1e-6, no more layers
+    plain and accelerated (estimates from 8 Lanczos steps per side, as the
+    benchmark takes them): every entry within the stated 1e-6, no more layers
     than with tol 1e-5 (where the stop rule ends at the rounding floor)."""
     import torch
     pk, gold, H, p_ref, w = setup
     n, n_occ = int(gold["n"]), int(gold["n_occ"])
-    banner(f"benchmark configuration water N={n} fp16x3 refine=split bound_steps=16 tol=1e-3")
+    banner(f"benchmark configuration water N={n} fp16x3 refine=split bound_steps=16 tol=2e-3")
     P5, info5 = pk.density(H, n_occ, precision="fp16x3", refine="split", bound_steps=16,
                            return_info=True)
-    P, info = pk.density(H, n_occ, precision="fp16x3", refine="split", bound_steps=16, tol=1e-3,
+    P, info = pk.density(H, n_occ, precision="fp16x3", refine="split", bound_steps=16, tol=2e-3,
                          return_info=True)
-    homo, lumo = pk.homo_lumo(H, P)
-    Pa, infoa = pk.density(H, n_occ, precision="fp16x3", refine="split", bound_steps=16, tol=1e-3,
+    homo, lumo = pk.homo_lumo(H, P, steps=8)
+    Pa, infoa = pk.density(H, n_occ, precision="fp16x3", refine="split", bound_steps=16, tol=2e-3,
                            homo=homo, lumo=lumo, return_info=True)
     for name, Q, inf in (("plain", P, info), ("accelerated", Pa, infoa)):
         d = Q.double().cpu().numpy() - p_ref
@@ -173,8 +174,8 @@ def test_single_pass_bf16_meets_its_bound(setup):
     3.9e-3)."""
     pk, gold, H, p_ref, w = setup
     n, n_occ = int(gold["n"]), int(gold["n_occ"])
-    banner(f"single-pass bf16 water N={n} refine=fp32 bound_steps=16 tol=1e-3")
-    P, info = pk.density(H, n_occ, precision="bf16x1", refine="fp32", bound_steps=16, tol=1e-3,
+    banner(f"single-pass bf16 water N={n} refine=fp32 bound_steps=16 tol=2e-3")
+    P, info = pk.density(H, n_occ, precision="bf16x1", refine="fp32", bound_steps=16, tol=2e-3,
                          return_info=True)
     d = P.double().cpu().numpy() - p_ref
     fro = float(np.linalg.norm(d)) / math.sqrt(n)
