@@ -610,7 +610,7 @@ def main():
         legs["bf16x3_gershgorin"] = leg("bf16x3", "fp32", 0, "BF16 pair, Gershgorin bounds")
         legs["bf16x3_lanczos"] = leg("bf16x3", "fp32", args.bound_steps,
                                      "BF16 pair, Lanczos bounds")
-        sp = leg("bf16x1", "fp32", args.bound_steps, "single-pass BF16")
+        sp = leg("bf16x1", "split", args.bound_steps, "single-pass BF16")
         sp["stated_tolerance"] = TOL_SINGLE_PASS_BF16
         sp["meets_tolerance"] = bool(sp["fro_over_sqrt_n"] <= TOL_SINGLE_PASS_BF16)
         if not sp["meets_tolerance"]:

@@ -165,7 +165,7 @@ def test_benchmark_configuration(setup):
 
 
 def test_single_pass_bf16_meets_its_bound(setup):
-    """Single-pass BF16 (one BF16 product per layer, FP32 refinement, 16
+    """Single-pass BF16 (one BF16 product per layer, FP16-pair refinement, 16
     Lanczos bound steps), as the benchmark's single-pass leg runs it: every
     entry of P within the stated 1e-3 of the diagonalisation.  The late
     layers round an iterate close to a projector to 8 significant bits;
@@ -174,8 +174,8 @@ def test_single_pass_bf16_meets_its_bound(setup):
     3.9e-3)."""
     pk, gold, H, p_ref, w = setup
     n, n_occ = int(gold["n"]), int(gold["n_occ"])
-    banner(f"single-pass bf16 water N={n} refine=fp32 bound_steps=16 tol=2e-3")
-    P, info = pk.density(H, n_occ, precision="bf16x1", refine="fp32", bound_steps=16, tol=2e-3,
+    banner(f"single-pass bf16 water N={n} refine=split bound_steps=16 tol=2e-3")
+    P, info = pk.density(H, n_occ, precision="bf16x1", refine="split", bound_steps=16, tol=2e-3,
                          return_info=True)
     d = P.double().cpu().numpy() - p_ref
     fro = float(np.linalg.norm(d)) / math.sqrt(n)
