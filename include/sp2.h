@@ -56,14 +56,21 @@ typedef enum {
  *   SP2_BF16X1 one bfloat16 product (X0 X0 only; single pass).
  *   SP2_BF16X3 X0 X0 + X0 X1 + X1 X0 with X0 = BF16[X], X1 = BF16[X - X0].
  *   SP2_FP16X3 the same with IEEE half on 2^14 X (exact power-of-two scale
- *              that keeps the residual X1 out of the half subnormal range). */
+ *              that keeps the residual X1 out of the half subnormal range).
+ * In the three split modes X is the centred iterate S - I/2 (FP32), and
+ * each layer restores S^2 = X^2 + S - I/4 in FP32: a S^2 + b S + c I is
+ * formed as a X^2 + (a + b) S + (c - a/4) I.  The centred matrix has far
+ * smaller entries than S near a projector, which shrinks both the FP32
+ * accumulation and the 16-bit rounding errors. */
 typedef enum { SP2_FP32 = 0, SP2_BF16X1 = 1, SP2_BF16X3 = 2, SP2_FP16X3 = 3 } sp2_precision;
 
 /* Refinement after the last layer: the McWeeny purification 3 S^2 - 2 S^3
  * (the refinement step that closes Section II.D).
  *   SP2_REFINE_NONE  no refinement.
  *   SP2_REFINE_FP32  both products in FP32 MFMA.
- *   SP2_REFINE_SPLIT both products in the FP16X3 split representation. */
+ *   SP2_REFINE_SPLIT both products in the FP16X3 split representation:
+ *                    Q = S^2 from the centred S - I/2, then
+ *                    P = -2 (S - I/2) Q + 2Q. */
 typedef enum { SP2_REFINE_NONE = 0, SP2_REFINE_FP32 = 1, SP2_REFINE_SPLIT = 2 } sp2_refine;
 
 #define SP2_MAX_ITER 256
@@ -285,8 +292,9 @@ sp2_status sp2_split(const float* X, int64_t n, int64_t ld, int32_t precision,
 /* One expansion layer (Eq. 19, Fig. 1): Y = X^2 (sign = +1) or
  * Y = 2X - X^2 (sign = -1) for a symmetric X, computed by the same
  * symmetric-output MFMA kernels (and arithmetic `precision`) as the solver's
- * layers.  X, Y: n x n, leading dimension ld, distinct buffers.  Blocks
- * until done. */
+ * layers; in the split modes the product is that of the centred X - I/2
+ * with the square restored as described for sp2_precision.  X, Y: n x n,
+ * leading dimension ld, distinct buffers.  Blocks until done. */
 sp2_status sp2_layer(const float* X, int64_t n, int64_t ld, int32_t precision, int32_t sign,
                      float* Y, void* workspace, size_t ws_bytes, void* stream);
 
