@@ -99,6 +99,7 @@ struct Layout {
   int init_blocks, gersh_blocks, max_parts;
   size_t off_ctrl, off_hist, off_meta, off_parts0, off_parts1, off_gersh, off_partial;
   size_t off_lz, off_lzvec, off_lzpart;   // Lanczos state, vectors, chunk partials
+  size_t off_lz1, off_lzvec1, off_lzpart1;   // the same for the estimator's second side
   int lz_blocks, lz_chunks;
   size_t off_slot0;     // first matrix slot
   size_t slot_bytes;
@@ -143,6 +144,10 @@ bool make_layout(int64_t n, const sp2_options& o, Layout& L) {
   // first-pass dot partials per matvec work-group, second-pass partials and
   // squared-norm partials per 256-row chunk, first-pass coefficients
   L.off_lzpart = take((size_t(L.lz_blocks + L.lz_chunks) * kLzCoef + size_t(L.lz_chunks) + kLzCoef) * 8);
+  // the HOMO/LUMO estimator runs its two sides together: a second set
+  L.off_lz1 = take(sizeof(LzState));
+  L.off_lzvec1 = take(size_t(kLzMaxSteps + 3) * size_t(n) * 8);
+  L.off_lzpart1 = take((size_t(L.lz_blocks + L.lz_chunks) * kLzCoef + size_t(L.lz_chunks) + kLzCoef) * 8);
   L.slot_bytes = size_t(L.np) * size_t(L.np) * 4;
   L.every = o.checkpoint_every;
   // slots 0-3: S (FP32), two hi/lo plane pairs (or FP32 ping-pong), S^2 for
@@ -167,6 +172,9 @@ struct WS {
   LzState* lz;
   double* lzv;      // Lanczos vectors v_0 .. v_kmax, then two w buffers: n doubles each
   double* lzpart;
+  LzState* lz1;     // the estimator's second side
+  double* lzv1;
+  double* lzpart1;
   float* slotf(int i) const { return reinterpret_cast<float*>(base + L.off_slot0 + L.slot_bytes * size_t(i)); }
   uint16_t* hi(int pair) const { return reinterpret_cast<uint16_t*>(slotf(1 + pair)); }
   uint16_t* lo(int pair) const { return hi(pair) + L.np * L.np; }
@@ -189,6 +197,9 @@ void bind(WS& w, void* ws, const Layout& L) {
   w.lz = reinterpret_cast<LzState*>(w.base + L.off_lz);
   w.lzv = reinterpret_cast<double*>(w.base + L.off_lzvec);
   w.lzpart = reinterpret_cast<double*>(w.base + L.off_lzpart);
+  w.lz1 = reinterpret_cast<LzState*>(w.base + L.off_lz1);
+  w.lzv1 = reinterpret_cast<double*>(w.base + L.off_lzvec1);
+  w.lzpart1 = reinterpret_cast<double*>(w.base + L.off_lzpart1);
 }
 
 // Lanczos tightening of the Gershgorin bounds already in ctrl (no host
@@ -1127,43 +1138,74 @@ sp2_status sp2_homo_lumo(const float* H, const float* P, int64_t n, int64_t ld, 
   LAUNCH_TRY();
   const int nb = L.lz_blocks, nc = L.lz_chunks;
   const int k = static_cast<int>(std::min<int64_t>(steps, n));
-  double* V = w.lzv;
-  double* wv = w.lzv + int64_t(kLzMaxSteps + 1) * n;   // w
-  double* yv = w.lzv + int64_t(kLzMaxSteps + 2) * n;   // (H - shift) v_j
-  double* p1 = w.lzpart;
-  double* p2 = p1 + size_t(nb) * kLzCoef;
-  double* pn = p2 + size_t(nc) * kLzCoef;
-  double* pc = pn + nc;
-  for (int side = 0; side < 2; ++side) {
-    const int qmode = side == 0 ? 1 : 2;   // Q = P, or I - P
-    // Gershgorin shifts read on the device: the kernels take them from ctrl
-    k_lz_start<<<1, kLzThreads, 0, st>>>(V, n, static_cast<uint64_t>(static_cast<uint32_t>(seed)), w.lz);
-    LAUNCH_TRY();
-    k_hl_matvec<<<nb, kLzMvThreads, 0, st>>>(P, n, ld, V, wv, qmode, 0.0, V, 0, nullptr, w.lz);
-    LAUNCH_TRY();
-    k_hl_norm_parts<<<nc, kLzChunk, 0, st>>>(wv, n, pn, w.lz);
-    LAUNCH_TRY();
-    k_hl_next<<<nc, kLzChunk, 0, st>>>(V, wv, n, 0, pn, nc, w.lz);
-    LAUNCH_TRY();
-    for (int j = 0; j < k; ++j) {
-      k_hl_shifted_matvec<<<nb, kLzMvThreads, 0, st>>>(H, n, ld, V + int64_t(j) * n, yv, side, w.ctrl,
-                                                       w.lz);
-      LAUNCH_TRY();
-      k_hl_matvec<<<nb, kLzMvThreads, 0, st>>>(P, n, ld, yv, wv, qmode, 0.0, V, j, p1, w.lz);
-      LAUNCH_TRY();
-      k_lz_coef<<<j + 1, kLzChunk, 0, st>>>(p1, nb, pc, w.lz);
-      LAUNCH_TRY();
-      k_lz_apply<<<nc, kLzChunk, 0, st>>>(V, wv, n, j, pc, nullptr, 0, p2, w.lz, 0);
-      LAUNCH_TRY();
-      k_lz_apply<<<nc, kLzChunk, 0, st>>>(V, wv, n, j, nullptr, p2, nc, pn, w.lz, 1);
-      LAUNCH_TRY();
-      k_hl_next<<<nc, kLzChunk, 0, st>>>(V, wv, n, j + 1, pn, nc, w.lz);
-      LAUNCH_TRY();
-    }
-    k_hl_ritz<<<1, kWave, 0, st>>>(w.lz, side);
+  // side 0: occupied (Q = P), side 1: virtual (Q = I - P); both run
+  // together, each matrix read once per step for the two (k_hl_matvec2)
+  LzState* lz[2] = {w.lz, w.lz1};
+  double *V[2], *wv[2], *yv[2], *p1[2], *p2[2], *pn[2], *pc[2];
+  double* lzv[2] = {w.lzv, w.lzv1};
+  double* lzp[2] = {w.lzpart, w.lzpart1};
+  for (int sd = 0; sd < 2; ++sd) {
+    V[sd] = lzv[sd];
+    wv[sd] = lzv[sd] + int64_t(kLzMaxSteps + 1) * n;   // w
+    yv[sd] = lzv[sd] + int64_t(kLzMaxSteps + 2) * n;   // (H - shift) v_j
+    p1[sd] = lzp[sd];
+    p2[sd] = p1[sd] + size_t(nb) * kLzCoef;
+    pn[sd] = p2[sd] + size_t(nc) * kLzCoef;
+    pc[sd] = pn[sd] + nc;
+  }
+  const uint64_t seed64 = static_cast<uint64_t>(static_cast<uint32_t>(seed));
+  for (int sd = 0; sd < 2; ++sd) {
+    k_lz_start<<<1, kLzThreads, 0, st>>>(V[sd], n, seed64, lz[sd]);
     LAUNCH_TRY();
   }
-  HIP_TRY(hipMemcpyAsync(hm->ritz, w.lz->ritz, sizeof(hm->ritz), hipMemcpyDeviceToHost, st));
+  HlTwo a;
+  memset(&a, 0, sizeof(a));
+  for (int sd = 0; sd < 2; ++sd) {
+    a.st[sd] = lz[sd];
+    a.x[sd] = V[sd];
+    a.out[sd] = wv[sd];
+    a.mode[sd] = sd == 0 ? 1 : 2;   // Q = P, or I - P
+  }
+  k_hl_matvec2<<<nb, kLzMvThreads, 0, st>>>(P, n, ld, a, w.ctrl, 0);
+  LAUNCH_TRY();
+  for (int sd = 0; sd < 2; ++sd) {
+    k_hl_norm_parts<<<nc, kLzChunk, 0, st>>>(wv[sd], n, pn[sd], lz[sd]);
+    LAUNCH_TRY();
+    k_hl_next<<<nc, kLzChunk, 0, st>>>(V[sd], wv[sd], n, 0, pn[sd], nc, lz[sd]);
+    LAUNCH_TRY();
+  }
+  for (int j = 0; j < k; ++j) {
+    HlTwo sh = a;   // y = (H - shift) v_j
+    HlTwo q = a;    // w = Q y with the first Gram-Schmidt partials
+    for (int sd = 0; sd < 2; ++sd) {
+      sh.x[sd] = V[sd] + int64_t(j) * n;
+      sh.out[sd] = yv[sd];
+      sh.mode[sd] = 0;
+      q.x[sd] = yv[sd];
+      q.V[sd] = V[sd];
+      q.dot_part[sd] = p1[sd];
+    }
+    k_hl_matvec2<<<nb, kLzMvThreads, 0, st>>>(H, n, ld, sh, w.ctrl, j);
+    LAUNCH_TRY();
+    k_hl_matvec2<<<nb, kLzMvThreads, 0, st>>>(P, n, ld, q, w.ctrl, j);
+    LAUNCH_TRY();
+    for (int sd = 0; sd < 2; ++sd) {
+      k_lz_coef<<<j + 1, kLzChunk, 0, st>>>(p1[sd], nb, pc[sd], lz[sd]);
+      LAUNCH_TRY();
+      k_lz_apply<<<nc, kLzChunk, 0, st>>>(V[sd], wv[sd], n, j, pc[sd], nullptr, 0, p2[sd], lz[sd], 0);
+      LAUNCH_TRY();
+      k_lz_apply<<<nc, kLzChunk, 0, st>>>(V[sd], wv[sd], n, j, nullptr, p2[sd], nc, pn[sd], lz[sd], 1);
+      LAUNCH_TRY();
+      k_hl_next<<<nc, kLzChunk, 0, st>>>(V[sd], wv[sd], n, j + 1, pn[sd], nc, lz[sd]);
+      LAUNCH_TRY();
+    }
+  }
+  for (int sd = 0; sd < 2; ++sd) {
+    k_hl_ritz<<<1, kWave, 0, st>>>(lz[sd], sd);
+    LAUNCH_TRY();
+  }
+  HIP_TRY(hipMemcpyAsync(hm->ritz, w.lz->ritz, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(hm->ritz + 2, w.lz1->ritz + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
   if (sp2_status s = read_back(w, hm, false, st)) return s;
   const Ctrl& c = hm->ctrl[0];
   if (c.nonfinite) return fail(SP2_ERR_NONFINITE, "H holds NaN or Inf");

@@ -153,6 +153,74 @@ __device__ __forceinline__ void rows_dot(const float* const (&mrow)[kLzRowsPerWa
   }
 }
 
+// rows_dot for two vectors x0, x1 at once (xs = 1): every matrix load
+// serves both; each vector's FMA chain runs in the same order as rows_dot's.
+__device__ __forceinline__ void rows_dot2(const float* const (&mrow)[kLzRowsPerWave],
+                                          const double* __restrict__ x0,
+                                          const double* __restrict__ x1, int64_t n, int64_t ld,
+                                          bool vec, int lane, double (&acc0)[kLzRowsPerWave],
+                                          double (&acc1)[kLzRowsPerWave]) {
+  constexpr int U = 4, R = kLzRowsPerWave;
+  int64_t c_done = 0;
+  if (vec) {
+    const int64_t n4 = n & ~int64_t(3);
+    int64_t c = 4 * lane;
+    for (; c + (U - 1) * 4 * kWave < n4; c += U * 4 * kWave) {
+      f32x4 h[U][R];
+      double xa[U][4], xb[U][4];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr)
+          h[u][rr] = *reinterpret_cast<const f32x4*>(mrow[rr] + c + u * 4 * kWave);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          xa[u][e] = x0[c + u * 4 * kWave + e];
+          xb[u][e] = x1[c + u * 4 * kWave + e];
+        }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const double hv = static_cast<double>(h[u][rr][e]);
+            acc0[rr] = fma(hv, xa[u][e] * 1.0, acc0[rr]);
+            acc1[rr] = fma(hv, xb[u][e] * 1.0, acc1[rr]);
+          }
+    }
+    for (; c < n4; c += 4 * kWave) {
+      double xa[4], xb[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        xa[e] = x0[c + e] * 1.0;
+        xb[e] = x1[c + e] * 1.0;
+      }
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr) {
+        const f32x4 h = *reinterpret_cast<const f32x4*>(mrow[rr] + c);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          acc0[rr] = fma(static_cast<double>(h[e]), xa[e], acc0[rr]);
+          acc1[rr] = fma(static_cast<double>(h[e]), xb[e], acc1[rr]);
+        }
+      }
+    }
+    c_done = n4;
+  }
+  for (int64_t c = c_done + lane; c < n; c += kWave) {
+    const double xa = x0[c] * 1.0, xb = x1[c] * 1.0;
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr) {
+      acc0[rr] = fma(static_cast<double>(mrow[rr][c]), xa, acc0[rr]);
+      acc1[rr] = fma(static_cast<double>(mrow[rr][c]), xb, acc1[rr]);
+    }
+  }
+}
+
 // V_0 = u / |u|, u_i = (z_i >> 11) 2^-53 - 1/2; state reset.  V holds the
 // Lanczos vectors as consecutive rows of n doubles.
 __global__ __launch_bounds__(kLzThreads) void k_lz_start(double* __restrict__ V, int64_t n,
@@ -513,83 +581,86 @@ __global__ __launch_bounds__(2 * kWave) void k_lz_bounds(LzState* st, Ctrl* ctrl
 // side), started from Q u / |Q u|.  For a projector commuting with H the
 // vectors stay in the range of Q, where the operator is H - shift I on the
 // occupied (virtual) eigenstates; the shift (eps_min, resp. eps_max) keeps
-// the zero eigenvalue of the complement on the inner side.  Each step:
-// y = (H - shift) v_j (k_hl_matvec, mode 0), w = Q y with the first
-// Gram-Schmidt dot partials (mode 1 or 2), the two Gram-Schmidt passes of
-// the bound refinement (k_lz_coef, k_lz_apply), then v_{j+1} = w / |w|
-// (k_hl_next).
+// the zero eigenvalue of the complement on the inner side.  The two sides
+// run together.  Each step: y = (H - shift) v_j (k_hl_matvec2, mode 0),
+// w = Q y with the first Gram-Schmidt dot partials (mode 1 or 2), the two
+// Gram-Schmidt passes of the bound refinement (k_lz_coef, k_lz_apply), then
+// v_{j+1} = w / |w| (k_hl_next).
 // ---------------------------------------------------------------------------
 
-// out = M x (mode 0: minus shift * x; mode 1: as is; mode 2: x - M x), M an
-// FP32 n x n matrix (leading dimension ld), FP64 vectors, 2 rows per wave.
-// With dot_part (modes 1, 2): partial dots of out with V rows 0 .. j per
-// work-group, dot_part[block * kLzCoef + i].
-__device__ __forceinline__ void k_hl_matvec_body(const float* __restrict__ M, int64_t n, int64_t ld,
-                                                 const double* __restrict__ x,
-                                                 double* __restrict__ out, int mode, double shift,
-                                                 const double* __restrict__ V, int j,
-                                                 double* __restrict__ dot_part, const LzState* st) {
-  __shared__ double dred[kLzMvThreads / kWave][kWave];
-  if (st->broke) return;
+// The two sides of the estimator at once: out_s = M x_s (mode 0: minus
+// shift_s x_s, the shifts eps_min (side 0) and eps_max (side 1) from ctrl;
+// mode 1: as is; mode 2: x_s - M x_s) for s = 0, 1, reading M once for
+// both; with V_s (rows 0 .. j) and dot_part_s, the partial dots of out_s
+// with those rows per work-group (FP32 M, FP64 vectors and sums, 2 rows
+// per wave as in k_lz_matvec).  A side whose recurrence broke down is
+// skipped.
+struct HlTwo {
+  const double* x[2];
+  double* out[2];
+  const double* V[2];       // null: no dot partials
+  double* dot_part[2];
+  const LzState* st[2];
+  int mode[2];
+};
+
+__global__ __launch_bounds__(kLzMvThreads) void k_hl_matvec2(const float* __restrict__ M, int64_t n,
+                                                    int64_t ld, HlTwo a, const Ctrl* ctrl, int j) {
+  __shared__ double dred[2][kLzMvThreads / kWave][kWave];
+  const bool live[2] = {!a.st[0]->broke, !a.st[1]->broke};
+  if (!live[0] && !live[1]) return;
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int64_t r0 = int64_t(blockIdx.x) * kLzRowsPerBlock + wv * kLzRowsPerWave;
-  double acc[kLzRowsPerWave];
+  double acc[2][kLzRowsPerWave];
   const float* mrow[kLzRowsPerWave];
-  // rows past n read row 0 instead (in bounds; their sums are discarded)
 #pragma unroll
   for (int rr = 0; rr < kLzRowsPerWave; ++rr) {
-    acc[rr] = 0.0;
+    acc[0][rr] = 0.0;
+    acc[1][rr] = 0.0;
     mrow[rr] = M + (r0 + rr < n ? r0 + rr : 0) * ld;
   }
   const bool vec = (ld % 4 == 0) && ((reinterpret_cast<uintptr_t>(M) & 15) == 0);
-  rows_dot(mrow, x, 1.0, n, ld, vec, lane, acc);
-  double ws[kLzRowsPerWave];
+  rows_dot2(mrow, a.x[0], a.x[1], n, ld, vec, lane, acc[0], acc[1]);
+  const double shift[2] = {ctrl->eps_min, ctrl->eps_max};
+  double ws[2][kLzRowsPerWave];
 #pragma unroll
-  for (int rr = 0; rr < kLzRowsPerWave; ++rr) {
-    const double sum = wave_sum(acc[rr]);
-    const int64_t row = r0 + rr;
-    double v = 0.0;
-    if (row < n) v = mode == 0 ? sum - shift * x[row] : (mode == 1 ? sum : x[row] - sum);
-    ws[rr] = v;
-    if (lane == 0 && row < n) out[row] = v;
-  }
-  if (!dot_part) return;
-  double d = 0.0;
-  if (lane <= j) {
+  for (int sd = 0; sd < 2; ++sd)
 #pragma unroll
     for (int rr = 0; rr < kLzRowsPerWave; ++rr) {
+      const double sum = wave_sum(acc[sd][rr]);
       const int64_t row = r0 + rr;
-      if (row < n) d = fma(V[int64_t(lane) * n + row], ws[rr], d);
+      const int mode = a.mode[sd];
+      double v = 0.0;
+      if (row < n)
+        v = mode == 0 ? sum - shift[sd] * a.x[sd][row] : (mode == 1 ? sum : a.x[sd][row] - sum);
+      ws[sd][rr] = v;
+      if (live[sd] && lane == 0 && row < n) a.out[sd][row] = v;
     }
+  if (!a.V[0]) return;
+#pragma unroll
+  for (int sd = 0; sd < 2; ++sd) {
+    double d = 0.0;
+    if (lane <= j) {
+#pragma unroll
+      for (int rr = 0; rr < kLzRowsPerWave; ++rr) {
+        const int64_t row = r0 + rr;
+        if (row < n) d = fma(a.V[sd][int64_t(lane) * n + row], ws[sd][rr], d);
+      }
+    }
+    dred[sd][wv][lane] = d;
   }
-  dred[wv][lane] = d;
   __syncthreads();
   if (threadIdx.x <= j) {
-    double t = 0.0;
 #pragma unroll
-    for (int q = 0; q < kLzMvThreads / kWave; ++q) t += dred[q][threadIdx.x];
-    dot_part[int64_t(blockIdx.x) * kLzCoef + threadIdx.x] = t;
+    for (int sd = 0; sd < 2; ++sd) {
+      if (!live[sd]) continue;
+      double t = 0.0;
+#pragma unroll
+      for (int q = 0; q < kLzMvThreads / kWave; ++q) t += dred[sd][q][threadIdx.x];
+      a.dot_part[sd][int64_t(blockIdx.x) * kLzCoef + threadIdx.x] = t;
+    }
   }
-}
-
-__global__ __launch_bounds__(kLzMvThreads) void k_hl_matvec(const float* __restrict__ M, int64_t n,
-                                                   int64_t ld, const double* __restrict__ x,
-                                                   double* __restrict__ out, int mode, double shift,
-                                                   const double* __restrict__ V, int j,
-                                                   double* __restrict__ dot_part, const LzState* st) {
-  k_hl_matvec_body(M, n, ld, x, out, mode, shift, V, j, dot_part, st);
-}
-
-// y = (H - shift I) v with shift = eps_min (side 0) or eps_max (side 1)
-// from the control block (the spectral bounds of H).
-__global__ __launch_bounds__(kLzMvThreads) void k_hl_shifted_matvec(const float* __restrict__ H,
-                                                           int64_t n, int64_t ld,
-                                                           const double* __restrict__ v,
-                                                           double* __restrict__ y, int side,
-                                                           const Ctrl* ctrl, const LzState* st) {
-  const double shift = side == 0 ? ctrl->eps_min : ctrl->eps_max;
-  k_hl_matvec_body(H, n, ld, v, y, 0, shift, nullptr, 0, nullptr, st);
 }
 
 // Squared-norm partials of w per chunk of 256 rows.

@@ -58,8 +58,9 @@ def test_workspace_bytes(lib):
     n = 6144
     b = _lib.sp2_workspace_bytes(n, o)
     assert b >= 4 * n * n * 4                   # four padded FP32 slots
-    # + split-K partial accumulators and 66 Lanczos vectors of n doubles
-    assert b < 4 * n * n * 4 + (65 << 20) + 66 * n * 8 + (1 << 20)
+    # + split-K partial accumulators and two sets (the estimator's two sides)
+    # of 67 Lanczos vectors of n doubles
+    assert b < 4 * n * n * 4 + (65 << 20) + 2 * 67 * n * 8 + (1 << 20)
     o.checkpoint_every = 4
     bt = _lib.sp2_workspace_bytes(n, o)
     assert bt - b == (4 + 4 + 100 // 4 + 1) * n * n * 4
