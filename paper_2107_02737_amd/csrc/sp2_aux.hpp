@@ -121,7 +121,8 @@ constexpr int kEwThreads = 256;
 
 // Input layer (Section II.D): S_0 = (eps_max I - H) / (eps_max - eps_min),
 // computed in FP64 per entry and rounded once to FP32, zero on the padding;
-// also its hi/lo planes (split: 1 bf16, 2 fp16 scaled) and FP64 partials of
+// also the hi/lo planes of S_0 - centre I (split: 1 bf16, 2 fp16 scaled;
+// the centre taken off the real diagonal) and FP64 partials of
 // Tr S_0 and ||S_0||_F^2 per work-group.  Work-groups stride over tiles of
 // 32 rows x 256 columns: the tile is read and S_0 written a row at a time
 // (1 KB per wave access), then the tile, staged in LDS, is written as planes

@@ -1485,7 +1485,8 @@ sp2_status refine_derivative_split(const WS& w, int ps, int qd, const float* S32
 }
 
 // Bring checkpoint `slot` into the forward buffers as iterate S_c (FP32 at
-// dst, hi/lo planes in pair 0 for the split precisions).
+// dst, the centred hi/lo planes of S_c - I/2 in pair 0 for the split
+// precisions).
 sp2_status load_checkpoint(const WS& w, int prec, int slot, float* dst, hipStream_t st) {
   HIP_TRY(hipMemcpyAsync(dst, w.tape(slot), w.L.slot_bytes, hipMemcpyDeviceToDevice, st));
   if (prec != SP2_FP32) {
@@ -1623,7 +1624,7 @@ sp2_status sp2_vjp(void* workspace, size_t ws_bytes, const float* W, int64_t ld,
         return s;
     for (int nn = e - 1; nn >= c; --nn) {
       if (sd) {
-        // planes of S_nn into pair 0 (the recomputation has moved on)
+        // centred planes of S_nn into pair 0 (the recomputation has moved on)
         k_split_tiled<<<L.init_blocks, kEwThreads, 0, st>>>(w.seg(nn - c), L.np, L.np, L.np, w.hi(0),
                                                             w.lo(0), split_code_of(SP2_BF16X3),
                                                             kPlaneCentre, L.n);

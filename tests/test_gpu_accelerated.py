@@ -191,6 +191,54 @@ def test_derivatives_of_the_accelerated_network(pk, c1):
     assert lhs == pytest.approx(rhs, rel=1e-4)
 
 
+def test_split_derivatives_of_the_accelerated_network(pk, c1):
+    """The same with BF16x3 layers and split derivatives (SP2_FLAG_SPLIT_
+    DERIVATIVES): the replayed scheduled layers, the derivative maps and the
+    refinement's derivative all run on the centred planes of the iterates
+    with their correction terms.  Against the oracle's derivatives of its
+    FP64 accelerated network and perturbation theory, within the BF16x3
+    tolerance of the plain network's split derivatives (1e-3), dot test
+    between JVP and VJP."""
+    import torch
+    h32, n_occ, _, w = c1
+    homo, lumo = w[n_occ - 1] + 0.01, w[n_occ] - 0.01
+    banner("accelerated JVP/VJP c1 bf16x3 split derivatives")
+    H = to_dev(h32)
+    P, info = pk.density(H, n_occ, precision="bf16x3", refine="fp32", homo=homo, lumo=lumo,
+                         checkpoint_every=3, split_derivatives=True, return_info=True)
+    nl = info["n_iter"]
+    assert info["converged"] and not info["fallback"]
+    h1 = symmetric_normal(256, 2, std=1e-3).astype(np.float32)
+    wm = symmetric_normal(256, 1).astype(np.float32)
+    P1 = torch.empty_like(H)
+    G = torch.empty_like(H)
+    pk.sp2_jvp(info["workspace"], to_dev(h1), P1)
+    pk.sp2_vjp(info["workspace"], to_dev(wm), G)
+    lo, hi, coefs = _oracle_schedule(h32, homo, lumo)
+    h64 = h32.astype(np.float64)
+    hist = pk.sp2_history(info["workspace"])
+    # the scheduled layers are the oracle's; the network differentiated is
+    # the one the GPU recorded (its trace-driven signs after the schedule)
+    for k in range(min(nl, len(coefs))):
+        np.testing.assert_allclose(hist["coef"][k], coefs[k], rtol=1e-12, atol=1e-14)
+    rec = oracle.SP2Record(eps_min=info["eps_min"], eps_max=info["eps_max"], refine=True,
+                           branches=[1 if c[0] > 0 else -1 for c in hist["coef"][:nl]],
+                           coefs=[tuple(c) for c in hist["coef"][:nl]])
+    j_ref = oracle.sp2_jvp(h64, h1.astype(np.float64), rec)
+    g_ref = oracle.sp2_vjp(h64, wm.astype(np.float64), rec)
+    j, g = to_host(P1), to_host(G)
+    rel_j = np.linalg.norm(j - j_ref) / np.linalg.norm(j_ref)
+    rel_g = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    dm = oracle.dmpt_response(h64, n_occ, h1.astype(np.float64))
+    rel_dm = np.linalg.norm(j - dm) / np.linalg.norm(dm)
+    print(f"  n_iter={nl} jvp {rel_j:.2e} vjp {rel_g:.2e} vs DMPT {rel_dm:.2e}", flush=True)
+    assert rel_j < 1e-3 and rel_g < 1e-3
+    assert rel_dm < 2e-3
+    lhs = float(np.sum(wm.astype(np.float64) * j))
+    rhs = float(np.sum(g * h1.astype(np.float64)))
+    assert lhs == pytest.approx(rhs, rel=1e-3)
+
+
 @pytest.mark.parametrize("m,steps", [(170, 24), (64, 16)])
 def test_homo_lumo_estimator_matches_the_oracle(pk, m, steps):
     """sp2_homo_lumo on the FP32 H and the FP32 cast of the exact P against
