@@ -327,31 +327,62 @@ __global__ __launch_bounds__(kEwThreads) void k_copy_scaled(const float* __restr
 }
 
 // Y = X with the strict lower triangle taken from the upper one
-// (Y_ij = X_ji for i > j), np x np with leading dimension np; Y may be X
-// (then only the lower triangle is written).  64 x 64 blocks, transposed
-// through LDS so that both the reads and the writes are row-contiguous.
+// (Y_ij = X_ji for i > j), np x np with leading dimension np (a multiple of
+// 64, rows 16-byte aligned); Y may be X.  64 x 64 blocks, transposed through
+// LDS so that both the reads and the writes are row-contiguous; every thread
+// moves 16 floats as four 16-byte loads, all issued before the first store.
+// lower_only (for Y = X): the grid holds only the nb (nb + 1) / 2 blocks on
+// or below the diagonal, block b = bi (bi + 1) / 2 + bj; otherwise all
+// nb^2 blocks, the upper ones copied.
 constexpr int kMirrorTile = 64;
-__global__ __launch_bounds__(256) void k_mirror_upper(const float* X,
-                                                      float* Y, int64_t np) {
+__global__ __launch_bounds__(256) void k_mirror_upper(const float* X, float* Y, int64_t np,
+                                                      int lower_only) {
   __shared__ float t[kMirrorTile][kMirrorTile + 1];
   const int nb = static_cast<int>(np / kMirrorTile);
-  const int bi = blockIdx.x / nb, bj = blockIdx.x % nb;   // output block (bi, bj)
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 columns x 4 rows per pass
+  int bi, bj;   // output block (bi, bj)
+  if (lower_only) {
+    const int b = blockIdx.x;
+    bi = static_cast<int>((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
+    while (bi * (bi + 1) / 2 > b) --bi;
+    while ((bi + 1) * (bi + 2) / 2 <= b) ++bi;
+    bj = b - bi * (bi + 1) / 2;
+  } else {
+    bi = blockIdx.x / nb;
+    bj = blockIdx.x % nb;
+  }
+  const int cq = (threadIdx.x & 15) * 4, rq = threadIdx.x >> 4;   // 16 x float4 columns, 16 rows
   const int64_t r0 = int64_t(bi) * kMirrorTile, c0 = int64_t(bj) * kMirrorTile;
-  if (bi < bj) {   // upper block: plain copy
-    if (X != Y)
-      for (int r = ty; r < kMirrorTile; r += 4) Y[(r0 + r) * np + c0 + tx] = X[(r0 + r) * np + c0 + tx];
+  f32x4 v[4];
+  if (bi < bj) {   // upper block (Y != X only): plain copy
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      v[k] = *reinterpret_cast<const f32x4*>(X + (r0 + rq + 16 * k) * np + c0 + cq);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      *reinterpret_cast<f32x4*>(Y + (r0 + rq + 16 * k) * np + c0 + cq) = v[k];
     return;
   }
-  // source block (bj, bi) of the upper triangle, transposed
-  for (int r = ty; r < kMirrorTile; r += 4) t[r][tx] = X[(c0 + r) * np + r0 + tx];
+  // source block (bj, bi) of the upper triangle: t[r][c] = X[c0 + r][r0 + c]
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    v[k] = *reinterpret_cast<const f32x4*>(X + (c0 + rq + 16 * k) * np + r0 + cq);
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) t[rq + 16 * k][cq + e] = v[k][e];
   __syncthreads();
-  for (int r = ty; r < kMirrorTile; r += 4) {
-    const int64_t i = r0 + r, j = c0 + tx;
-    if (i > j)
-      Y[i * np + j] = t[tx][r];
-    else if (X != Y)
-      Y[i * np + j] = X[i * np + j];
+  // Y[r0 + r][c0 + c] = X[c0 + c][r0 + r] = t[c][r]; on a diagonal block the
+  // elements on or above the diagonal keep X[r0 + r][r0 + c] = t[r][c]
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int r = rq + 16 * k;
+    f32x4 o;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int c = cq + e;
+      o[e] = (bi > bj || r > c) ? t[c][r] : t[r][c];
+    }
+    *reinterpret_cast<f32x4*>(Y + (r0 + r) * np + c0 + cq) = o;
   }
 }
 

@@ -559,7 +559,9 @@ sp2_status launch_layer(const WS& w, int precision, int n, int mode, const float
 // Complete an FP32 iterate that split layers left upper-triangle-only.
 sp2_status mirror_upper(const WS& w, const float* X, float* Y, hipStream_t st) {
   const int nb = static_cast<int>(w.L.np / kMirrorTile);
-  k_mirror_upper<<<nb * nb, 256, 0, st>>>(X, Y, w.L.np);
+  const bool in_place = X == Y;
+  k_mirror_upper<<<in_place ? nb * (nb + 1) / 2 : nb * nb, 256, 0, st>>>(X, Y, w.L.np,
+                                                                       in_place ? 1 : 0);
   LAUNCH_TRY();
   return SP2_OK;
 }
