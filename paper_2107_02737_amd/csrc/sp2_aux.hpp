@@ -11,7 +11,12 @@ constexpr int kRowThreads = 256;     // threads per Gershgorin block
 constexpr int kRowsPerBlock = 4;     // one wave per row
 
 // Per-row Gershgorin discs in FP64 for rows [0, n) of H: block b writes
-// (min_i lower, max_i upper, any non-finite) over its rows.
+// (min_i lower, max_i upper, any non-finite) over its rows.  A wave sums
+// |H_ij| over its whole row, diagonal included, and takes |H_ii| off at
+// the end: the loop is a convert and an add per element, with four 16-byte
+// loads per lane issued before any of them is used.  A NaN or Inf anywhere
+// in the row makes the sum non-finite (an FP64 sum of FP32 magnitudes
+// cannot overflow: it would take more than 2^890 terms), which is the flag.
 __global__ __launch_bounds__(kRowThreads) void k_gershgorin_rows(const float* __restrict__ H,
                                                                  int64_t n, int64_t ld,
                                                                  double* __restrict__ part) {
@@ -22,34 +27,40 @@ __global__ __launch_bounds__(kRowThreads) void k_gershgorin_rows(const float* __
   double lo = INFINITY, hi = -INFINITY, bad = 0.0;
   if (row < n) {
     const float* r = H + row * ld;
-    double s = 0.0, s1 = 0.0;   // two chains: loads stay in flight
-    bool finite = true;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     int64_t j0 = 0;
     if ((ld % 4 == 0) && ((reinterpret_cast<uintptr_t>(H) & 15) == 0)) {
+      constexpr int U = 4;
       const int64_t n4 = n & ~int64_t(3);
-#pragma unroll 2
-      for (int64_t c = 4 * lane; c < n4; c += 4 * kWave) {
-        const f32x4 v = *reinterpret_cast<const f32x4*>(r + c);
+      int64_t c = 4 * lane;
+      for (; c + 4 * kWave * (U - 1) < n4; c += 4 * kWave * U) {
+        f32x4 v[U];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          finite = finite && isfinite(v[e]);
-          const double a = c + e != row ? fabs(static_cast<double>(v[e])) : 0.0;
-          if (e & 1) s1 += a; else s += a;
+        for (int u = 0; u < U; ++u) v[u] = *reinterpret_cast<const f32x4*>(r + c + 4 * kWave * u);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          s0 += fabs(static_cast<double>(v[u][0]));
+          s1 += fabs(static_cast<double>(v[u][1]));
+          s2 += fabs(static_cast<double>(v[u][2]));
+          s3 += fabs(static_cast<double>(v[u][3]));
         }
+      }
+      for (; c < n4; c += 4 * kWave) {
+        const f32x4 v = *reinterpret_cast<const f32x4*>(r + c);
+        s0 += fabs(static_cast<double>(v[0]));
+        s1 += fabs(static_cast<double>(v[1]));
+        s2 += fabs(static_cast<double>(v[2]));
+        s3 += fabs(static_cast<double>(v[3]));
       }
       j0 = n4;
     }
-    for (int64_t j = j0 + lane; j < n; j += kWave) {
-      const float v = r[j];
-      finite = finite && isfinite(v);
-      if (j != row) s += fabs(static_cast<double>(v));
-    }
-    s = wave_sum(s + s1);
-    const double fin = wave_min(finite ? 1.0 : 0.0);
+    for (int64_t j = j0 + lane; j < n; j += kWave) s0 += fabs(static_cast<double>(r[j]));
+    const double s = wave_sum((s0 + s1) + (s2 + s3));
     const double d = static_cast<double>(r[row]);
-    lo = d - s;
-    hi = d + s;
-    bad = (fin == 0.0 || !isfinite(s) || !isfinite(d)) ? 1.0 : 0.0;
+    const double off = s - fabs(d);
+    lo = d - off;
+    hi = d + off;
+    bad = !isfinite(s) ? 1.0 : 0.0;
   }
   if (lane == 0) {
     red[w] = lo;
