@@ -1141,7 +1141,8 @@ sp2_status sp2_homo_lumo(const float* H, const float* P, int64_t n, int64_t ld, 
   const int nb = L.lz_blocks, nc = L.lz_chunks;
   const int k = static_cast<int>(std::min<int64_t>(steps, n));
   // side 0: occupied (Q = P), side 1: virtual (Q = I - P); both run
-  // together, each matrix read once per step for the two (k_hl_matvec2)
+  // together: each matrix is read once per step for the two (k_hl_matvec2)
+  // and their vector steps share launches (k_hl_*2, side = blockIdx.y)
   LzState* lz[2] = {w.lz, w.lz1};
   double *V[2], *wv[2], *yv[2], *p1[2], *p2[2], *pn[2], *pc[2];
   double* lzv[2] = {w.lzv, w.lzv1};
@@ -1168,14 +1169,22 @@ sp2_status sp2_homo_lumo(const float* H, const float* P, int64_t n, int64_t ld, 
     a.out[sd] = wv[sd];
     a.mode[sd] = sd == 0 ? 1 : 2;   // Q = P, or I - P
   }
+  HlVecs vs;
+  for (int sd = 0; sd < 2; ++sd) {
+    vs.V[sd] = V[sd];
+    vs.w[sd] = wv[sd];
+    vs.p1[sd] = p1[sd];
+    vs.p2[sd] = p2[sd];
+    vs.pn[sd] = pn[sd];
+    vs.pc[sd] = pc[sd];
+    vs.st[sd] = lz[sd];
+  }
   k_hl_matvec2<<<nb, kLzMvThreads, 0, st>>>(P, n, ld, a, w.ctrl, 0);
   LAUNCH_TRY();
-  for (int sd = 0; sd < 2; ++sd) {
-    k_hl_norm_parts<<<nc, kLzChunk, 0, st>>>(wv[sd], n, pn[sd], lz[sd]);
-    LAUNCH_TRY();
-    k_hl_next<<<nc, kLzChunk, 0, st>>>(V[sd], wv[sd], n, 0, pn[sd], nc, lz[sd]);
-    LAUNCH_TRY();
-  }
+  k_hl_norm_parts2<<<dim3(nc, 2), kLzChunk, 0, st>>>(vs, n);
+  LAUNCH_TRY();
+  k_hl_next2<<<dim3(nc, 2), kLzChunk, 0, st>>>(vs, n, 0, nc);
+  LAUNCH_TRY();
   for (int j = 0; j < k; ++j) {
     HlTwo sh = a;   // y = (H - shift) v_j
     HlTwo q = a;    // w = Q y with the first Gram-Schmidt partials
@@ -1191,16 +1200,14 @@ sp2_status sp2_homo_lumo(const float* H, const float* P, int64_t n, int64_t ld, 
     LAUNCH_TRY();
     k_hl_matvec2<<<nb, kLzMvThreads, 0, st>>>(P, n, ld, q, w.ctrl, j);
     LAUNCH_TRY();
-    for (int sd = 0; sd < 2; ++sd) {
-      k_lz_coef<<<j + 1, kLzChunk, 0, st>>>(p1[sd], nb, pc[sd], lz[sd]);
-      LAUNCH_TRY();
-      k_lz_apply<<<nc, kLzChunk, 0, st>>>(V[sd], wv[sd], n, j, pc[sd], nullptr, 0, p2[sd], lz[sd], 0);
-      LAUNCH_TRY();
-      k_lz_apply<<<nc, kLzChunk, 0, st>>>(V[sd], wv[sd], n, j, nullptr, p2[sd], nc, pn[sd], lz[sd], 1);
-      LAUNCH_TRY();
-      k_hl_next<<<nc, kLzChunk, 0, st>>>(V[sd], wv[sd], n, j + 1, pn[sd], nc, lz[sd]);
-      LAUNCH_TRY();
-    }
+    k_hl_coef2<<<dim3(j + 1, 2), kLzChunk, 0, st>>>(vs, nb);
+    LAUNCH_TRY();
+    k_hl_apply2<<<dim3(nc, 2), kLzChunk, 0, st>>>(vs, n, j, nc, 0);
+    LAUNCH_TRY();
+    k_hl_apply2<<<dim3(nc, 2), kLzChunk, 0, st>>>(vs, n, j, nc, 1);
+    LAUNCH_TRY();
+    k_hl_next2<<<dim3(nc, 2), kLzChunk, 0, st>>>(vs, n, j + 1, nc);
+    LAUNCH_TRY();
   }
   for (int sd = 0; sd < 2; ++sd) {
     k_hl_ritz<<<1, kWave, 0, st>>>(lz[sd], sd);

@@ -356,9 +356,8 @@ __device__ __forceinline__ void chunk_dots(const double* V, double wr, int64_t r
 // Coefficient i = blockIdx.x of a Gram-Schmidt pass from many partials
 // (one per matrix-vector work-group): thread t adds partials t, t + 256, ...
 // in turn, then a fixed-order tree over the work-group.
-__global__ __launch_bounds__(kLzChunk) void k_lz_coef(const double* __restrict__ part, int nparts,
-                                                      double* __restrict__ coef,
-                                                      const LzState* st) {
+__device__ __forceinline__ void lz_coef_body(const double* __restrict__ part, int nparts,
+                                             double* __restrict__ coef, const LzState* st) {
   __shared__ double red[kLzChunk / kWave];
   if (st->broke) return;
   const int i = blockIdx.x;
@@ -368,17 +367,21 @@ __global__ __launch_bounds__(kLzChunk) void k_lz_coef(const double* __restrict__
   if (threadIdx.x == 0) coef[i] = s;
 }
 
+__global__ __launch_bounds__(kLzChunk) void k_lz_coef(const double* __restrict__ part, int nparts,
+                                                      double* __restrict__ coef,
+                                                      const LzState* st) {
+  lz_coef_body(part, nparts, coef, st);
+}
+
 // A Gram-Schmidt update: c from coef_in (the first pass, reduced by
 // k_lz_coef) or summed here from the chunk partials part_in (the second
 // pass), w -= V c on this chunk; then either the partial dots of the second
 // pass (last = 0; block 0 records alpha_j = c_j of the first pass) or the
 // partial |w|^2 (last = 1).
-__global__ __launch_bounds__(kLzChunk) void k_lz_apply(const double* __restrict__ V,
-                                                       double* __restrict__ w, int64_t n, int j,
-                                                       const double* __restrict__ coef_in,
-                                                       const double* __restrict__ part_in,
-                                                       int nchunks, double* __restrict__ part_out,
-                                                       LzState* st, int last) {
+__device__ __forceinline__ void lz_apply_body(const double* __restrict__ V, double* __restrict__ w,
+                                              int64_t n, int j, const double* __restrict__ coef_in,
+                                              const double* __restrict__ part_in, int nchunks,
+                                              double* __restrict__ part_out, LzState* st, int last) {
   constexpr int kBuf = 64 * kLzCoef;
   __shared__ double red[(kLzChunk / kWave) * kLzCoef];
   __shared__ double coef[kLzCoef];
@@ -407,6 +410,15 @@ __global__ __launch_bounds__(kLzChunk) void k_lz_apply(const double* __restrict_
     const double s = block_sum1<kLzChunk>(wr * wr, red);
     if (threadIdx.x == 0) part_out[blockIdx.x] = s;
   }
+}
+
+__global__ __launch_bounds__(kLzChunk) void k_lz_apply(const double* __restrict__ V,
+                                                       double* __restrict__ w, int64_t n, int j,
+                                                       const double* __restrict__ coef_in,
+                                                       const double* __restrict__ part_in,
+                                                       int nchunks, double* __restrict__ part_out,
+                                                       LzState* st, int last) {
+  lz_apply_body(V, w, n, j, coef_in, part_in, nchunks, part_out, st, last);
 }
 
 // Eigenvalues of the symmetric tridiagonal T (diagonal a, off-diagonal b)
@@ -584,8 +596,8 @@ __global__ __launch_bounds__(2 * kWave) void k_lz_bounds(LzState* st, Ctrl* ctrl
 // the zero eigenvalue of the complement on the inner side.  The two sides
 // run together.  Each step: y = (H - shift) v_j (k_hl_matvec2, mode 0),
 // w = Q y with the first Gram-Schmidt dot partials (mode 1 or 2), the two
-// Gram-Schmidt passes of the bound refinement (k_lz_coef, k_lz_apply), then
-// v_{j+1} = w / |w| (k_hl_next).
+// Gram-Schmidt passes of the bound refinement (k_hl_coef2, k_hl_apply2: the
+// bodies of k_lz_coef and k_lz_apply), then v_{j+1} = w / |w| (k_hl_next2).
 // ---------------------------------------------------------------------------
 
 // The two sides of the estimator at once: out_s = M x_s (mode 0: minus
@@ -664,9 +676,8 @@ __global__ __launch_bounds__(kLzMvThreads) void k_hl_matvec2(const float* __rest
 }
 
 // Squared-norm partials of w per chunk of 256 rows.
-__global__ __launch_bounds__(kLzChunk) void k_hl_norm_parts(const double* __restrict__ w, int64_t n,
-                                                          double* __restrict__ part,
-                                                          const LzState* st) {
+__device__ __forceinline__ void hl_norm_parts_body(const double* __restrict__ w, int64_t n,
+                                                   double* __restrict__ part, const LzState* st) {
   __shared__ double red[kLzChunk / kWave];
   if (st->broke) return;
   const int64_t row = int64_t(blockIdx.x) * kLzChunk + threadIdx.x;
@@ -679,9 +690,9 @@ __global__ __launch_bounds__(kLzChunk) void k_hl_norm_parts(const double* __rest
 // beta[row - 1] for row >= 1.  A vanishing norm ends the recurrence (broke;
 // with row 0, no step is recorded).  Every work-group sums the partials
 // identically.
-__global__ __launch_bounds__(kLzChunk) void k_hl_next(double* __restrict__ V, const double* __restrict__ w,
-                                                    int64_t n, int row, const double* __restrict__ part,
-                                                    int nchunks, LzState* st) {
+__device__ __forceinline__ void hl_next_body(double* __restrict__ V, const double* __restrict__ w,
+                                             int64_t n, int row, const double* __restrict__ part,
+                                             int nchunks, LzState* st) {
   __shared__ double sbuf[256];
   __shared__ double snorm;
   if (st->broke) return;
@@ -697,6 +708,46 @@ __global__ __launch_bounds__(kLzChunk) void k_hl_next(double* __restrict__ V, co
   if (blockIdx.x == 0 && threadIdx.x == 0 && row > 0) st->beta[row - 1] = nrm;
   const int64_t i = int64_t(blockIdx.x) * kLzChunk + threadIdx.x;
   if (i < n) V[int64_t(row) * n + i] = w[i] * (1.0 / nrm);
+}
+
+// The estimator's two recurrences (side 0: occupied, side 1: virtual) share
+// every launch of their vector steps: side = blockIdx.y, each with its own
+// basis, residual, partials and state, the same arithmetic as one side alone.
+struct HlVecs {
+  double* V[2];       // basis, (steps + 1) x n
+  double* w[2];       // residual
+  double* p1[2];      // first Gram-Schmidt pass: partials per matrix-vector work-group
+  double* p2[2];      // second pass: partials per chunk
+  double* pn[2];      // |w|^2 partials per chunk
+  double* pc[2];      // first-pass coefficients
+  LzState* st[2];
+};
+
+__global__ __launch_bounds__(kLzChunk) void k_hl_norm_parts2(HlVecs a, int64_t n) {
+  const int sd = blockIdx.y;
+  hl_norm_parts_body(a.w[sd], n, a.pn[sd], a.st[sd]);
+}
+
+__global__ __launch_bounds__(kLzChunk) void k_hl_next2(HlVecs a, int64_t n, int row, int nchunks) {
+  const int sd = blockIdx.y;
+  hl_next_body(a.V[sd], a.w[sd], n, row, a.pn[sd], nchunks, a.st[sd]);
+}
+
+__global__ __launch_bounds__(kLzChunk) void k_hl_coef2(HlVecs a, int nparts) {
+  const int sd = blockIdx.y;
+  lz_coef_body(a.p1[sd], nparts, a.pc[sd], a.st[sd]);
+}
+
+// Both Gram-Schmidt passes of step j: pass 0 takes the first-pass
+// coefficients and leaves the second pass's partials, pass 1 sums those and
+// leaves the |w|^2 partials.
+__global__ __launch_bounds__(kLzChunk) void k_hl_apply2(HlVecs a, int64_t n, int j, int nchunks,
+                                                      int pass) {
+  const int sd = blockIdx.y;
+  if (pass == 0)
+    lz_apply_body(a.V[sd], a.w[sd], n, j, a.pc[sd], nullptr, 0, a.p2[sd], a.st[sd], 0);
+  else
+    lz_apply_body(a.V[sd], a.w[sd], n, j, nullptr, a.p2[sd], nchunks, a.pn[sd], a.st[sd], 1);
 }
 
 // Extreme Ritz value of the recorded tridiagonal matrix and its residual

@@ -21,7 +21,7 @@ def pk():
     return pk
 
 
-@pytest.mark.parametrize("n,ld", [(256, 256), (300, 307), (1000, 1000)])
+@pytest.mark.parametrize("n,ld", [(256, 256), (300, 307), (302, 308), (1000, 1000), (1100, 1100)])
 def test_bounds_match_oracle(pk, n, ld):
     banner(f"bounds n={n} ld={ld}")
     h32 = random_orthogonal_hamiltonian(n, n // 2, seed=n).astype(np.float32)
@@ -32,13 +32,22 @@ def test_bounds_match_oracle(pk, n, ld):
     assert abs(lo - rlo) <= 1e-13 * scale and abs(hi - rhi) <= 1e-13 * scale
 
 
-def test_bounds_reject_nonfinite(pk):
-    banner("bounds NaN")
-    h = random_orthogonal_hamiltonian(64, 32, seed=1).astype(np.float32)
-    h[3, 5] = h[5, 3] = np.nan
-    ws = pk.allocate_workspace(64)
+@pytest.mark.parametrize("n,ld,i,j,val", [
+    (64, 64, 3, 5, np.nan),        # off the diagonal, inside the 16-byte loop
+    (64, 64, 7, 7, np.nan),        # on the diagonal
+    (64, 64, 10, 40, np.inf),
+    (64, 64, 12, 12, -np.inf),     # the diagonal term taken off the row sum: inf - inf
+    (1100, 1100, 600, 1031, np.nan),   # a later batch of four loads per lane
+    (67, 72, 66, 65, np.inf),      # ragged: the scalar tail of the row
+    (67, 72, 66, 66, np.nan),      # ragged: the diagonal in the scalar tail
+])
+def test_bounds_reject_nonfinite(pk, n, ld, i, j, val):
+    banner(f"bounds non-finite n={n} ld={ld} H[{i},{j}]={val}")
+    h = random_orthogonal_hamiltonian(n, n // 2, seed=1).astype(np.float32)
+    h[i, j] = h[j, i] = val
+    ws = pk.allocate_workspace(n)
     with pytest.raises(pk.SP2Error) as ei:
-        pk.sp2_bounds(to_dev(h), ws)
+        pk.sp2_bounds(to_dev(h, ld), ws)
     assert ei.value.status == 2
 
 
