@@ -102,6 +102,8 @@ def parse():
     ap.add_argument("--nvt-coords", type=int, default=3 * 2 ** 24,
                     help="also time the canonical integration step on this many FP64 "
                          "coordinates (0: skip)")
+    ap.add_argument("--no-mfma-probe", action="store_true",
+                    help="skip the matrix-core rate probe (no memory traffic) beside the roofline")
     ap.add_argument("--no-diag", action="store_true",
                     help="skip the GPU diagonalisation context (library eigh + outer product)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -438,6 +440,89 @@ def cpu_baseline(h32, n_occ, layers, n_iter_ref):
     }
 
 
+def mfma_probe(pk, H, n_occ, precision, iters=2500, warm=20, reps=10):
+    """What the matrix cores reach on this GPU under its power limit with no
+    memory traffic: the layer kernel's 96-instruction K-step pair on
+    register-resident fragments (libsp2_probe.so, one work-group per CU),
+    for operand planes of the same water box at several points of a solve:
+    the centred input layer S_0 - I/2 (sparse), the iterates after 4 and 8
+    layers, the converged P - I/2, and all-zero planes.  Rate from HIP
+    events on the launch stream; shader clock from the kernel's own clock
+    and wall-clock counters."""
+    import ctypes
+
+    import torch
+    from paper_2107_02737_amd.build import PROBE_PATH
+    lib = ctypes.CDLL(PROBE_PATH)
+    lib.sp2_probe_mfma.restype = ctypes.c_int32
+    lib.sp2_probe_mfma.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                   ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]
+    n = H.shape[0]
+    dev = H.device
+    nblocks = torch.cuda.get_device_properties(dev).multi_processor_count
+    code = {"bf16x3": 2, "fp16x3": 3}[precision]
+    eye = torch.eye(n, device=dev)
+    ws = pk.allocate_workspace(n, None, dev)
+    P = torch.empty_like(H)
+    iterates = {}
+    for k in (0, 4, 8):
+        # the iterate after k layers (max_iter = k stops there; k = 0: the input layer)
+        opt = pk.make_options(precision, "none", max_iter=max(k, 1), tol=0.0)
+        if k == 0:
+            lo_hi = pk.sp2_bounds(H, ws)
+            iterates["input layer"] = (lo_hi[1] * eye - H) / (lo_hi[1] - lo_hi[0])
+            continue
+        st, info, _ = pk.sp2_density_ex(H, n_occ, opt, P, ws, check=False)
+        if st not in (0, 3):
+            raise RuntimeError(f"probe input solve failed with status {st}")
+        iterates[f"after {k} layers"] = P.clone()
+    st, info, _ = pk.sp2_density_ex(H, n_occ, pk.make_options(precision, "none", tol=2e-3), P, ws,
+                                    check=False)
+    iterates["converged"] = P.clone()
+    hi = torch.empty((n, n), dtype=torch.int16, device=dev)
+    lo = torch.empty_like(hi)
+    sink = torch.empty(nblocks * 256, dtype=torch.float32, device=dev)
+    clocks = torch.zeros(4 * nblocks, dtype=torch.int64, device=dev)
+    wall_hz = ctypes.c_double()
+    stream = torch.cuda.current_stream(dev)
+    flop = nblocks * 4 * iters * 96 * 32768.0
+    out = {"precision": precision, "work_groups": nblocks, "iters": iters,
+           "flop_per_launch": flop, "peak_tflops": PEAK_TFLOPS[precision], "operands": {}}
+    kinds = list(iterates.items()) + [("zeros", None)]
+    for name, S in kinds:
+        if S is None:
+            hi.zero_()
+            lo.zero_()
+        else:
+            pk.sp2_split((S - 0.5 * eye).contiguous(), precision, hi, lo)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+        def launch():
+            r = lib.sp2_probe_mfma(ctypes.c_void_p(hi.data_ptr()), ctypes.c_void_p(lo.data_ptr()), n,
+                                   code, iters, nblocks, ctypes.c_void_p(sink.data_ptr()),
+                                   ctypes.c_void_p(clocks.data_ptr()), ctypes.byref(wall_hz),
+                                   ctypes.c_void_p(stream.cuda_stream))
+            if r != 0:
+                raise RuntimeError(f"sp2_probe_mfma returned {r}")
+
+        for _ in range(warm):
+            launch()
+        ev[0].record(stream)
+        for _ in range(reps):
+            launch()
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / reps
+        c = clocks.view(nblocks, 4).cpu().numpy().astype(np.float64)
+        ghz = float(np.mean((c[:, 2] - c[:, 0]) / (c[:, 3] - c[:, 1]))) * wall_hz.value / 1e9
+        tf = flop / (ms * 1e-3) / 1e12
+        out["operands"][name] = {"ms_per_launch": ms, "tflops": tf,
+                                 "frac_of_peak": tf / PEAK_TFLOPS[precision], "shader_ghz": ghz}
+    del hi, lo, ws, P
+    return out
+
+
 def canonical_step(pk, n, reps=20):
     """Both halves of the canonical integration step (Section IV, Eq. 31) on
     ``n`` FP64 coordinates (seeded, device-resident), timed with HIP events
@@ -576,6 +661,17 @@ def main():
     print(f"# headline {1.0 / sec:.2f} solves/s, layer {layer_ms:.3f} ms", file=sys.stderr,
           flush=True)
 
+    if not args.no_mfma_probe and args.precision in ("bf16x3", "fp16x3"):
+        print("# matrix-core rate probe", file=sys.stderr, flush=True)
+        probe = mfma_probe(pk, H, n_occ, args.precision)
+        mid = probe["operands"]["after 8 layers"]["tflops"]
+        probe["layer_vs_probe_mid_solve"] = achieved / mid
+        print(f"# probe: " + ", ".join(f"{k} {v['tflops']:.0f} TFLOP/s @ {v['shader_ghz']:.2f} GHz"
+                                        for k, v in probe["operands"].items()),
+              file=sys.stderr, flush=True)
+    else:
+        probe = None
+
     p_ref, cb = None, None
     if not args.no_cpu_baseline:
         print("# cpu baseline (FP64 oracle on the host cores)", file=sys.stderr, flush=True)
@@ -620,7 +716,8 @@ def main():
                      "refine_ms": float(np.mean([d["refine_ms"] for d in tinfos])),
                      "timing": f"HIP events around every layer launch, {args.steps} solves "
                                "after the timed ones",
-                     "solves_per_s_with_layer_events": 1.0 / tsec},
+                     "solves_per_s_with_layer_events": 1.0 / tsec,
+                     "mfma_only_probe": probe},
     }
 
     def leg(precision, refine, bound_steps, label):

@@ -14,6 +14,9 @@ CSRC = os.path.join(PKG, "csrc")
 LIB_DIR = os.path.join(PKG, "lib")
 LIB_PATH = os.path.join(LIB_DIR, "libsp2.so")
 SOURCES = ["sp2_capi.hip"]   # includes every csrc/*.hpp
+# measurement helper beside the solver (include/sp2_probe.h), its own library
+PROBE_PATH = os.path.join(LIB_DIR, "libsp2_probe.so")
+PROBE_SOURCES = ["sp2_probe.hip"]
 
 
 def hipcc():
@@ -23,7 +26,7 @@ def hipcc():
     return path
 
 
-def compile_command(out=LIB_PATH):
+def compile_command(out=LIB_PATH, sources=SOURCES):
     return [
         hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
         "-mcode-object-version=5",
@@ -31,7 +34,7 @@ def compile_command(out=LIB_PATH):
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-Wall", "-Wno-unused-function",
         "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-        *[os.path.join(CSRC, s) for s in SOURCES],
+        *[os.path.join(CSRC, s) for s in sources],
         "-o", out,
     ]
 
@@ -79,11 +82,9 @@ def kernel_resources():
     return kernels
 
 
-def build(verbose=False):
-    """Compile the library (always, even when one is present) and return its path."""
-    os.makedirs(LIB_DIR, exist_ok=True)
-    tmp = LIB_PATH + ".tmp"
-    cmd = compile_command(tmp)
+def _compile(path, sources, verbose):
+    tmp = path + ".tmp"
+    cmd = compile_command(tmp, sources)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if verbose or res.returncode != 0:
         msg = "\n".join(line for line in (res.stdout + res.stderr).splitlines()
@@ -91,8 +92,16 @@ def build(verbose=False):
         if msg.strip():
             print(msg)
     if res.returncode != 0:
-        raise RuntimeError("hipcc failed building libsp2.so:\n" + " ".join(cmd))
-    os.replace(tmp, LIB_PATH)
+        raise RuntimeError(f"hipcc failed building {os.path.basename(path)}:\n" + " ".join(cmd))
+    os.replace(tmp, path)
+
+
+def build(verbose=False):
+    """Compile the library and the probe library beside it (always, even when
+    they are present) and return the library's path."""
+    os.makedirs(LIB_DIR, exist_ok=True)
+    _compile(LIB_PATH, SOURCES, verbose)
+    _compile(PROBE_PATH, PROBE_SOURCES, verbose)
     return LIB_PATH
 
 

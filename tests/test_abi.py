@@ -261,3 +261,31 @@ def test_homo_lumo_argument_checks(lib):
     assert lib.sp2_homo_lumo(None, dummy, 64, 64, 16, 0, 0.0, ctypes.byref(a), ctypes.byref(b), ws,
                              1 << 40, None) == _lib.SP2_ERR_INVALID_ARG
 
+
+
+def test_probe_library_exports_and_rejects_bad_arguments():
+    """The matrix-core rate probe beside the library (include/sp2_probe.h):
+    every declared symbol is exported, and invalid arguments return 1 before
+    anything is launched."""
+    from paper_2107_02737_amd.build import PROBE_PATH
+    if not os.path.exists(PROBE_PATH):
+        pytest.fail("libsp2_probe.so is not built; run paper_2107_02737_amd.build.build()")
+    text = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "sp2_probe.h")).read(),
+                  flags=re.S)
+    names = sorted(set(re.findall(r"\b(sp2_[a-z_]+)\s*\(", text)))
+    assert names == ["sp2_probe_mfma"]
+    plib = ctypes.CDLL(PROBE_PATH)
+    f = plib.sp2_probe_mfma
+    f.restype = ctypes.c_int32
+    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                  ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                  ctypes.c_void_p]
+    p = ctypes.c_void_p(256)   # never dereferenced: every call below fails its checks first
+    ok = dict(hi=p, lo=p, np=512, precision=3, iters=10, nblocks=4, sink=p, clocks=p)
+    bad = [dict(hi=None), dict(lo=None), dict(sink=None), dict(clocks=None), dict(np=300),
+           dict(np=0), dict(precision=0), dict(precision=1), dict(iters=0), dict(nblocks=0),
+           dict(nblocks=70000)]
+    for b in bad:
+        a = {**ok, **b}
+        assert f(a["hi"], a["lo"], a["np"], a["precision"], a["iters"], a["nblocks"], a["sink"],
+                 a["clocks"], None, None) == 1, b
