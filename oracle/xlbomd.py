@@ -1,8 +1,8 @@
 """XL-BOMD kernel building block -- TEST INFRASTRUCTURE ONLY.
 
 Section III propagates net Mulliken charges ``n`` and drives them towards
-the ground-state charges ``q0[n]`` through the kernel ``K``, the inverse of
-the Jacobian of the residual ``f(n) = q0[n] - n`` (Eq. 27-28); the action
+the ground-state charges ``q0[n]`` through the kernel ``K = J^-1``, with
+``J`` the Jacobian of ``f(n) = q0[n] - n`` (Eq. 27-28); the action
 ``K f`` is to be approximated in a preconditioned Krylov subspace.  This
 module is the plain FP64 reference of that building block on the synthetic
 charge model of ``workloads.charges``:
