@@ -900,6 +900,7 @@ sp2_status density_impl(const float* H, int64_t n, int64_t ld, int64_t n_occ, co
   }
   int launched = 0, chunk = 0;
   bool stopped = false;
+  int stop_slot = -1;   // host copy of the control block that showed the stop
   sp2_status err = SP2_OK;
   while (!stopped && launched < o.max_iter && err == SP2_OK) {
     const int end = std::min(o.max_iter, launched + (L.np >= kChunkLargeNp ? kChunkLarge : kChunk));
@@ -929,7 +930,10 @@ sp2_status density_impl(const float* H, int64_t n, int64_t ld, int64_t n_occ, co
     if (!pinned) {
       if (e == hipSuccess) e = hipStreamSynchronize(st);
       if (e != hipSuccess) { err = fail(SP2_ERR_DEVICE, "poll: %s", hipGetErrorString(e)); break; }
-      if (hm->ctrl[slot].stopped) stopped = true;
+      if (hm->ctrl[slot].stopped) {
+        stopped = true;
+        stop_slot = slot;
+      }
       ++chunk;
       continue;
     }
@@ -938,20 +942,29 @@ sp2_status density_impl(const float* H, int64_t n, int64_t ld, int64_t n_occ, co
     if (chunk > 0) {
       e = hipEventSynchronize(ev[slot ^ 1]);
       if (e != hipSuccess) { err = fail(SP2_ERR_DEVICE, "poll sync: %s", hipGetErrorString(e)); break; }
-      if (hm->ctrl[slot ^ 1].stopped) stopped = true;
+      if (hm->ctrl[slot ^ 1].stopped) {
+        stopped = true;
+        stop_slot = slot ^ 1;
+      }
     }
     ++chunk;
   }
-  if (err == SP2_OK) {
-    hipError_t e = hipStreamSynchronize(st);
-    if (e != hipSuccess) err = fail(SP2_ERR_DEVICE, "sync: %s", hipGetErrorString(e));
-  }
   if (err != SP2_OK) return err;
-
-  // The freshest control block: the loop has drained, read it again.
-  if ((s = read_back(w, hm, false, st))) return s;
-  if (hm->ctrl[0].nonfinite) return fail(SP2_ERR_NONFINITE, "H holds NaN or Inf");
-  if (hm->ctrl[0].acc_failed) {
+  // Once the stop flag is set the control block no longer changes (later
+  // layer launches exit at entry), so the host copy that showed it is final
+  // and the rest of the solve is queued behind those launches without
+  // waiting.  (A copy of the last chunk may still be landing in the other
+  // host slot.)  At the layer cap: the freshest copy after the queue drains.
+  if (!stopped) {
+    if ((s = read_back(w, hm, false, st))) return s;
+    stop_slot = 0;
+  }
+  const Ctrl cl = hm->ctrl[stop_slot];
+  if (cl.nonfinite) {
+    HIP_TRY(hipStreamSynchronize(st));   // nothing of this call lands after it returns
+    return fail(SP2_ERR_NONFINITE, "H holds NaN or Inf");
+  }
+  if (cl.acc_failed) {
     // The estimates did not bracket the gap (trace check at the end of the
     // schedule): run the plain network from the start.
     sp2_options plain = o;
@@ -961,7 +974,7 @@ sp2_status density_impl(const float* H, int64_t n, int64_t ld, int64_t n_occ, co
     if (info) info->fallback = 1;
     return r;
   }
-  if (!hm->ctrl[0].stopped) {
+  if (!cl.stopped) {
     k_finish_loop<<<1, 256, 0, st>>>(w.ctrl, w.hist, w.parts[o.max_iter & 1],
                                      nparts_of_layer(w, prec, o.max_iter), o.max_iter,
                                      static_cast<double>(n_occ), o.tol, o.stop_rule,
@@ -969,7 +982,7 @@ sp2_status density_impl(const float* H, int64_t n, int64_t ld, int64_t n_occ, co
     LAUNCH_TRY();
     n_iter = o.max_iter;
   } else {
-    n_iter = hm->ctrl[0].n_iter;
+    n_iter = cl.n_iter;
   }
   const float* S = s_f32(w, prec, n_iter);
   // split layers wrote the FP32 iterate's upper triangle only
@@ -982,7 +995,7 @@ sp2_status density_impl(const float* H, int64_t n, int64_t ld, int64_t n_occ, co
     n_iter_even_for_refine = true;
   }
 
-  if (o.refine != SP2_REFINE_NONE && !hm->ctrl[0].degenerate) {
+  if (o.refine != SP2_REFINE_NONE && !cl.degenerate) {
     HIP_TRY(timer.mark(2 * refine_ev, st));
     if ((s = refine(w, prec, o.refine, n_iter_even_for_refine ? 0 : n_iter, S, P, ld, n, vec_ok, st)))
       return s;
