@@ -1,7 +1,7 @@
 """Benchmark: DNN-SP2 density-matrix solves/s at N = 6144 on one MI355X.
 
 One step = one full ``sp2_density_ex`` call on a device-resident FP32
-Hamiltonian in the FP32-equivalent mode: Gershgorin discs tightened by 16
+Hamiltonian in the FP32-equivalent mode: Gershgorin discs tightened by 8
 Lanczos steps, the input layer, every SP2 layer as an FP16 hi/lo split
 product of the centred iterate S - I/2 on MFMA (Eq. 20-22; FP64
 trace-driven branch and stop decided on the device) and the McWeeny
@@ -72,7 +72,7 @@ def parse():
                          "refines: one McWeeny step maps an eigenvalue's deviation d to "
                          "3d^2 - 2d^3, which leaves at most 3 tol^2 / sqrt(N) = 1.5e-7 in "
                          "||P - P_ref||_F / sqrt(N) at N = 6144, 15%% of the 1e-6 budget)")
-    ap.add_argument("--bound-steps", type=int, default=16,
+    ap.add_argument("--bound-steps", type=int, default=8,
                     help="Lanczos steps tightening the Gershgorin bounds (0: Gershgorin only)")
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the side legs in other arithmetics")
